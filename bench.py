@@ -1,0 +1,246 @@
+"""ARG-CSR SpMV benchmark on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload powerlaw|stencil27|laplace64]
+                    [--dtype f64|f32|bf16|f16] [--block-dim T] [--desired-chunk-size D]
+                    [--warm] [--no-cpu-baseline] [--no-extras]
+
+A step is one y = A x in ARG-CSR (argcsr_spmv) on a matrix converted once
+beforehand (conversion time is reported separately).  Inputs are resident in
+HBM when timing starts.  By default every step is preceded by a 1 GiB
+read-modify-write "flush" (not timed) so that neither the L2s nor the 256 MB
+Infinity Cache hold the matrix: the figure is HBM bandwidth, not cache
+bandwidth.  Each SpMV launch is bracketed by HIP events on the stream it is
+launched on; `value` is algorithmic bytes / mean launch time.
+
+Algorithmic bytes per SpMV (the same for every format, so a GB/s ratio is a
+speed-up):  nnz*(s_v + 4) + n_rows*(4 + s_y) + n_cols*s_x.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ARG-CSR SpMV GB/s (% HBM peak) vs plain CSR; served p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
+KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_amd/csrc/spmv.hip",
+                  "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_workload(name: str):
+    import synth
+    if name == "powerlaw":
+        A, x = synth.workload_powerlaw()
+        desc = "power-law rows: n=1e6, L=clip(Zipf(2.0),1,1e4), distinct uniform columns, U[-1,1]"
+    elif name == "stencil27":
+        A, x = synth.workload_stencil27(128)
+        desc = "3D 27-point stencil 128^3, symmetric U[0.5,1.5] couplings, diagonally dominant"
+    elif name == "laplace64":
+        A, x = synth.workload_laplace64()
+        desc = "2D 5-point Laplacian 64x64"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return A, x, desc
+
+
+def useful_bytes(A, dtype: int) -> int:
+    sv = VALUE_BYTES[dtype]
+    sx = 8 if dtype == 0 else 4
+    return A.nnz * (sv + 4) + A.n_rows * (4 + sx) + A.n_cols * sx
+
+
+def format_bytes(M, dtype: int) -> int:
+    sv = VALUE_BYTES[dtype]
+    sx = 8 if dtype == 0 else 4
+    return M.n_slots * (sv + 4) + 16 * M.n_groups + 4 * M.n_rows + sx * (M.n_rows + M.n_cols)
+
+
+class Timer:
+    """Times `fn` launches with HIP events on the current stream, optionally
+    evicting the caches (1 GiB read-modify-write) before each launch."""
+
+    def __init__(self, torch, cold: bool):
+        self.torch = torch
+        self.cold = cold
+        self.flush_buf = torch.empty(1 << 28, dtype=torch.float32, device="cuda") if cold else None
+
+    def run(self, fn, steps: int):
+        torch = self.torch
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            if self.cold:
+                self.flush_buf.add_(1.0)
+            starts[i].record()
+            fn()
+            ends[i].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+        return ms, wall
+
+
+def stats(ms):
+    return {"mean_ms": float(ms.mean()), "median_ms": float(np.median(ms)),
+            "p10_ms": float(np.percentile(ms, 10)), "p90_ms": float(np.percentile(ms, 90))}
+
+
+def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
+    """The FP64 CSR oracle on this host's cores (OpenMP row split; identical
+    result to the sequential oracle), on a bounded number of full SpMVs."""
+    import oracle
+    threads = os.cpu_count() or 1
+    y = oracle.csr_spmv(A.rp, A.col, A.val, x, threads)       # warm-up
+    t0 = time.perf_counter()
+    oracle.csr_spmv(A.rp, A.col, A.val, x, threads)
+    one = max(time.perf_counter() - t0, 1e-6)
+    reps = int(max(3, min(2000, (budget_s * 0.6) / one)))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.csr_spmv(A.rp, A.col, A.val, x, threads)
+    mt = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    st_reps = max(1, min(reps, int((budget_s * 0.4) / max(one * threads, 1e-6))))
+    for _ in range(st_reps):
+        oracle.csr_spmv(A.rp, A.col, A.val, x, 1)
+    st = (time.perf_counter() - t0) / st_reps
+    del y
+    return {"value": B_useful / mt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"full matrix, {reps} SpMVs on {threads} threads (OpenMP row split) "
+                      f"+ {st_reps} single-threaded",
+            "ms_per_spmv": mt * 1e3, "single_thread_gbps": B_useful / st / 1e9,
+            "single_thread_ms": st * 1e3}
+
+
+def traffic_for(workload: str, dtype_name: str, T: int, D: int):
+    """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE for
+    the current kernel source (None when absent or the kernel has changed)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(f"{workload}/{dtype_name}/T{T}/D{D}")
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="powerlaw")
+    ap.add_argument("--dtype", default="f64", choices=list(DTYPES))
+    ap.add_argument("--block-dim", type=int, default=64)
+    ap.add_argument("--desired-chunk-size", type=int, default=1)
+    ap.add_argument("--warm", action="store_true", help="no cache flush between steps")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the CSR and warm timings")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1203_5737_amd as ac
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    ac._lib.lib()                                    # fails loudly if not built
+    dtype = DTYPES[args.dtype]
+    T, D = args.block_dim, args.desired_chunk_size
+
+    A, x, desc = load_workload(args.workload)
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")
+    torch.cuda.synchronize()
+
+    # conversion (timed separately, host grouping included)
+    t0 = time.perf_counter()
+    M = ac.convert(dev, T, D, dtype)
+    convert_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    M = ac.convert(dev, T, D, dtype)
+    convert_ms = min(convert_ms, (time.perf_counter() - t0) * 1e3)
+
+    vdt = ac.vector_dtype(dtype)
+    xd = torch.from_numpy(x).to("cuda", vdt)
+    yd = torch.empty(A.n_rows, dtype=vdt, device="cuda")
+    B = useful_bytes(A, dtype)
+    Bf = format_bytes(M, dtype)
+
+    timer = Timer(torch, cold=not args.warm)
+    spmv = lambda: ac.spmv(M, xd, yd)
+    timer.run(spmv, args.warmup)
+    ms, wall = timer.run(spmv, args.steps)
+    mean_s = ms.mean() * 1e-3
+    gbps = B / mean_s / 1e9
+
+    out = {
+        "metric": METRIC, "value": round(gbps, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": float(ms.mean()),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": desc, "n_rows": A.n_rows, "nnz": A.nnz, "block_dim": T,
+                   "desired_chunk_size": D, "value_dtype": args.dtype,
+                   "timing": "warm" if args.warm else "cold (1 GiB flush before each step, untimed)"},
+        "roofline": {"bound": "hbm", "achieved": round(gbps, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic_for(args.workload, args.dtype, T, D)},
+        "spmv": stats(ms) | {"gflops": 2 * A.nnz / mean_s / 1e9, "useful_bytes": B,
+                             "format_bytes": Bf, "padding_ratio": M.n_slots / max(A.nnz, 1),
+                             "n_groups": M.n_groups, "wall_ms_per_step": wall * 1e3 / args.steps},
+        "convert_ms": convert_ms,
+        "kernel_hash": kernel_source_hash(),
+    }
+
+    if not args.no_extras:
+        # the same SpMV without flushes (matrix may stay in the Infinity Cache)
+        warm_ms, _ = Timer(torch, cold=False).run(spmv, args.steps)
+        out["spmv_warm"] = stats(warm_ms) | {"gbps": B / (warm_ms.mean() * 1e-3) / 1e9}
+        # plain CSR on the same GPU, same timing; best lanes-per-row of a sweep
+        vals = dev.val if dtype == 0 else dev.val.to(ac.storage_dtype(dtype))
+        best = None
+        for V in (0, 1, 2, 4, 8, 16, 32, 64):
+            f = lambda V=V: ac.csr_spmv(dev, xd, yd, values=vals, dtype=dtype, lanes_per_row=V)
+            timer.run(f, 3)
+            t, _ = timer.run(f, max(10, args.steps // 5))
+            if best is None or t.mean() < best[1].mean():
+                best = (V, t)
+        V, t = best
+        f = lambda: ac.csr_spmv(dev, xd, yd, values=vals, dtype=dtype, lanes_per_row=V)
+        t, _ = timer.run(f, args.steps)
+        csr_gbps = B / (t.mean() * 1e-3) / 1e9
+        out["csr"] = stats(t) | {"gbps": csr_gbps, "lanes_per_row": V}
+        out["speedup_vs_csr"] = gbps / csr_gbps
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, x, useful_bytes(A, 0))   # the oracle is FP64
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

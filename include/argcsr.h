@@ -1,0 +1,163 @@
+/*
+ * argcsr.h -- C ABI of libargcsr, Adaptive Row-grouped CSR (ARG-CSR) sparse
+ * matrix-vector multiplication for AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Heller, T. Oberhuber, "Adaptive Row-grouped CSR format for
+ * storing of sparse matrices on GPU" (arXiv:1203.5737).
+ *
+ * Conventions (all entry points):
+ *   - Every function returns int status: ARGCSR_OK (0) or a negative code.
+ *     argcsr_last_error() returns a message for the calling thread's last
+ *     failure.  No C++ exception crosses this interface.
+ *   - "device" pointers are HIP device memory owned by the caller; the
+ *     library never frees them.  "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Kernels are enqueued on it; calls documented as synchronous wait for
+ *     their own work before returning.  A kernel fault surfaces as
+ *     ARGCSR_EHIP at the next call that synchronises.
+ *   - Indices are int32 (the group structure of Listing 1 uses int); a slot
+ *     count above INT32_MAX is ARGCSR_EOVERFLOW.
+ */
+#ifndef ARGCSR_H
+#define ARGCSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ARGCSR_OK          0
+#define ARGCSR_EINVAL     (-1)  /* malformed argument or matrix            */
+#define ARGCSR_EOVERFLOW  (-2)  /* slot count or offset exceeds int32      */
+#define ARGCSR_ENOMEM     (-3)  /* device or host allocation failed        */
+#define ARGCSR_EHIP       (-4)  /* a HIP runtime call failed               */
+#define ARGCSR_EBUDGET    (-5)  /* request exceeds the device memory budget */
+#define ARGCSR_EBUSY      (-6)  /* no free slot; retry later               */
+#define ARGCSR_ENOTFOUND  (-7)  /* unknown handle, id or ticket            */
+#define ARGCSR_EUNSUPPORTED (-8) /* valid, but not supported on the GPU    */
+
+/* ---- value storage types ------------------------------------------------ */
+/* FP64 stores FP64 values and takes FP64 x, y.  The reduced types store
+ * values rounded to nearest-even from FP64 and take FP32 x, y with FP32
+ * accumulation. */
+typedef enum {
+  ARGCSR_F64 = 0,
+  ARGCSR_F32 = 1,
+  ARGCSR_BF16 = 2,
+  ARGCSR_F16 = 3
+} argcsr_dtype;
+
+/* One group of consecutive rows (Sec. 3, Listing 1): rows
+ * first_row .. first_row+size-1; its chunk_size*block_dim slots start at
+ * `offset` in values/columns, element j of chunk k at offset + j*block_dim + k. */
+typedef struct {
+  int32_t first_row;
+  int32_t size;
+  int32_t offset;
+  int32_t chunk_size;
+} argcsr_group_info;
+
+/* A converted matrix.  All four arrays are caller-owned device memory:
+ *   groups[n_groups]            group table (Listing 1)
+ *   threads_mapping[n_rows]     per group, inclusive prefix sum of the number
+ *                               of chunks of each row (Sec. 3, Listing 2)
+ *   columns[n_slots]            column index, -1 marks an artificial zero
+ *   values[n_slots]             value, element type given by dtype
+ * block_dim (chunks per group, the paper's blockDim.x) must be 64, 128 or
+ * 256 on the GPU; desired_chunk_size (the paper's desiredChunkSize) >= 1. */
+typedef struct {
+  int32_t n_rows;
+  int32_t n_cols;
+  int32_t block_dim;
+  int32_t desired_chunk_size;
+  int32_t dtype;               /* argcsr_dtype */
+  int32_t n_groups;
+  int64_t nnz;
+  int64_t n_slots;
+  argcsr_group_info* groups;
+  int32_t* threads_mapping;
+  int32_t* columns;
+  void* values;
+} argcsr_matrix;
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* argcsr_last_error(void);
+
+/* Library version, e.g. 100 for 0.1.0. */
+int argcsr_version(void);
+
+/*
+ * argcsr_plan -- sizes of the ARG-CSR form of a CSR matrix (host only).
+ * Conversion steps 1 and 2 of Sec. 3: rows are grouped in order, a row
+ * joining the open group only while the group keeps at most
+ * desired_chunk_size*block_dim nonzeros and at most block_dim rows (a longer
+ * single row forms its own group); each group's chunk size is the smallest
+ * c >= 1 with sum over its rows of max(1, ceil(L_r / c)) <= block_dim.
+ *   n_rows            >= 0
+ *   row_ptr_host      host int32[n_rows+1], CSR row offsets (Sec. 2)
+ *   block_dim         >= 1 (the GPU entry points accept 64, 128, 256)
+ *   desired_chunk_size >= 1
+ *   n_groups, n_slots out: group count and slot count (sum c_g*block_dim)
+ * Errors: EINVAL (bad sizes, row_ptr not starting at 0 or decreasing),
+ * EOVERFLOW (slot count > INT32_MAX).  Allocates only host memory.
+ */
+int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
+                int32_t desired_chunk_size, int32_t* n_groups, int64_t* n_slots);
+
+/*
+ * argcsr_convert -- CSR -> ARG-CSR on the GPU (Sec. 3, all four steps).
+ * Step 1 (grouping, inherently sequential) runs on the host from
+ * row_ptr_host; steps 2-4 (chunk size, threads mapping, offsets, fill) run
+ * as HIP kernels on `stream`.  The result equals, byte for byte, the
+ * sequential conversion the paper describes.
+ *   row_ptr_host  host int32[n_rows+1]  (same content as row_ptr)
+ *   row_ptr       device int32[n_rows+1]
+ *   col           device int32[nnz], 0 <= col < n_cols
+ *   val           device double[nnz]
+ *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, dtype,
+ *                     n_groups and n_slots as returned by argcsr_plan, and
+ *                     the four device buffers of those sizes;
+ *                 out: nnz, and the four buffers filled.
+ * Reduced dtypes round each value to nearest-even directly from FP64.
+ * Synchronous: waits for its kernels (it reads back a validation flag).
+ * Errors: EINVAL (malformed CSR incl. a column outside [0, n_cols), sizes
+ * not matching argcsr_plan), EUNSUPPORTED (block_dim), EOVERFLOW, EHIP.
+ */
+int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                   const int32_t* row_ptr, const int32_t* col, const double* val,
+                   argcsr_matrix* out, void* stream);
+
+/*
+ * argcsr_spmv -- y = A x for a converted matrix (Sec. 4, Listing 2
+ * semantics: each chunk sums value*x[column] up to its first -1, each row
+ * sums its chunks; y is overwritten, empty rows give 0).
+ *   A   converted matrix (device buffers as filled by argcsr_convert)
+ *   x   device FP64[n_cols] for ARGCSR_F64, FP32[n_cols] otherwise
+ *   y   device FP64[n_rows] / FP32[n_rows]; must not alias x
+ * Asynchronous on `stream`.  Errors: EINVAL, EUNSUPPORTED, EHIP (launch).
+ */
+int argcsr_spmv(const argcsr_matrix* A, const void* x, void* y, void* stream);
+
+/*
+ * argcsr_csr_spmv -- plain CSR y = A x baseline on the same GPU (Sec. 2
+ * definition): lanes_per_row consecutive lanes share a row and stride through
+ * it, then combine their partial sums.
+ *   row_ptr        device int32[n_rows+1]; col device int32[nnz] (valid
+ *                  indices in [0, n_cols) are the caller's responsibility)
+ *   val            device values of `dtype` (FP64, FP32, BF16 or FP16 bits)
+ *   lanes_per_row  power of two in [1, 64], or 0: the power of two at or
+ *                  above the mean row length (capped at 64)
+ *   x, y           as for argcsr_spmv
+ * Asynchronous on `stream`.  Errors: EINVAL, EHIP.
+ */
+int argcsr_csr_spmv(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                    const int32_t* row_ptr, const int32_t* col, const void* val,
+                    int32_t dtype, int32_t lanes_per_row, const void* x, void* y,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARGCSR_H */

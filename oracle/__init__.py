@@ -64,6 +64,8 @@ def _bind(L):
         "ora_bf16_value": (f64, [u16]),
         "ora_f16_value": (f64, [u16]),
         "ora_cg": (i32, [i32, vp, vp, vp, vp, vp, f64, i32, vp]),
+        "ora_round_array": (None, [i64, vp, i32, vp]),
+        "ora_decode_array": (None, [i64, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -196,24 +198,17 @@ def round_f16(v: float) -> int:
 def round_array(v, dtype: int) -> np.ndarray:
     """Stored representation of FP64 values (float32 / uint16 bits)."""
     v = _c(v, np.float64)
-    if dtype == F64:
-        return v.copy()
-    if dtype == F32:
-        return v.astype(np.float32)
-    fn = lib().ora_round_bf16 if dtype == BF16 else lib().ora_round_f16
-    # deduplicate on the bit pattern (0.0 and -0.0 compare equal as floats)
-    uniq, inv = np.unique(v.view(np.uint64), return_inverse=True)
-    table = np.array([fn(float(u)) for u in uniq.view(np.float64)], dtype=np.uint16)
-    return table[inv].reshape(v.shape)
+    out = np.empty(v.shape, dtype=_NP_STORAGE[dtype])
+    lib().ora_round_array(v.size, _p(v), dtype, _p(out))
+    return out
 
 
-def stored_as_f64(bits_or_vals: np.ndarray, dtype: int) -> np.ndarray:
-    if dtype in (F64, F32):
-        return np.asarray(bits_or_vals, dtype=np.float64)
-    fn = lib().ora_bf16_value if dtype == BF16 else lib().ora_f16_value
-    uniq, inv = np.unique(bits_or_vals, return_inverse=True)
-    table = np.array([fn(int(u)) for u in uniq], dtype=np.float64)
-    return table[inv].reshape(np.shape(bits_or_vals))
+def stored_as_f64(stored: np.ndarray, dtype: int) -> np.ndarray:
+    """Exact FP64 value of stored values (float32 / uint16 bits)."""
+    st = _c(stored, _NP_STORAGE[dtype])
+    out = np.empty(st.shape, dtype=np.float64)
+    lib().ora_decode_array(st.size, _p(st), dtype, _p(out))
+    return out
 
 
 def cg(rp, col, val, b, tol: float = 1e-10, max_iter: int = 10000):

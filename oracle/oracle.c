@@ -215,6 +215,30 @@ static double small_float_value(uint16_t b, int exp_bits, int man_bits)
 double ora_bf16_value(uint16_t b) { return small_float_value(b, 8, 7); }
 double ora_f16_value(uint16_t h) { return small_float_value(h, 5, 10); }
 
+void ora_round_array(int64_t n, const double* v, int32_t dtype, void* out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        switch (dtype) {
+        case ORA_F64: ((double*)out)[i] = v[i]; break;
+        case ORA_F32: ((float*)out)[i] = (float)v[i]; break;
+        case ORA_BF16: ((uint16_t*)out)[i] = ora_round_bf16(v[i]); break;
+        default: ((uint16_t*)out)[i] = ora_round_f16(v[i]); break;
+        }
+    }
+}
+
+void ora_decode_array(int64_t n, const void* stored, int32_t dtype, double* out)
+{
+    for (int64_t i = 0; i < n; i++) {
+        switch (dtype) {
+        case ORA_F64: out[i] = ((const double*)stored)[i]; break;
+        case ORA_F32: out[i] = (double)((const float*)stored)[i]; break;
+        case ORA_BF16: out[i] = ora_bf16_value(((const uint16_t*)stored)[i]); break;
+        default: out[i] = ora_f16_value(((const uint16_t*)stored)[i]); break;
+        }
+    }
+}
+
 static void store_value(void* values, int32_t dtype, int64_t slot, double v)
 {
     switch (dtype) {

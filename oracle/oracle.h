@@ -51,9 +51,10 @@ enum { ORA_F64 = 0, ORA_F32 = 1, ORA_BF16 = 2, ORA_F16 = 3 };
 /* Return codes. */
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_EOVERFLOW = -2 };
 
-/* CSR SpMV by definition: y_i = sum_{k=rp[i]}^{rp[i+1]-1} val[k] * x[col[k]], left to right,
- * FP64 (Sec. 2 CSR definition).  n_threads > 1 splits the ROWS over OpenMP
- * threads; each row's sum keeps the same order, so y is identical. */
+/* CSR SpMV by definition (Sec. 2):
+ * y_i = sum_{k=rp[i]}^{rp[i+1]-1} val[k] * x[col[k]], left to right, FP64.
+ * n_threads > 1 splits the ROWS over OpenMP threads; each row's sum keeps
+ * the same order, so y is identical. */
 void ora_csr_spmv(int32_t n_rows, const int32_t* rp, const int32_t* col,
                   const double* val, const double* x, double* y,
                   int32_t n_threads);
@@ -112,6 +113,11 @@ uint16_t ora_round_f16(double v);
 /* Exact value of bfloat16 / binary16 bits as FP64. */
 double ora_bf16_value(uint16_t b);
 double ora_f16_value(uint16_t h);
+
+/* Element-wise: FP64 -> storage representation of `dtype` (as stored by
+ * ora_argcsr_convert), and storage -> exact FP64 value. */
+void ora_round_array(int64_t n, const double* v, int32_t dtype, void* out);
+void ora_decode_array(int64_t n, const void* stored, int32_t dtype, double* out);
 
 /* Textbook conjugate gradients in FP64 from x0 = 0 on a CSR matrix;
  * stops when the TRUE residual ||b - A x||_2 <= tol * ||b||_2 or after

@@ -1,0 +1,163 @@
+"""ARG-CSR sparse matrix-vector multiplication on AMD MI355X (gfx950).
+
+Python binding of libargcsr (include/argcsr.h).  Every step of the path runs
+in the library's HIP kernels; this module only marshals arguments.  PyTorch
+provides device memory and streams.  The library must be built
+(``python -m paper_1203_5737_amd.build``); there is no CPU fallback.
+
+Method: Heller & Oberhuber, "Adaptive Row-grouped CSR format for storing of
+sparse matrices on GPU" (arXiv:1203.5737), Sec. 3 (format and conversion)
+and Sec. 4 (SpMV).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from ._lib import (BF16, F16, F32, F64, ArgCsrError, MatrixDesc, check, lib)
+
+__all__ = ["F64", "F32", "BF16", "F16", "ArgCsrError", "ArgCsrMatrix", "DeviceCsr",
+           "plan", "convert", "spmv", "csr_spmv", "to_device_csr", "storage_dtype",
+           "vector_dtype"]
+
+_STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}
+
+
+def storage_dtype(dtype: int) -> torch.dtype:
+    """torch dtype holding the stored values (bf16/f16 share their bit layout)."""
+    return _STORAGE[dtype]
+
+
+def vector_dtype(dtype: int) -> torch.dtype:
+    """torch dtype of x and y: FP64 for the FP64 path, FP32 otherwise."""
+    return torch.float64 if dtype == F64 else torch.float32
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+@dataclass
+class DeviceCsr:
+    """A CSR matrix (Sec. 2) resident on the device, with a host copy of the
+    row offsets (conversion step 1 runs on the host)."""
+    n_rows: int
+    n_cols: int
+    row_ptr_host: np.ndarray     # int32 [n_rows+1]
+    row_ptr: torch.Tensor        # device int32 [n_rows+1]
+    col: torch.Tensor            # device int32 [nnz]
+    val: torch.Tensor            # device float64 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+
+def to_device_csr(row_ptr, col, val, n_cols: int, device="cuda") -> DeviceCsr:
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+    return DeviceCsr(
+        n_rows=int(rp.shape[0] - 1), n_cols=int(n_cols), row_ptr_host=rp,
+        row_ptr=torch.from_numpy(rp).to(device),
+        col=torch.from_numpy(np.ascontiguousarray(col, dtype=np.int32)).to(device),
+        val=torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).to(device))
+
+
+@dataclass
+class ArgCsrMatrix:
+    """A converted matrix; the four arrays are device tensors it owns."""
+    n_rows: int
+    n_cols: int
+    block_dim: int
+    desired_chunk_size: int
+    dtype: int
+    n_groups: int
+    nnz: int
+    n_slots: int
+    groups: torch.Tensor           # int32 [n_groups, 4]: firstRow, size, offset, chunkSize
+    threads_mapping: torch.Tensor  # int32 [n_rows]
+    columns: torch.Tensor          # int32 [n_slots]
+    values: torch.Tensor           # storage_dtype(dtype) [n_slots]
+
+    def desc(self) -> MatrixDesc:
+        return MatrixDesc(self.n_rows, self.n_cols, self.block_dim, self.desired_chunk_size,
+                          self.dtype, self.n_groups, self.nnz, self.n_slots,
+                          _ptr(self.groups), _ptr(self.threads_mapping), _ptr(self.columns),
+                          _ptr(self.values))
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size()
+                   for t in (self.groups, self.threads_mapping, self.columns, self.values))
+
+
+def plan(row_ptr_host, block_dim: int, desired_chunk_size: int):
+    """(n_groups, n_slots) of the converted matrix (host only)."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr_host, dtype=np.int32))
+    g, s = ctypes.c_int32(0), ctypes.c_int64(0)
+    check(lib().argcsr_plan(int(rp.shape[0] - 1), rp.ctypes.data_as(ctypes.c_void_p),
+                            int(block_dim), int(desired_chunk_size), ctypes.byref(g),
+                            ctypes.byref(s)), "argcsr_plan")
+    return g.value, s.value
+
+
+def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
+            dtype: int = F64, stream=None) -> ArgCsrMatrix:
+    """CSR -> ARG-CSR on the GPU (argcsr_convert); allocates the result."""
+    G, S = plan(A.row_ptr_host, block_dim, desired_chunk_size)
+    dev = A.row_ptr.device
+    out = ArgCsrMatrix(
+        A.n_rows, A.n_cols, int(block_dim), int(desired_chunk_size), int(dtype), G, A.nnz, S,
+        torch.empty((G, 4), dtype=torch.int32, device=dev),
+        torch.empty(A.n_rows, dtype=torch.int32, device=dev),
+        torch.empty(S, dtype=torch.int32, device=dev),
+        torch.empty(S, dtype=_STORAGE[dtype], device=dev))
+    d = out.desc()
+    check(lib().argcsr_convert(A.n_rows, A.n_cols,
+                               A.row_ptr_host.ctypes.data_as(ctypes.c_void_p),
+                               _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), ctypes.byref(d),
+                               _stream(stream)), "argcsr_convert")
+    out.nnz = int(d.nnz)
+    return out
+
+
+def spmv(A: ArgCsrMatrix, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+         stream=None) -> torch.Tensor:
+    """y = A x (argcsr_spmv), enqueued on `stream`."""
+    want = vector_dtype(A.dtype)
+    if x.dtype != want or not x.is_contiguous() or x.numel() != A.n_cols:
+        raise ValueError(f"x must be a contiguous {want} vector of length {A.n_cols}")
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=want, device=x.device)
+    elif y.dtype != want or not y.is_contiguous() or y.numel() != A.n_rows:
+        raise ValueError(f"y must be a contiguous {want} vector of length {A.n_rows}")
+    d = A.desc()
+    check(lib().argcsr_spmv(ctypes.byref(d), _ptr(x), _ptr(y), _stream(stream)), "argcsr_spmv")
+    return y
+
+
+def csr_spmv(A: DeviceCsr, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+             values: Optional[torch.Tensor] = None, dtype: int = F64, lanes_per_row: int = 0,
+             stream=None) -> torch.Tensor:
+    """Plain CSR baseline y = A x (argcsr_csr_spmv).  `values` overrides A.val
+    with a tensor of storage_dtype(dtype) (e.g. FP32 values)."""
+    vals = A.val if values is None else values
+    if vals.dtype != _STORAGE[dtype]:
+        raise ValueError(f"values must be {_STORAGE[dtype]} for dtype {dtype}")
+    want = vector_dtype(dtype)
+    if x.dtype != want or x.numel() != A.n_cols:
+        raise ValueError(f"x must be a {want} vector of length {A.n_cols}")
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=want, device=x.device)
+    check(lib().argcsr_csr_spmv(A.n_rows, A.n_cols, A.nnz, _ptr(A.row_ptr), _ptr(A.col),
+                                _ptr(vals), int(dtype), int(lanes_per_row), _ptr(x), _ptr(y),
+                                _stream(stream)), "argcsr_csr_spmv")
+    return y

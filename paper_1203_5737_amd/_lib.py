@@ -1,0 +1,75 @@
+"""ctypes view of libargcsr.so (the C ABI declared in include/argcsr.h).
+
+There is no fallback: if the library is missing or fails to load, every
+entry point raises.  Build it with ``python -m paper_1203_5737_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libargcsr.so")
+
+OK, EINVAL, EOVERFLOW, ENOMEM, EHIP, EBUDGET, EBUSY, ENOTFOUND, EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+F64, F32, BF16, F16 = 0, 1, 2, 3
+
+_NAMES = {OK: "OK", EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EHIP: "EHIP",
+          EBUDGET: "EBUDGET", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND", EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class ArgCsrError(RuntimeError):
+    def __init__(self, code: int, where: str, message: str):
+        super().__init__(f"{where}: {_NAMES.get(code, code)} ({code}): {message}")
+        self.code = code
+
+
+class GroupInfo(ctypes.Structure):
+    _fields_ = [("first_row", ctypes.c_int32), ("size", ctypes.c_int32),
+                ("offset", ctypes.c_int32), ("chunk_size", ctypes.c_int32)]
+
+
+class MatrixDesc(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("block_dim", ctypes.c_int32), ("desired_chunk_size", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("n_slots", ctypes.c_int64),
+                ("groups", ctypes.c_void_p), ("threads_mapping", ctypes.c_void_p),
+                ("columns", ctypes.c_void_p), ("values", ctypes.c_void_p)]
+
+
+_lib = None
+i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+
+SIGNATURES = {
+    "argcsr_last_error": (ctypes.c_char_p, []),
+    "argcsr_version": (ctypes.c_int, []),
+    "argcsr_plan": (ctypes.c_int, [i32, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+    "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
+    "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),
+    "argcsr_csr_spmv": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, vp, vp, vp]),
+}
+
+
+def lib():
+    """The loaded library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is not built; run `python -m paper_1203_5737_amd.build` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int, where: str) -> None:
+    if code != OK:
+        msg = lib().argcsr_last_error()
+        raise ArgCsrError(code, where, msg.decode() if msg else "")

@@ -1,0 +1,318 @@
+// CSR -> ARG-CSR conversion on the GPU (Sec. 3 of the paper).
+//
+// Step 1 (grouping) is a sequential scan and runs on the host (plan.cpp).
+// The kernels here run steps 2-4, every group independently:
+//   chunks_kernel   step 2: chunk size c_g = min{c >= 1 : sum_r max(1,ceil(L_r/c)) <= T}
+//                   and t_r = max(1, ceil(L_r/c_g)) chunks per row;
+//                   step 3: inclusive per-group prefix sum of t_r -> threadsMapping
+//   offsets kernels exclusive scan of c_g*T over the groups -> groupInfo.offset
+//   fill_kernel     step 4: every slot (j, k) of a group -- element j of chunk
+//                   k at offset + j*T + k -- is written exactly once: the
+//                   matching CSR element if chunk k's row has one there,
+//                   otherwise the artificial zero (0, -1).
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.hpp"
+#include "plan.hpp"
+#include "values.hpp"
+
+namespace argcsr {
+namespace {
+
+constexpr int kWaves = 4;             // waves per workgroup, one group per wave
+constexpr int kMaxBlockDim = 1024;    // conversion accepts 1 <= T <= 1024
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;         // groups per thread in the offset scan
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+struct Status {                       // device-side results read back by the host
+  int bad_column;
+  int pad;
+  long long total_slots;
+};
+
+__global__ __launch_bounds__(256) void validate_columns_kernel(
+    const int32_t* __restrict__ col, int64_t nnz, int32_t n_cols, Status* st) {
+  bool bad = false;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < nnz;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t c = col[k];
+    bad |= (c < 0) | (c >= n_cols);
+  }
+  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&st->bad_column, 1);
+}
+
+// Step 2 + 3, one wave per group.  Row l of the group lives in lane l % 64,
+// sub-row l / 64.
+__global__ __launch_bounds__(kWaves * 64) void chunks_kernel(
+    const int32_t* __restrict__ rp, argcsr_group_info* __restrict__ groups,
+    int32_t n_groups, int32_t T, int32_t* __restrict__ tm) {
+  const int lane = lane_id();
+  const int g = blockIdx.x * kWaves + wave_uniform(int(threadIdx.x >> 6));
+  if (g >= n_groups) return;
+  const int32_t first = groups[g].first_row;
+  const int32_t size = groups[g].size;
+  const int sub_rows = (size + 63) / 64;
+
+  int64_t my_nnz = 0;
+  int my_longest = 0;
+  for (int s = 0; s < sub_rows; ++s) {
+    const int l = s * 64 + lane;
+    if (l < size) {
+      const int L = rp[first + l + 1] - rp[first + l];
+      my_nnz += L;
+      my_longest = L > my_longest ? L : my_longest;
+    }
+  }
+  const int64_t total = wave_sum_i64(my_nnz);
+  const int longest = wave_max(my_longest);
+
+  auto chunks_needed = [&](uint32_t c) {
+    int64_t need = 0;
+    for (int s = 0; s < sub_rows; ++s) {
+      const int l = s * 64 + lane;
+      if (l < size) {
+        const uint32_t L = uint32_t(rp[first + l + 1] - rp[first + l]);
+        need += L > c ? (L - 1u) / c + 1u : 1u;
+      }
+    }
+    return wave_sum_i64(need);
+  };
+  // binary search on the non-increasing chunks_needed(c)
+  uint32_t lo = uint32_t((total + T - 1) / T);
+  lo = lo < 1u ? 1u : lo;
+  uint32_t hi = longest < 1 ? 1u : uint32_t(longest);
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (chunks_needed(mid) <= T) hi = mid;
+    else lo = mid + 1;
+  }
+  const uint32_t c = lo;
+
+  int carry = 0;
+  for (int s = 0; s < sub_rows; ++s) {
+    const int l = s * 64 + lane;
+    int t = 0;
+    if (l < size) {
+      const uint32_t L = uint32_t(rp[first + l + 1] - rp[first + l]);
+      t = L > c ? int((L - 1u) / c + 1u) : 1;
+    }
+    const int incl = wave_inclusive_scan(t) + carry;
+    if (l < size) tm[first + l] = incl;
+    carry = __shfl(incl, 63, 64);
+  }
+  if (lane == 0) groups[g].chunk_size = int32_t(c);
+}
+
+// Offsets: block-local sums of c_g*T, a single-block scan of those, then the
+// block-local exclusive scan plus the block's base.
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t wave_tot[kScanBlock / 64];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  int64_t incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  if (lane == 63) wave_tot[w] = incl;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int i = 0; i < kScanBlock / 64; ++i) {
+    if (i < w) before += wave_tot[i];
+    all += wave_tot[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void offsets_reduce_kernel(
+    const argcsr_group_info* __restrict__ groups, int32_t n_groups, int32_t T,
+    int64_t* __restrict__ tile_sums) {
+  int64_t s = 0;
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n_groups) s += int64_t(groups[base + i].chunk_size) * T;
+  int64_t total;
+  (void)block_exclusive_scan(s, &total);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void offsets_tiles_kernel(
+    int64_t* __restrict__ tile_sums, int32_t n_tiles, Status* st) {
+  int64_t carry = 0;
+  for (int32_t base = 0; base < n_tiles; base += kScanBlock) {
+    const int32_t i = base + threadIdx.x;
+    const int64_t v = i < n_tiles ? tile_sums[i] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(v, &total);
+    if (i < n_tiles) tile_sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) st->total_slots = carry;
+}
+
+__global__ __launch_bounds__(kScanBlock) void offsets_apply_kernel(
+    argcsr_group_info* __restrict__ groups, int32_t n_groups, int32_t T,
+    const int64_t* __restrict__ tile_base) {
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+  int64_t s = 0;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n_groups) s += int64_t(groups[base + i].chunk_size) * T;
+  int64_t total;
+  int64_t off = tile_base[blockIdx.x] + block_exclusive_scan(s, &total);
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n_groups) {
+      groups[base + i].offset = int32_t(off);     // host checks the total fits int32
+      off += int64_t(groups[base + i].chunk_size) * T;
+    }
+  }
+}
+
+// Step 4, one wave per group.  For every chunk k the wave first records in
+// LDS where its elements start in the CSR arrays and how many there are
+// (0 for free chunks), then writes all c*T slots in slot order.
+template <int DT>
+__global__ __launch_bounds__(kWaves * 64) void fill_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const argcsr_group_info* __restrict__ groups,
+    int32_t n_groups, int32_t T, const int32_t* __restrict__ tm,
+    int32_t* __restrict__ columns, typename Val<DT>::storage* __restrict__ values) {
+  using S = typename Val<DT>::storage;
+  __shared__ int32_t src_start[kWaves][kMaxBlockDim];
+  __shared__ int32_t src_len[kWaves][kMaxBlockDim];
+  const int lane = lane_id();
+  const int w = wave_uniform(int(threadIdx.x >> 6));
+  const int g = blockIdx.x * kWaves + w;
+  if (g >= n_groups) return;
+  const argcsr_group_info gi = groups[g];
+  const int32_t c = gi.chunk_size;
+
+  for (int k = lane; k < T; k += 64) src_len[w][k] = 0;
+  wave_lds_sync();
+  for (int l = lane; l < gi.size; l += 64) {
+    const int32_t r = gi.first_row + l;
+    const int32_t begin = l == 0 ? 0 : tm[r - 1];
+    const int32_t end = tm[r];
+    const int32_t row_start = rp[r];
+    const int32_t L = rp[r + 1] - row_start;
+    for (int32_t k = begin; k < end; ++k) {
+      const int32_t q = k - begin;                    // chunk q of row r
+      const int32_t first_elem = q * c;
+      src_start[w][k] = row_start + first_elem;
+      const int32_t left = L - first_elem;
+      src_len[w][k] = left < 0 ? 0 : (left < c ? left : c);
+    }
+  }
+  wave_lds_sync();
+  const uint32_t n = uint32_t(c) * uint32_t(T);           // <= INT32_MAX (checked)
+  for (uint32_t s = lane; s < n; s += 64) {
+    const int32_t j = int32_t(s / uint32_t(T));
+    const int32_t k = int32_t(s - uint32_t(j) * uint32_t(T));
+    const int64_t dst = int64_t(gi.offset) + s;
+    if (j < src_len[w][k]) {
+      const int32_t e = src_start[w][k] + j;
+      columns[dst] = col[e];
+      values[dst] = Val<DT>::from_f64(val[e]);
+    } else {
+      columns[dst] = -1;
+      values[dst] = S(0);
+    }
+  }
+}
+
+template <int DT>
+void launch_fill(int blocks, hipStream_t s, const int32_t* rp, const int32_t* col,
+                 const double* val, const argcsr_matrix* out) {
+  fill_kernel<DT><<<blocks, kWaves * 64, 0, s>>>(
+      rp, col, val, out->groups, out->n_groups, out->block_dim, out->threads_mapping,
+      out->columns, static_cast<typename Val<DT>::storage*>(out->values));
+}
+
+}  // namespace
+}  // namespace argcsr
+
+extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                              const int32_t* row_ptr, const int32_t* col, const double* val,
+                              argcsr_matrix* out, void* stream) {
+  using namespace argcsr;
+  clear_error();
+  if (!out) return fail(ARGCSR_EINVAL, "out is NULL");
+  if (n_rows < 0 || n_cols < 0) return fail(ARGCSR_EINVAL, "negative dimension");
+  if (out->n_rows != n_rows || out->n_cols != n_cols)
+    return fail(ARGCSR_EINVAL, "out->n_rows/n_cols do not match the arguments");
+  const int32_t T = out->block_dim;
+  if (T < 1 || T > kMaxBlockDim)
+    return fail(ARGCSR_EUNSUPPORTED, "block_dim %d outside [1, %d]", T, kMaxBlockDim);
+  if (out->desired_chunk_size < 1) return fail(ARGCSR_EINVAL, "desired_chunk_size < 1");
+  if (out->dtype < ARGCSR_F64 || out->dtype > ARGCSR_F16)
+    return fail(ARGCSR_EINVAL, "unknown dtype %d", out->dtype);
+  int rc = check_row_ptr(n_rows, row_ptr_host);
+  if (rc) return rc;
+  const int64_t nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
+
+  std::vector<argcsr_group_info> host_groups;
+  rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, &host_groups);
+  if (rc) return rc;
+  const int32_t G = (int32_t)host_groups.size();
+  if (G != out->n_groups)
+    return fail(ARGCSR_EINVAL, "out->n_groups = %d but the matrix has %d groups", out->n_groups, G);
+  out->nnz = nnz;
+  if (G == 0) {
+    if (out->n_slots != 0) return fail(ARGCSR_EINVAL, "out->n_slots must be 0 for an empty matrix");
+    return ARGCSR_OK;
+  }
+  if (!row_ptr || !out->groups || !out->threads_mapping || !out->columns || !out->values ||
+      (nnz > 0 && (!col || !val)))
+    return fail(ARGCSR_EINVAL, "NULL device buffer");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
+  void* ws = nullptr;
+  rc = device_workspace(sizeof(Status) + sizeof(int64_t) * size_t(n_tiles), &ws);
+  if (rc) return rc;
+  Status* st = static_cast<Status*>(ws);
+  int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
+
+  ARGCSR_HIP(hipMemsetAsync(st, 0, sizeof(Status), s));
+  ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
+                            sizeof(argcsr_group_info) * size_t(G), hipMemcpyHostToDevice, s));
+  if (nnz > 0) {
+    const int64_t want = (nnz + 255) / 256;
+    const int blocks = (int)(want < 8192 ? want : 8192);
+    validate_columns_kernel<<<blocks, 256, 0, s>>>(col, nnz, n_cols, st);
+    ARGCSR_HIP(hipGetLastError());
+  }
+  const int wave_blocks = (G + kWaves - 1) / kWaves;
+  chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, out->groups, G, T,
+                                                   out->threads_mapping);
+  ARGCSR_HIP(hipGetLastError());
+  offsets_reduce_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, T, tile_sums);
+  offsets_tiles_kernel<<<1, kScanBlock, 0, s>>>(tile_sums, n_tiles, st);
+  offsets_apply_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, T, tile_sums);
+  ARGCSR_HIP(hipGetLastError());
+
+  Status host_st{};
+  ARGCSR_HIP(hipMemcpyAsync(&host_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  ARGCSR_HIP(hipStreamSynchronize(s));
+  if (host_st.bad_column)
+    return fail(ARGCSR_EINVAL, "a column index lies outside [0, %d)", n_cols);
+  if (host_st.total_slots > INT32_MAX)
+    return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", host_st.total_slots);
+  if (host_st.total_slots != out->n_slots)
+    return fail(ARGCSR_EINVAL, "out->n_slots = %lld but the matrix needs %lld",
+                (long long)out->n_slots, host_st.total_slots);
+
+  switch (out->dtype) {
+    case ARGCSR_F64: launch_fill<ARGCSR_F64>(wave_blocks, s, row_ptr, col, val, out); break;
+    case ARGCSR_F32: launch_fill<ARGCSR_F32>(wave_blocks, s, row_ptr, col, val, out); break;
+    case ARGCSR_BF16: launch_fill<ARGCSR_BF16>(wave_blocks, s, row_ptr, col, val, out); break;
+    default: launch_fill<ARGCSR_F16>(wave_blocks, s, row_ptr, col, val, out); break;
+  }
+  ARGCSR_HIP(hipGetLastError());
+  ARGCSR_HIP(hipStreamSynchronize(s));
+  return ARGCSR_OK;
+}

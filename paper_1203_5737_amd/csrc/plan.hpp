@@ -1,0 +1,27 @@
+// Host side of the conversion: validation of CSR row offsets, step 1
+// (grouping) and the chunk-size rule of step 2 used for sizing.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "argcsr.h"
+
+namespace argcsr {
+
+// rp[0] == 0 and non-decreasing.  Returns ARGCSR_OK or ARGCSR_EINVAL.
+int check_row_ptr(int32_t n_rows, const int32_t* rp);
+
+// Step 1 of the conversion (Sec. 3): consecutive rows form a group while the
+// group holds at most block_dim rows and at most desired*block_dim nonzeros;
+// a row that would break either limit opens the next group.  Fills
+// first_row/size of every group (offset and chunk_size left 0).
+int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+               int32_t desired, std::vector<argcsr_group_info>* groups);
+
+// Step 2 sizing: the smallest chunk size c >= 1 for which the rows of the
+// group need at most block_dim chunks, sum max(1, ceil(L_r / c)).
+int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
+                       int32_t block_dim);
+
+}  // namespace argcsr

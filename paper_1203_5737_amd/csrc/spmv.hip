@@ -1,0 +1,84 @@
+// y = A x for an ARG-CSR matrix on gfx950 (Sec. 4 of the paper: chunk
+// partial sums, then per-row sums of the partial sums).
+//
+// Mapping to CDNA4 (a wave has 64 lanes):
+//   - one wave per group; with T = 64*W chunks per group, lane i owns chunks
+//     i, i+64, ..., i+64*(W-1) ("sub-blocks" w = 0..W-1).  A group's slots
+//     for step j are T consecutive values/columns, so every load is a
+//     contiguous, fully coalesced wave-wide access (the paper's column-major
+//     chunk storage, Sec. 3);
+//   - the group struct is read with scalar loads (wave-uniform); no
+//     workgroup barrier is needed anywhere;
+//   - the threads mapping is turned into a bitmask of row-end chunks (chunk
+//     tm[l]-1 ends row l) through a small per-wave LDS table and a ballot;
+//   - each chunk sums value*x[column] over its slots, stopping at the first
+//     artificial zero (column -1); a wave leaves the loop once every lane
+//     has hit padding (Sec. 4);
+//   - row sums are a segmented inclusive scan across lanes (segments = rows,
+//     delimited by the row-end mask), carried from one sub-block to the next;
+//     the lane holding a row's last chunk writes y[first_row + row].
+//     Summation order is fixed by the layout, so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "spmv_kernels.hpp"
+
+namespace argcsr {
+namespace {
+
+template <int DT, int W, int U>
+void launch(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
+  using Vt = Val<DT>;
+  const int blocks = (A->n_groups + kSpmvWaves - 1) / kSpmvWaves;
+  argcsr_spmv_kernel<DT, W, U><<<blocks, kSpmvWaves * 64, 0, s>>>(
+      A->groups, A->n_groups, A->threads_mapping, A->columns,
+      static_cast<const typename Vt::storage*>(A->values),
+      static_cast<const typename Vt::acc*>(x), static_cast<typename Vt::acc*>(y));
+}
+
+template <int DT>
+void launch_dt(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
+  switch (A->block_dim) {
+    case 64: launch<DT, 1, 8>(A, x, y, s); break;
+    case 128: launch<DT, 2, 4>(A, x, y, s); break;
+    default: launch<DT, 4, 2>(A, x, y, s); break;
+  }
+}
+
+}  // namespace
+
+int check_matrix(const argcsr_matrix* A) {
+  if (!A) return fail(ARGCSR_EINVAL, "matrix is NULL");
+  if (A->n_rows < 0 || A->n_cols < 0 || A->n_groups < 0 || A->n_slots < 0)
+    return fail(ARGCSR_EINVAL, "negative size in matrix descriptor");
+  if (A->block_dim != 64 && A->block_dim != 128 && A->block_dim != 256)
+    return fail(ARGCSR_EUNSUPPORTED, "block_dim %d: the GPU kernels take 64, 128 or 256",
+                A->block_dim);
+  if (A->dtype < ARGCSR_F64 || A->dtype > ARGCSR_F16)
+    return fail(ARGCSR_EINVAL, "unknown dtype %d", A->dtype);
+  if (A->n_slots > INT32_MAX) return fail(ARGCSR_EOVERFLOW, "n_slots exceeds INT32_MAX");
+  if (A->n_groups > 0 && (!A->groups || !A->threads_mapping || !A->columns || !A->values))
+    return fail(ARGCSR_EINVAL, "NULL device buffer in matrix descriptor");
+  return ARGCSR_OK;
+}
+
+}  // namespace argcsr
+
+extern "C" int argcsr_spmv(const argcsr_matrix* A, const void* x, void* y, void* stream) {
+  using namespace argcsr;
+  clear_error();
+  int rc = check_matrix(A);
+  if (rc) return rc;
+  if (A->n_groups == 0) return ARGCSR_OK;
+  if (!x || !y) return fail(ARGCSR_EINVAL, "x or y is NULL");
+  if (x == y) return fail(ARGCSR_EINVAL, "y must not alias x");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  switch (A->dtype) {
+    case ARGCSR_F64: launch_dt<ARGCSR_F64>(A, x, y, s); break;
+    case ARGCSR_F32: launch_dt<ARGCSR_F32>(A, x, y, s); break;
+    case ARGCSR_BF16: launch_dt<ARGCSR_BF16>(A, x, y, s); break;
+    default: launch_dt<ARGCSR_F16>(A, x, y, s); break;
+  }
+  ARGCSR_HIP(hipGetLastError());
+  return ARGCSR_OK;
+}

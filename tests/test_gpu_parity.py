@@ -1,0 +1,286 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Conversion must be bit-exact (groups, threads mapping, columns, value bits).
+FP64 SpMV must satisfy |y_gpu - y_oracle| <= 1e-12 * sum_j |a_ij x_j| per
+row (exact where that sum is 0).  Reduced-precision SpMV (FP32 accumulation)
+is checked against the FP64 oracle evaluated on the stored (rounded) values
+with the worst-case bound gamma_{L+1}(2^-24) * sum_j |a_ij x_j|.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from conftest import gpu_available
+from helpers import U32, abs_row_sums, gamma, powerlaw_sample, scaled_error
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ac():
+    import paper_1203_5737_amd as ac
+    ac._lib.lib()          # raises if the HIP library is not built
+    return ac
+
+
+def announce(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+def compare_conversion(ac, A, T, D, dtype):
+    announce(f"convert n={A.n_rows} nnz={A.nnz} T={T} D={D} dtype={dtype}")
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    M = ac.convert(dev, T, D, dtype)
+    ref = oracle.convert(A.rp, A.col, A.val, T, D, dtype)
+    assert M.n_groups == ref.n_groups and M.n_slots == ref.n_slots
+    assert np.array_equal(M.groups.cpu().numpy(), ref.groups)
+    assert np.array_equal(M.threads_mapping.cpu().numpy(), ref.tm)
+    assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
+    gv = M.values.cpu()
+    gbits = gv.view(torch.int64 if dtype == 0 else torch.int32 if dtype == 1 else torch.int16)
+    rbits = ref.values.view(np.int64 if dtype == 0 else np.int32 if dtype == 1 else np.int16)
+    assert np.array_equal(gbits.numpy(), rbits)
+    return dev, M, ref
+
+
+def fig3():
+    rp = np.array([0, 1, 2, 3, 4, 5, 6, 7, 15], dtype=np.int32)
+    col = np.array(list(range(7)) + list(range(8)), dtype=np.int32)
+    val = np.array([1, 2, 3, 4, 5, 6, 7] + [10 + j for j in range(8)], dtype=np.float64)
+    return synth.Csr(8, 8, rp, col, val)
+
+
+# ---------------------------------------------------------------------------
+# conversion: bit-exact
+# ---------------------------------------------------------------------------
+
+def test_convert_fig3_any_block_dim(ac):
+    compare_conversion(ac, fig3(), 12, 2, oracle.F64)
+    compare_conversion(ac, fig3(), 12, 1, oracle.F64)
+    compare_conversion(ac, fig3(), 3, 1, oracle.F32)
+
+
+@pytest.mark.parametrize("T,D", [(64, 1), (64, 5), (128, 1), (256, 4), (100, 2)])
+def test_convert_laplace64(ac, T, D):
+    A, _ = synth.workload_laplace64()
+    compare_conversion(ac, A, T, D, oracle.F64)
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2, 3])
+def test_convert_dtypes_bit_exact(ac, dtype):
+    A, _ = powerlaw_sample(40_000, seed=1)
+    # include values that stress rounding: ties, subnormal and overflow range
+    rng = np.random.default_rng(5)
+    special = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -11, 65520.0, 70000.0, 1e-7,
+                        3e-8, 2.0 ** -25, 1e-300, 3.4e38, -(1 + 2 ** -8), 0.0, -0.0, 1e39,
+                        1e-40, -2.5e-39, 1.2e-38, 6.1e-5, -6.0e-5])
+    A.val[: special.size] = special
+    A.val[special.size:2000] = rng.normal(0, 1e4, 2000 - special.size)
+    for T, D in [(64, 1), (256, 2)]:
+        compare_conversion(ac, A, T, D, dtype)
+
+
+@pytest.mark.parametrize("T,D", [(64, 1), (64, 2), (64, 4), (128, 1), (256, 1), (7, 3), (1000, 1)])
+def test_convert_powerlaw(ac, T, D):
+    A, _ = powerlaw_sample(60_000, seed=2)
+    compare_conversion(ac, A, T, D, oracle.F64)
+
+
+def test_convert_edge_cases(ac):
+    rng = np.random.default_rng(9)
+    # empty rows mixed in, a 10^4 row, a row of 1000 (chunk 16 at T=64)
+    L = rng.integers(0, 5, 3000)
+    L[::7] = 0
+    L[100] = 10_000
+    L[2000] = 1000
+    A = synth.random_csr(L, 20_000, rng, rng)
+    for T, D in [(64, 1), (128, 3), (256, 1)]:
+        compare_conversion(ac, A, T, D, oracle.F64)
+    # every row empty
+    E = synth.Csr(500, 10, np.zeros(501, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    compare_conversion(ac, E, 64, 1, oracle.F64)
+    # a single row
+    compare_conversion(ac, synth.random_csr(np.array([1000]), 1000, rng, rng), 64, 1, oracle.F64)
+
+
+def test_convert_rejects_bad_input(ac):
+    A, _ = synth.workload_laplace64()
+    col = A.col.copy()
+    col[77] = A.n_cols           # out of range
+    dev = ac.to_device_csr(A.rp, col, A.val, A.n_cols, DEV)
+    with pytest.raises(ac.ArgCsrError) as e:
+        ac.convert(dev, 64, 1)
+    assert e.value.code == ac._lib.EINVAL
+    col[77] = -1                 # the padding marker is never a real column
+    dev = ac.to_device_csr(A.rp, col, A.val, A.n_cols, DEV)
+    with pytest.raises(ac.ArgCsrError):
+        ac.convert(dev, 64, 1)
+
+
+# ---------------------------------------------------------------------------
+# SpMV
+# ---------------------------------------------------------------------------
+
+def gpu_spmv(ac, M, x):
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    y = torch.full((M.n_rows,), float("nan"), dtype=ac.vector_dtype(M.dtype), device=DEV)
+    ac.spmv(M, xd, y)
+    return y.cpu().numpy().astype(np.float64)
+
+
+def check_f64(A, x, y):
+    y_ref = oracle.csr_spmv(A.rp, A.col, A.val, x)
+    worst, zero_ok = scaled_error(y, y_ref, abs_row_sums(A.rp, A.col, A.val, x))
+    assert zero_ok and worst <= 1e-12, worst
+    return worst
+
+
+def check_reduced(A, x, y, dtype):
+    """y computed with values stored in `dtype`, x in FP32, FP32 accumulation."""
+    stored = oracle.stored_as_f64(oracle.round_array(A.val, dtype), dtype)
+    x32 = x.astype(np.float32).astype(np.float64)
+    y_ref = oracle.csr_spmv(A.rp, A.col, stored, x32)
+    scale = abs_row_sums(A.rp, A.col, stored, x32)
+    L = np.diff(A.rp)
+    d = np.abs(y - y_ref)
+    bound = gamma(L + 1, U32) * scale
+    assert np.all(d <= bound), float(np.max(d - bound))      # rows with scale 0: exact
+    # storage error against the FP64 oracle on the original values (reported)
+    y64 = oracle.csr_spmv(A.rp, A.col, A.val, x)
+    s64 = abs_row_sums(A.rp, A.col, A.val, x)
+    acc_err, _ = scaled_error(y, y_ref, scale)
+    tot_err, _ = scaled_error(y, y64, s64)
+    return acc_err, tot_err
+
+
+def test_spmv_laplace64_closed_form_exact(ac):
+    """5-point stencil on u = i^2 + j^2: every product and partial sum is a
+    small integer, so the GPU result equals the closed form bit for bit."""
+    A, _ = synth.workload_laplace64()
+    n = 64
+    i, j = np.divmod(np.arange(n * n), n)
+    u = (i * i + j * j).astype(np.float64)
+    want = 4 * u
+    for di, dj in [(-1, 0), (1, 0), (0, -1), (0, 1)]:
+        ok = (i + di >= 0) & (i + di < n) & (j + dj >= 0) & (j + dj < n)
+        want[ok] -= u[((i + di) * n + j + dj)[ok]]
+    for T, D in [(64, 1), (64, 5), (128, 1), (256, 4)]:
+        for dtype in [0, 1, 2, 3]:
+            dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+            M = ac.convert(dev, T, D, dtype)
+            y = gpu_spmv(ac, M, u if dtype == 0 else u.astype(np.float32))
+            assert np.array_equal(y, want), (T, D, dtype)
+
+
+@pytest.mark.parametrize("T,D", [(64, 1), (64, 5), (128, 1), (256, 4)])
+def test_spmv_laplace64_f64(ac, T, D):
+    A, x = synth.workload_laplace64()
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    M = ac.convert(dev, T, D)
+    check_f64(A, x, gpu_spmv(ac, M, x))
+
+
+@pytest.mark.parametrize("T,D", [(64, 1), (64, 4), (128, 1), (128, 2), (256, 1), (256, 2)])
+def test_spmv_powerlaw_f64(ac, T, D):
+    A, x = powerlaw_sample(80_000, seed=3)
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    M = ac.convert(dev, T, D)
+    check_f64(A, x, gpu_spmv(ac, M, x))
+
+
+def test_spmv_edge_cases(ac):
+    rng = np.random.default_rng(10)
+    L = rng.integers(0, 4, 5000)
+    L[::5] = 0
+    L[17] = 10_000
+    L[4000] = 64 * 64 + 3          # longer than one group's 64 chunks of 64
+    A = synth.random_csr(L, 30_000, rng, rng)
+    x = rng.uniform(-1, 1, A.n_cols)
+    for T, D in [(64, 1), (128, 1), (256, 1), (256, 8)]:
+        dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+        M = ac.convert(dev, T, D)
+        y = gpu_spmv(ac, M, x)
+        check_f64(A, x, y)
+        assert np.all(y[L == 0] == 0)
+    # all rows empty: y overwritten with zeros
+    E = synth.Csr(300, 5, np.zeros(301, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    M = ac.convert(ac.to_device_csr(E.rp, E.col, E.val, 5, DEV), 64, 1)
+    assert np.all(gpu_spmv(ac, M, np.ones(5)) == 0)
+
+
+@pytest.mark.parametrize("dtype", [1, 2, 3])
+def test_spmv_reduced_precision(ac, dtype):
+    for A, x in [powerlaw_sample(50_000, seed=4), synth.workload_stencil27(24)]:
+        dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+        for T, D in [(64, 1), (256, 2)]:
+            M = ac.convert(dev, T, D, dtype)
+            y = gpu_spmv(ac, M, x.astype(np.float32))
+            acc_err, tot_err = check_reduced(A, x, y, dtype)
+            announce(f"dtype={dtype} T={T} D={D}: accumulation err {acc_err:.2e}, "
+                     f"total err vs FP64 {tot_err:.2e} (x sum|ax|)")
+
+
+def test_spmv_deterministic(ac):
+    A, x = powerlaw_sample(100_000, seed=5)
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    M = ac.convert(dev, 128, 1)
+    y1, y2 = gpu_spmv(ac, M, x), gpu_spmv(ac, M, x)
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+
+
+@pytest.mark.parametrize("V", [0, 1, 2, 8, 64])
+def test_csr_baseline(ac, V):
+    A, x = powerlaw_sample(30_000, seed=6)
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    xd = torch.from_numpy(x).to(DEV)
+    y = ac.csr_spmv(dev, xd, lanes_per_row=V).cpu().numpy()
+    check_f64(A, x, y)
+    vals32 = dev.val.to(torch.float32)
+    y32 = ac.csr_spmv(dev, xd.float(), values=vals32, dtype=ac.F32, lanes_per_row=V)
+    check_reduced(A, x, y32.cpu().numpy().astype(np.float64), oracle.F32)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def powerlaw_full():
+    return synth.workload_powerlaw()
+
+
+@pytest.fixture(scope="module")
+def stencil_full():
+    return synth.workload_stencil27(128)
+
+
+@pytest.mark.parametrize("T,D", [(64, 1), (256, 1)])
+def test_full_powerlaw_f64(ac, powerlaw_full, T, D):
+    A, x = powerlaw_full
+    dev, M, ref = compare_conversion(ac, A, T, D, oracle.F64)
+    check_f64(A, x, gpu_spmv(ac, M, x))
+
+
+def test_full_powerlaw_f32(ac, powerlaw_full):
+    A, x = powerlaw_full
+    dev, M, ref = compare_conversion(ac, A, 64, 1, oracle.F32)
+    acc, tot = check_reduced(A, x, gpu_spmv(ac, M, x.astype(np.float32)), oracle.F32)
+    announce(f"powerlaw FP32: accumulation err {acc:.2e}, total {tot:.2e}")
+
+
+def test_full_stencil_all_dtypes(ac, stencil_full):
+    A, x = stencil_full
+    dev, M, ref = compare_conversion(ac, A, 64, 27, oracle.F64)
+    check_f64(A, x, gpu_spmv(ac, M, x))
+    del M, ref
+    for dtype in (1, 2, 3):
+        M = ac.convert(dev, 64, 27, dtype)
+        acc, tot = check_reduced(A, x, gpu_spmv(ac, M, x.astype(np.float32)), dtype)
+        announce(f"stencil dtype={dtype}: accumulation err {acc:.2e}, total {tot:.2e}")
+        del M
+    torch.cuda.empty_cache()

@@ -1,0 +1,124 @@
+"""Host-side checks of libargcsr that need no GPU: the library loads, exports
+every symbol the public header declares, its host planning (conversion step
+1 and the step-2 slot count) agrees with the oracle, and it reports errors."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1203_5737_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1203_5737_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(argcsr_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "argcsr_spmv" in names and "argcsr_convert" in names and len(names) >= 6
+    from paper_1203_5737_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    for n in names:
+        assert hasattr(L, n)
+
+
+def test_product_does_not_touch_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1203_5737_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "oracle.h" not in text, f
+                assert "liboracle" not in text, f
+    from paper_1203_5737_amd import _lib
+    ldd = subprocess.run(["ldd", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in ldd
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_1203_5737_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libargcsr.so")
+    with pytest.raises(ImportError):
+        _lib.lib()
+
+
+def plan(L, rp, T, D):
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    g, s = ctypes.c_int32(0), ctypes.c_int64(0)
+    rc = L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D,
+                       ctypes.byref(g), ctypes.byref(s))
+    return rc, g.value, s.value
+
+
+def test_plan_matches_oracle_on_workload_shapes(L, ora):
+    A, _ = synth.workload_laplace64()
+    Ap, _ = synth.workload_powerlaw(300_000)
+    fig3 = np.array([0, 1, 2, 3, 4, 5, 6, 7, 15], dtype=np.int32)
+    cases = [(fig3, 12, 2), (fig3, 12, 1), (A.rp, 64, 1), (A.rp, 64, 5), (A.rp, 256, 3),
+             (Ap.rp, 64, 1), (Ap.rp, 64, 4), (Ap.rp, 128, 1), (Ap.rp, 256, 2), (Ap.rp, 7, 3)]
+    for rp, T, D in cases:
+        assert plan(L, rp, T, D) == ora.sizes(rp, T, D), (T, D)
+
+
+@settings(max_examples=200, deadline=None)
+@given(lengths=st.lists(st.integers(0, 300), min_size=0, max_size=200),
+       T=st.integers(1, 300), D=st.integers(1, 40))
+def test_plan_matches_oracle_random(L, ora, lengths, T, D):
+    rp = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    assert plan(L, rp, T, D) == ora.sizes(rp, T, D)
+
+
+def test_plan_errors(L):
+    from paper_1203_5737_amd import _lib
+    good = np.array([0, 2, 3], dtype=np.int32)
+    assert plan(L, good, 0, 1)[0] == _lib.EINVAL
+    assert plan(L, good, 64, 0)[0] == _lib.EINVAL
+    assert plan(L, np.array([1, 2, 3], dtype=np.int32), 64, 1)[0] == _lib.EINVAL
+    assert plan(L, np.array([0, 3, 2], dtype=np.int32), 64, 1)[0] == _lib.EINVAL
+    assert b"decreases" in L.argcsr_last_error()
+    # 17M rows of 65 nonzeros at T=64: every row alone with chunk size 2
+    rp = (np.arange(17_000_001, dtype=np.int64) * 65).astype(np.int32)
+    rc, G, S = plan(L, rp, 64, 1)
+    assert rc == _lib.EOVERFLOW and S == 17_000_000 * 128
+    assert plan(L, np.zeros(1, dtype=np.int32), 64, 1) == (0, 0, 0)
+
+
+def test_gpu_entry_points_reject_bad_arguments_without_gpu(L):
+    """Argument checks run before any HIP call, so they work on a CPU host."""
+    from paper_1203_5737_amd import _lib
+    d = _lib.MatrixDesc()
+    d.block_dim, d.dtype, d.n_rows, d.n_cols = 96, 0, 10, 10
+    assert L.argcsr_spmv(ctypes.byref(d), None, None, None) == _lib.EUNSUPPORTED
+    d.block_dim, d.dtype = 64, 9
+    assert L.argcsr_spmv(ctypes.byref(d), None, None, None) == _lib.EINVAL
+    assert L.argcsr_spmv(None, None, None, None) == _lib.EINVAL
+    assert L.argcsr_csr_spmv(4, 4, 4, None, None, None, 0, 3, None, None, None) == _lib.EINVAL
