@@ -36,7 +36,10 @@ HBM_PEAK_GBPS = 8000.0
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_amd/csrc/spmv.hip",
-                  "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp"]
+                  "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp",
+                  "paper_1203_5737_amd/csrc/schedule.hpp"]
+# (block_dim, desired_chunk_size) per workload unless given on the command line
+DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (64, 27), "laplace64": (64, 1)}
 
 
 def kernel_source_hash() -> str:
@@ -116,7 +119,7 @@ def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
     t0 = time.perf_counter()
     oracle.csr_spmv(A.rp, A.col, A.val, x, threads)
     one = max(time.perf_counter() - t0, 1e-6)
-    reps = int(max(3, min(2000, (budget_s * 0.6) / one)))
+    reps = int(max(3, min(100_000, (budget_s * 0.6) / one)))
     t0 = time.perf_counter()
     for _ in range(reps):
         oracle.csr_spmv(A.rp, A.col, A.val, x, threads)
@@ -137,13 +140,16 @@ def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
 def traffic_for(workload: str, dtype_name: str, T: int, D: int):
     """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE for
     the current kernel source (None when absent or the kernel has changed)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(f"{workload}/{dtype_name}/T{T}/D{D}")
-    if not rec or rec.get("kernel_hash") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+    want = f"{workload}/{dtype_name}/T{T}/D{D}"
+    for line in open(path):
+        f = line.split()
+        # key  kernel_hash  fetch_bytes  write_bytes  (scaled, per launch)
+        if len(f) >= 4 and not line.startswith("#") and f[0] == want and f[1] == kernel_source_hash():
+            return int(f[2]) + int(f[3])
+    return None
 
 
 def main():
@@ -153,8 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="powerlaw")
     ap.add_argument("--dtype", default="f64", choices=list(DTYPES))
-    ap.add_argument("--block-dim", type=int, default=64)
-    ap.add_argument("--desired-chunk-size", type=int, default=1)
+    ap.add_argument("--block-dim", type=int, default=None)
+    ap.add_argument("--desired-chunk-size", type=int, default=None)
     ap.add_argument("--warm", action="store_true", help="no cache flush between steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the CSR and warm timings")
@@ -172,7 +178,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     ac._lib.lib()                                    # fails loudly if not built
     dtype = DTYPES[args.dtype]
-    T, D = args.block_dim, args.desired_chunk_size
+    T0, D0 = DEFAULT_PARAMS.get(args.workload, (64, 1))
+    T = args.block_dim or T0
+    D = args.desired_chunk_size or D0
 
     A, x, desc = load_workload(args.workload)
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")

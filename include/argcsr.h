@@ -59,12 +59,19 @@ typedef struct {
   int32_t chunk_size;
 } argcsr_group_info;
 
-/* A converted matrix.  All four arrays are caller-owned device memory:
+/* A converted matrix.  All arrays are caller-owned device memory:
  *   groups[n_groups]            group table (Listing 1)
  *   threads_mapping[n_rows]     per group, inclusive prefix sum of the number
  *                               of chunks of each row (Sec. 3, Listing 2)
  *   columns[n_slots]            column index, -1 marks an artificial zero
  *   values[n_slots]             value, element type given by dtype
+ *   heavy_groups[n_heavy]       launch schedule (not part of the paper's
+ *                               format): ascending indices of the groups whose
+ *                               chunk_size exceeds heavy_chunk, i.e. whose
+ *                               chunk loop is long enough to be split over all
+ *                               waves of a workgroup and started first.  May
+ *                               be NULL (then every group is processed by one
+ *                               wave, in order).
  * block_dim (chunks per group, the paper's blockDim.x) must be 64, 128 or
  * 256 on the GPU; desired_chunk_size (the paper's desiredChunkSize) >= 1. */
 typedef struct {
@@ -80,6 +87,9 @@ typedef struct {
   int32_t* threads_mapping;
   int32_t* columns;
   void* values;
+  int32_t n_heavy;             /* set by argcsr_plan / argcsr_convert */
+  int32_t heavy_chunk;         /* set by argcsr_convert */
+  int32_t* heavy_groups;
 } argcsr_matrix;
 
 /* Message describing the calling thread's most recent failure ("" if none). */
@@ -100,11 +110,13 @@ int argcsr_version(void);
  *   block_dim         >= 1 (the GPU entry points accept 64, 128, 256)
  *   desired_chunk_size >= 1
  *   n_groups, n_slots out: group count and slot count (sum c_g*block_dim)
+ *   n_heavy           out (may be NULL): length of the heavy_groups schedule
  * Errors: EINVAL (bad sizes, row_ptr not starting at 0 or decreasing),
  * EOVERFLOW (slot count > INT32_MAX).  Allocates only host memory.
  */
 int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
-                int32_t desired_chunk_size, int32_t* n_groups, int64_t* n_slots);
+                int32_t desired_chunk_size, int32_t* n_groups, int64_t* n_slots,
+                int32_t* n_heavy);
 
 /*
  * argcsr_convert -- CSR -> ARG-CSR on the GPU (Sec. 3, all four steps).
@@ -117,9 +129,10 @@ int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
  *   col           device int32[nnz], 0 <= col < n_cols
  *   val           device double[nnz]
  *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, dtype,
- *                     n_groups and n_slots as returned by argcsr_plan, and
- *                     the four device buffers of those sizes;
- *                 out: nnz, and the four buffers filled.
+ *                     n_groups, n_slots and n_heavy as returned by
+ *                     argcsr_plan, and the device buffers of those sizes
+ *                     (heavy_groups may be NULL);
+ *                 out: nnz, heavy_chunk, and the buffers filled.
  * Reduced dtypes round each value to nearest-even directly from FP64.
  * Synchronous: waits for its kernels (it reads back a validation flag).
  * Errors: EINVAL (malformed CSR incl. a column outside [0, n_cols), sizes

@@ -87,45 +87,59 @@ class ArgCsrMatrix:
     threads_mapping: torch.Tensor  # int32 [n_rows]
     columns: torch.Tensor          # int32 [n_slots]
     values: torch.Tensor           # storage_dtype(dtype) [n_slots]
+    heavy_groups: Optional[torch.Tensor] = None   # int32 [n_heavy] launch schedule
+    n_heavy: int = 0
+    heavy_chunk: int = 0
 
     def desc(self) -> MatrixDesc:
         return MatrixDesc(self.n_rows, self.n_cols, self.block_dim, self.desired_chunk_size,
                           self.dtype, self.n_groups, self.nnz, self.n_slots,
                           _ptr(self.groups), _ptr(self.threads_mapping), _ptr(self.columns),
-                          _ptr(self.values))
+                          _ptr(self.values), self.n_heavy, self.heavy_chunk,
+                          _ptr(self.heavy_groups))
 
     def nbytes(self) -> int:
-        return sum(t.numel() * t.element_size()
-                   for t in (self.groups, self.threads_mapping, self.columns, self.values))
+        ts = [self.groups, self.threads_mapping, self.columns, self.values]
+        if self.heavy_groups is not None:
+            ts.append(self.heavy_groups)
+        return sum(t.numel() * t.element_size() for t in ts)
 
 
 def plan(row_ptr_host, block_dim: int, desired_chunk_size: int):
-    """(n_groups, n_slots) of the converted matrix (host only)."""
+    """(n_groups, n_slots, n_heavy) of the converted matrix (host only)."""
     rp = np.ascontiguousarray(np.asarray(row_ptr_host, dtype=np.int32))
-    g, s = ctypes.c_int32(0), ctypes.c_int64(0)
+    g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
     check(lib().argcsr_plan(int(rp.shape[0] - 1), rp.ctypes.data_as(ctypes.c_void_p),
                             int(block_dim), int(desired_chunk_size), ctypes.byref(g),
-                            ctypes.byref(s)), "argcsr_plan")
-    return g.value, s.value
+                            ctypes.byref(s), ctypes.byref(h)), "argcsr_plan")
+    return g.value, s.value, h.value
 
 
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
-            dtype: int = F64, stream=None) -> ArgCsrMatrix:
-    """CSR -> ARG-CSR on the GPU (argcsr_convert); allocates the result."""
-    G, S = plan(A.row_ptr_host, block_dim, desired_chunk_size)
+            dtype: int = F64, stream=None, schedule: bool = True) -> ArgCsrMatrix:
+    """CSR -> ARG-CSR on the GPU (argcsr_convert); allocates the result.
+    `schedule` also builds the heavy-group launch schedule."""
+    G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size)
     dev = A.row_ptr.device
     out = ArgCsrMatrix(
         A.n_rows, A.n_cols, int(block_dim), int(desired_chunk_size), int(dtype), G, A.nnz, S,
         torch.empty((G, 4), dtype=torch.int32, device=dev),
         torch.empty(A.n_rows, dtype=torch.int32, device=dev),
         torch.empty(S, dtype=torch.int32, device=dev),
-        torch.empty(S, dtype=_STORAGE[dtype], device=dev))
+        torch.empty(S, dtype=_STORAGE[dtype], device=dev),
+        torch.empty(H, dtype=torch.int32, device=dev) if schedule else None,
+        H if schedule else 0)
     d = out.desc()
+    if schedule and H == 0:
+        d.heavy_groups = None
     check(lib().argcsr_convert(A.n_rows, A.n_cols,
                                A.row_ptr_host.ctypes.data_as(ctypes.c_void_p),
                                _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), ctypes.byref(d),
                                _stream(stream)), "argcsr_convert")
     out.nnz = int(d.nnz)
+    out.heavy_chunk = int(d.heavy_chunk)
+    if not schedule:
+        out.n_heavy = 0
     return out
 
 

@@ -6,6 +6,8 @@
 //                   and t_r = max(1, ceil(L_r/c_g)) chunks per row;
 //                   step 3: inclusive per-group prefix sum of t_r -> threadsMapping
 //   offsets kernels exclusive scan of c_g*T over the groups -> groupInfo.offset
+//   heavy kernels   the launch schedule: ascending indices of groups whose
+//                   chunk loop is long (compaction by an exclusive scan)
 //   fill_kernel     step 4: every slot (j, k) of a group -- element j of chunk
 //                   k at offset + j*T + k -- is written exactly once: the
 //                   matching CSR element if chunk k's row has one there,
@@ -16,6 +18,7 @@
 
 #include "common.hpp"
 #include "plan.hpp"
+#include "schedule.hpp"
 #include "values.hpp"
 
 namespace argcsr {
@@ -31,6 +34,7 @@ struct Status {                       // device-side results read back by the ho
   int bad_column;
   int pad;
   long long total_slots;
+  long long total_heavy;
 };
 
 __global__ __launch_bounds__(256) void validate_columns_kernel(
@@ -141,8 +145,8 @@ __global__ __launch_bounds__(kScanBlock) void offsets_reduce_kernel(
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanBlock) void offsets_tiles_kernel(
-    int64_t* __restrict__ tile_sums, int32_t n_tiles, Status* st) {
+__global__ __launch_bounds__(kScanBlock) void tiles_scan_kernel(
+    int64_t* __restrict__ tile_sums, int32_t n_tiles, long long* total_out) {
   int64_t carry = 0;
   for (int32_t base = 0; base < n_tiles; base += kScanBlock) {
     const int32_t i = base + threadIdx.x;
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(kScanBlock) void offsets_tiles_kernel(
     if (i < n_tiles) tile_sums[i] = carry + ex;
     carry += total;
   }
-  if (threadIdx.x == 0) st->total_slots = carry;
+  if (threadIdx.x == 0) *total_out = carry;
 }
 
 __global__ __launch_bounds__(kScanBlock) void offsets_apply_kernel(
@@ -170,6 +174,34 @@ __global__ __launch_bounds__(kScanBlock) void offsets_apply_kernel(
       off += int64_t(groups[base + i].chunk_size) * T;
     }
   }
+}
+
+// Heavy-group schedule: per-tile counts, then (after the tile scan) each
+// tile writes the indices of its heavy groups in ascending order.
+__global__ __launch_bounds__(kScanBlock) void heavy_count_kernel(
+    const argcsr_group_info* __restrict__ groups, int32_t n_groups, int32_t heavy_chunk,
+    int64_t* __restrict__ tile_sums) {
+  int64_t s = 0;
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n_groups) s += groups[base + i].chunk_size > heavy_chunk;
+  int64_t total;
+  (void)block_exclusive_scan(s, &total);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void heavy_scatter_kernel(
+    const argcsr_group_info* __restrict__ groups, int32_t n_groups, int32_t heavy_chunk,
+    const int64_t* __restrict__ tile_base, int32_t* __restrict__ heavy) {
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+  int64_t s = 0;
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n_groups) s += groups[base + i].chunk_size > heavy_chunk;
+  int64_t total;
+  int64_t pos = tile_base[blockIdx.x] + block_exclusive_scan(s, &total);
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n_groups && groups[base + i].chunk_size > heavy_chunk)
+      heavy[pos++] = int32_t(base + i);
 }
 
 // Step 4, one wave per group.  For every chunk k the wave first records in
@@ -261,7 +293,9 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   if (G != out->n_groups)
     return fail(ARGCSR_EINVAL, "out->n_groups = %d but the matrix has %d groups", out->n_groups, G);
   out->nnz = nnz;
+  out->heavy_chunk = heavy_chunk_for(T, out->n_slots, G);
   if (G == 0) {
+    out->n_heavy = 0;
     if (out->n_slots != 0) return fail(ARGCSR_EINVAL, "out->n_slots must be 0 for an empty matrix");
     return ARGCSR_OK;
   }
@@ -272,10 +306,14 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
   void* ws = nullptr;
-  rc = device_workspace(sizeof(Status) + sizeof(int64_t) * size_t(n_tiles), &ws);
+  rc = device_workspace(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), &ws);
   if (rc) return rc;
   Status* st = static_cast<Status*>(ws);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
+  int64_t* heavy_tiles = tile_sums + n_tiles;
+  // uses the caller's slot count; it is checked against the device total
+  // before anything is written to the caller's heavy_groups buffer
+  const int32_t heavy_chunk = out->heavy_chunk;
 
   ARGCSR_HIP(hipMemsetAsync(st, 0, sizeof(Status), s));
   ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
@@ -291,8 +329,10 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
                                                    out->threads_mapping);
   ARGCSR_HIP(hipGetLastError());
   offsets_reduce_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, T, tile_sums);
-  offsets_tiles_kernel<<<1, kScanBlock, 0, s>>>(tile_sums, n_tiles, st);
+  tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(tile_sums, n_tiles, &st->total_slots);
   offsets_apply_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, T, tile_sums);
+  heavy_count_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, heavy_chunk, heavy_tiles);
+  tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(heavy_tiles, n_tiles, &st->total_heavy);
   ARGCSR_HIP(hipGetLastError());
 
   Status host_st{};
@@ -305,6 +345,13 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   if (host_st.total_slots != out->n_slots)
     return fail(ARGCSR_EINVAL, "out->n_slots = %lld but the matrix needs %lld",
                 (long long)out->n_slots, host_st.total_slots);
+  if (out->heavy_groups && host_st.total_heavy != out->n_heavy)
+    return fail(ARGCSR_EINVAL, "out->n_heavy = %d but the matrix has %lld heavy groups",
+                out->n_heavy, host_st.total_heavy);
+  out->n_heavy = int32_t(host_st.total_heavy);
+  if (out->heavy_groups && out->n_heavy > 0)
+    heavy_scatter_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, heavy_chunk, heavy_tiles,
+                                                        out->heavy_groups);
 
   switch (out->dtype) {
     case ARGCSR_F64: launch_fill<ARGCSR_F64>(wave_blocks, s, row_ptr, col, val, out); break;

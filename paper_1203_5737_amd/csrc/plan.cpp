@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "schedule.hpp"
 
 namespace argcsr {
 
@@ -66,7 +67,7 @@ int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
 
 extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
                            int32_t block_dim, int32_t desired_chunk_size,
-                           int32_t* n_groups, int64_t* n_slots) {
+                           int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy) {
   using namespace argcsr;
   clear_error();
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
@@ -77,11 +78,18 @@ extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
   std::vector<argcsr_group_info> groups;
   rc = group_rows(n_rows, row_ptr_host, block_dim, desired_chunk_size, &groups);
   if (rc) return rc;
+  std::vector<int32_t> chunk(groups.size());
   int64_t slots = 0;
-  for (const auto& g : groups)
-    slots += int64_t(min_chunk_size(row_ptr_host, g.first_row, g.size, block_dim)) * block_dim;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    chunk[g] = min_chunk_size(row_ptr_host, groups[g].first_row, groups[g].size, block_dim);
+    slots += int64_t(chunk[g]) * block_dim;
+  }
+  const int32_t heavy_chunk = heavy_chunk_for(block_dim, slots, (int32_t)groups.size());
+  int32_t heavy = 0;
+  for (int32_t c : chunk) heavy += c > heavy_chunk;
   *n_groups = (int32_t)groups.size();
   *n_slots = slots;
+  if (n_heavy) *n_heavy = heavy;
   if (slots > INT32_MAX)
     return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", (long long)slots);
   return ARGCSR_OK;

@@ -29,11 +29,15 @@ namespace {
 template <int DT, int W, int U>
 void launch(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
   using Vt = Val<DT>;
-  const int blocks = (A->n_groups + kSpmvWaves - 1) / kSpmvWaves;
+  const bool sched = A->heavy_groups != nullptr && A->n_heavy > 0;
+  const int32_t n_heavy = sched ? A->n_heavy : 0;
+  const int32_t heavy_chunk = sched ? A->heavy_chunk : INT32_MAX;
+  const int blocks = n_heavy + (A->n_groups + kSpmvWaves - 1) / kSpmvWaves;
   argcsr_spmv_kernel<DT, W, U><<<blocks, kSpmvWaves * 64, 0, s>>>(
       A->groups, A->n_groups, A->threads_mapping, A->columns,
       static_cast<const typename Vt::storage*>(A->values),
-      static_cast<const typename Vt::acc*>(x), static_cast<typename Vt::acc*>(y));
+      static_cast<const typename Vt::acc*>(x), static_cast<typename Vt::acc*>(y),
+      A->heavy_groups, n_heavy, heavy_chunk);
 }
 
 template <int DT>
@@ -59,6 +63,10 @@ int check_matrix(const argcsr_matrix* A) {
   if (A->n_slots > INT32_MAX) return fail(ARGCSR_EOVERFLOW, "n_slots exceeds INT32_MAX");
   if (A->n_groups > 0 && (!A->groups || !A->threads_mapping || !A->columns || !A->values))
     return fail(ARGCSR_EINVAL, "NULL device buffer in matrix descriptor");
+  if (A->heavy_groups && (A->n_heavy < 0 || A->n_heavy > A->n_groups ||
+                          A->heavy_chunk != heavy_chunk_for(A->block_dim, A->n_slots,
+                                                            A->n_groups)))
+    return fail(ARGCSR_EINVAL, "heavy-group schedule does not match the matrix");
   return ARGCSR_OK;
 }
 

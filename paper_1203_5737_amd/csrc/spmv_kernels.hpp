@@ -1,69 +1,76 @@
-// Device routine for one ARG-CSR group, shared by the single-matrix kernel
-// and the batched work-queue kernel.
+// Device routines for ARG-CSR SpMV, shared by the single-matrix kernel and
+// the batched work-queue kernel (Sec. 4 semantics: chunk partial sums, then
+// per-row sums of the partial sums).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "schedule.hpp"
 #include "values.hpp"
 
 namespace argcsr {
 
-constexpr int kSpmvWaves = 4;   // waves per workgroup; each wave owns one group at a time
+// This lane's threads-mapping entries (rows l = 64*w + lane of the group).
+template <int W>
+__device__ __forceinline__ void load_mapping(int32_t first, int32_t size,
+                                             const int32_t* __restrict__ tm, int32_t (&tmv)[W]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int l = w * 64 + lane;
+    tmv[w] = l < size ? __builtin_nontemporal_load(tm + first + l) : 0;
+  }
+}
 
-// Computes the rows of one group with the calling wave (Sec. 4 semantics).
-//   W      sub-blocks per lane: the group has T = 64*W chunks
-//   U      steps j loaded ahead per sub-block (memory-level parallelism)
-//   ends   this wave's LDS table of T ints (reused group after group)
-template <int DT, int W, int U>
-__device__ __forceinline__ void spmv_group(
-    int32_t first, int32_t size, int32_t offset, int32_t c,
-    const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
-    const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
-    int32_t* ends) {
-  using Vt = Val<DT>;
-  using S = typename Vt::storage;
-  using A = typename Vt::acc;
+// Row-end bitmask of a group: bit k of word w is set iff chunk 64*w + k is
+// the last chunk of a row, i.e. k+1 == threadsMapping[l] for some row l.
+// Built through this wave's LDS table `ends` (T ints) and a ballot.
+template <int W>
+__device__ __forceinline__ void row_end_mask(const int32_t (&tmv)[W], int32_t* ends,
+                                             uint64_t (&emask)[W]) {
   constexpr int T = 64 * W;
   const int lane = lane_id();
-
-  // ---- row-end mask: chunk tm[l]-1 closes row l --------------------------
   wave_lds_sync();
 #pragma unroll
   for (int w = 0; w < W; ++w) ends[w * 64 + lane] = 0;
   wave_lds_sync();
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    const int l = w * 64 + lane;
-    if (l < size) {
-      const uint32_t e = uint32_t(tm[first + l] - 1);
-      if (e < uint32_t(T)) ends[e] = 1;
-    }
+    const uint32_t e = uint32_t(tmv[w] - 1);        // rows beyond `size` hold 0 -> skipped
+    if (e < uint32_t(T)) ends[e] = 1;
   }
   wave_lds_sync();
-  uint64_t emask[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) emask[w] = __ballot(ends[w * 64 + lane] != 0);
-  const int n_mapped = tm[first + size - 1];    // chunks in use; the rest are free
+}
 
-  // ---- chunk partial sums ---------------------------------------------------
-  A acc[W];
+// Partial sums of this lane's W chunks over steps j in [j0, j1): value *
+// x[column], stopping at a chunk's first artificial zero (column -1).
+template <int DT, int W, int U>
+__device__ __forceinline__ void chunk_partials(
+    int32_t offset, int32_t j0, int32_t j1, const int32_t* __restrict__ columns,
+    const typename Val<DT>::storage* __restrict__ values,
+    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc (&acc)[W]) {
+  using Vt = Val<DT>;
+  using S = typename Vt::storage;
+  constexpr int T = 64 * W;
+  const int lane = lane_id();
   bool alive[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) { acc[w] = A(0); alive[w] = true; }
+  for (int w = 0; w < W; ++w) { acc[w] = 0; alive[w] = true; }
   const int32_t* cb = columns + offset + lane;
   const S* vb = values + offset + lane;
-  for (int j = 0; j < c; j += U) {
+  for (int j = j0; j < j1; j += U) {
     int32_t cc[U][W];
     S vv[U][W];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        if (j + u < c) {
-          cc[u][w] = cb[(j + u) * T + w * 64];
-          vv[u][w] = vb[(j + u) * T + w * 64];
+        if (j + u < j1) {   // streamed once: keep L2 for the x gathers
+          cc[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
+          vv[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
         } else {
           cc[u][w] = -1;
           vv[u][w] = S(0);
@@ -83,8 +90,19 @@ __device__ __forceinline__ void spmv_group(
     for (int w = 0; w < W; ++w) any |= alive[w];
     if (__ballot(any) == 0) break;                // every chunk reached its padding
   }
+}
 
-  // ---- row sums: segmented scan over lanes, carried across sub-blocks ------
+// Row sums from the chunk partial sums: a segmented inclusive scan across
+// lanes (segments = rows, delimited by the row-end mask), carried from one
+// sub-block of 64 chunks to the next; the lane holding a row's last chunk
+// writes y[first + row].  Free chunks (beyond n_mapped) take no part.
+template <int DT, int W>
+__device__ __forceinline__ void row_sums(int32_t first, int32_t size, int32_t n_mapped,
+                                         const uint64_t (&emask)[W],
+                                         const typename Val<DT>::acc (&acc)[W],
+                                         typename Val<DT>::acc* __restrict__ y) {
+  using A = typename Val<DT>::acc;
+  const int lane = lane_id();
   int rows_before = 0;
   A carry = A(0);
   bool carry_on = false;
@@ -103,7 +121,7 @@ __device__ __forceinline__ void spmv_group(
     if (carry_on && below == 0) v = carry + v;
     if ((E >> lane) & 1) {
       const int row = rows_before + __popcll(below);
-      if (row < size) y[first + row] = v;
+      if (row < size) __builtin_nontemporal_store(v, y + first + row);
     }
     rows_before += __popcll(E);
     carry = __shfl(v, 63, 64);
@@ -111,17 +129,87 @@ __device__ __forceinline__ void spmv_group(
   }
 }
 
+// One whole group with the calling wave.
+template <int DT, int W, int U>
+__device__ __forceinline__ void spmv_group(
+    int32_t first, int32_t size, int32_t offset, int32_t c,
+    const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
+    const typename Val<DT>::storage* __restrict__ values,
+    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
+    int32_t* ends) {
+  using A = typename Val<DT>::acc;
+  int32_t tmv[W];
+  load_mapping<W>(first, size, tm, tmv);           // in flight with the first chunk loads
+  const int32_t n_mapped = tm[first + size - 1];    // chunks in use; the rest are free
+  A acc[W];
+  chunk_partials<DT, W, U>(offset, 0, c, columns, values, x, acc);
+  uint64_t emask[W];
+  row_end_mask<W>(tmv, ends, emask);
+  row_sums<DT, W>(first, size, n_mapped, emask, acc, y);
+}
+
+// One heavy group with all kSpmvWaves waves of the workgroup: wave q sums
+// steps [q*share, (q+1)*share); waves 1.. leave their partials in LDS and
+// wave 0 adds them in wave order (a fixed order: results are deterministic),
+// then forms the row sums.  Every wave of the block must call this.
+template <int DT, int W, int U>
+__device__ __forceinline__ void spmv_group_split(
+    int32_t first, int32_t size, int32_t offset, int32_t c,
+    const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
+    const typename Val<DT>::storage* __restrict__ values,
+    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
+    int32_t* ends, typename Val<DT>::acc (*part)[64 * W], int wv) {
+  using A = typename Val<DT>::acc;
+  const int lane = lane_id();
+  const int32_t share = (c + kSpmvWaves - 1) / kSpmvWaves;
+  const int32_t j0 = min(c, wv * share), j1 = min(c, j0 + share);
+  int32_t tmv[W];
+  load_mapping<W>(first, size, tm, tmv);
+  A acc[W];
+  chunk_partials<DT, W, U>(offset, j0, j1, columns, values, x, acc);
+  if (wv > 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) part[wv - 1][w * 64 + lane] = acc[w];
+  }
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int q = 0; q < kSpmvWaves - 1; ++q) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[w] += part[q][w * 64 + lane];
+    }
+    uint64_t emask[W];
+    row_end_mask<W>(tmv, ends, emask);
+    row_sums<DT, W>(first, size, tm[first + size - 1], emask, acc, y);
+  }
+}
+
+// Single-matrix launch: blocks [0, n_heavy) take one heavy group each (in
+// the order of `heavy`, dispatched first); the remaining blocks take
+// kSpmvWaves consecutive groups, one per wave, skipping heavy ones.
 template <int DT, int W, int U>
 __global__ __launch_bounds__(kSpmvWaves * 64) void argcsr_spmv_kernel(
     const argcsr_group_info* __restrict__ groups, int32_t n_groups,
     const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
     const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y) {
+    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
+    const int32_t* __restrict__ heavy, int32_t n_heavy, int32_t heavy_chunk) {
+  using A = typename Val<DT>::acc;
   __shared__ int32_t ends[kSpmvWaves][64 * W];
+  __shared__ A part[kSpmvWaves - 1][64 * W];
   const int wv = wave_uniform(int(threadIdx.x >> 6));
-  const int g = int(xcd_remap(blockIdx.x, gridDim.x)) * kSpmvWaves + wv;
+  const int32_t b = int32_t(blockIdx.x);
+  if (b < n_heavy) {
+    const argcsr_group_info gi = groups[heavy[b]];
+    spmv_group_split<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, tm, columns,
+                               values, x, y, ends[0], part, wv);
+    return;
+  }
+  const uint32_t nb = gridDim.x - uint32_t(n_heavy);
+  const int g = int(xcd_remap(uint32_t(b - n_heavy), nb)) * kSpmvWaves + wv;
   if (g >= n_groups) return;
   const argcsr_group_info gi = groups[g];
+  if (gi.chunk_size > heavy_chunk) return;          // processed by a heavy block
   spmv_group<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, tm, columns, values,
                        x, y, ends[wv]);
 }

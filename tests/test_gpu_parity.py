@@ -45,6 +45,11 @@ def compare_conversion(ac, A, T, D, dtype):
     gbits = gv.view(torch.int64 if dtype == 0 else torch.int32 if dtype == 1 else torch.int16)
     rbits = ref.values.view(np.int64 if dtype == 0 else np.int32 if dtype == 1 else np.int16)
     assert np.array_equal(gbits.numpy(), rbits)
+    # launch schedule: ascending indices of the groups with long chunk loops
+    want_heavy = np.nonzero(ref.groups[:, 3] > M.heavy_chunk)[0]
+    assert M.n_heavy == len(want_heavy)
+    if M.n_heavy:
+        assert np.array_equal(M.heavy_groups.cpu().numpy(), want_heavy)
     return dev, M, ref
 
 
@@ -223,6 +228,23 @@ def test_spmv_reduced_precision(ac, dtype):
             acc_err, tot_err = check_reduced(A, x, y, dtype)
             announce(f"dtype={dtype} T={T} D={D}: accumulation err {acc_err:.2e}, "
                      f"total err vs FP64 {tot_err:.2e} (x sum|ax|)")
+
+
+def test_spmv_heavy_schedule_on_and_off(ac):
+    """Long rows: split over a workgroup (schedule) or one wave each (none)."""
+    rng = np.random.default_rng(12)
+    L = rng.integers(1, 6, 20_000)
+    L[rng.integers(0, 20_000, 40)] = rng.integers(200, 10_001, 40)
+    A = synth.random_csr(L, 50_000, rng, rng)
+    x = rng.uniform(-1, 1, A.n_cols)
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    for T in (64, 128, 256):
+        M = ac.convert(dev, T, 1)
+        assert M.n_heavy > 0
+        check_f64(A, x, gpu_spmv(ac, M, x))
+        M0 = ac.convert(dev, T, 1, schedule=False)
+        assert M0.heavy_groups is None
+        check_f64(A, x, gpu_spmv(ac, M0, x))
 
 
 def test_spmv_deterministic(ac):

@@ -75,7 +75,7 @@ def plan(L, rp, T, D):
     rp = np.ascontiguousarray(rp, dtype=np.int32)
     g, s = ctypes.c_int32(0), ctypes.c_int64(0)
     rc = L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D,
-                       ctypes.byref(g), ctypes.byref(s))
+                       ctypes.byref(g), ctypes.byref(s), None)
     return rc, g.value, s.value
 
 
