@@ -152,6 +152,73 @@ def traffic_for(workload: str, dtype_name: str, T: int, D: int):
     return None
 
 
+def run_batch(args, torch, ac):
+    """256 matrices (n log-uniform in [1e3, 2e5], half U{5..50} nonzeros per
+    row, half clip(Zipf(2.2), 1, min(5000, n))), FP32 values, (T, D)
+    autotuned per matrix; a step is ONE replay of the batch's hipGraph
+    (queue reset + persistent kernel over all matrices' groups)."""
+    import synth
+    dtype = DTYPES[args.dtype]
+    count = args.batch_count
+    mats = synth.workload_batch(count)
+    vdt = ac.vector_dtype(dtype)
+    devs, Ms, xs, ys, tunes = [], [], [], [], []
+    t0 = time.perf_counter()
+    for A, x in mats:
+        d = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")
+        r = ac.autotune(d, dtype, n_finalists=3)
+        tunes.append((r["block_dim"], r["desired_chunk_size"], r["from_cache"]))
+        Ms.append(ac.convert(d, r["block_dim"], r["desired_chunk_size"], dtype))
+        devs.append(d)
+        xs.append(torch.from_numpy(x).to("cuda", vdt))
+        ys.append(torch.empty(A.n_rows, dtype=vdt, device="cuda"))
+    setup_s = time.perf_counter() - t0
+    B = sum(useful_bytes(A, dtype) for A, _ in mats)
+    nnz = sum(A.nnz for A, _ in mats)
+    batch = ac.Batch(Ms, xs, ys)
+    timer = Timer(torch, cold=not args.warm)
+    run = lambda: batch.launch(graph=True)
+    timer.run(run, args.warmup)
+    ms, wall = timer.run(run, args.steps)
+    mean_s = ms.mean() * 1e-3
+    gbps = B / mean_s / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbps, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": float(ms.mean()),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"batch of {count} matrices, n log-uniform [1e3,2e5], half U{{5..50}} "
+                               "nnz/row, half clip(Zipf(2.2),1,min(5000,n)); one hipGraph replay "
+                               "per step", "n_rows": sum(A.n_rows for A, _ in mats), "nnz": nnz,
+                   "value_dtype": args.dtype,
+                   "timing": "warm" if args.warm else "cold (1 GiB flush before each step, untimed)"},
+        "roofline": {"bound": "hbm", "achieved": round(gbps, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None},
+        "spmv": stats(ms) | {"gflops": 2 * nnz / mean_s / 1e9, "useful_bytes": B,
+                             "wall_ms_per_step": wall * 1e3 / args.steps} | batch.info(),
+        "setup_s": setup_s,
+        "tuned": {f"T{T}/D{D}": sum(1 for t in tunes if t[:2] == (T, D))
+                  for T, D in sorted({t[:2] for t in tunes})},
+        "kernel_hash": kernel_source_hash(),
+    }
+    if not args.no_extras:
+        loop = lambda: [ac.spmv(M, x, y) for M, x, y in zip(Ms, xs, ys)]
+        timer.run(loop, 2)
+        t, _ = timer.run(loop, max(5, args.steps // 4))
+        out["single_launch_loop"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
+        direct = lambda: batch.launch(graph=False)
+        t, _ = timer.run(direct, max(5, args.steps // 4))
+        out["batch_direct_launch"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
+        vals = [d.val.to(ac.storage_dtype(dtype)) if dtype != 0 else d.val for d in devs]
+        csr = lambda: [ac.csr_spmv(d, x, y, values=v, dtype=dtype) for d, x, y, v in zip(devs, xs, ys, vals)]
+        timer.run(csr, 2)
+        t, _ = timer.run(csr, max(5, args.steps // 4))
+        out["csr_loop"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
+        out["speedup_vs_csr_loop"] = out["csr_loop"]["mean_ms"] / float(ms.mean())
+    batch.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +231,7 @@ def main():
     ap.add_argument("--warm", action="store_true", help="no cache flush between steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the CSR and warm timings")
+    ap.add_argument("--batch-count", type=int, default=256)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -177,6 +245,10 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     ac._lib.lib()                                    # fails loudly if not built
+    if args.workload == "batch":
+        if args.dtype == "f64" and "--dtype" not in sys.argv:
+            args.dtype = "f32"                        # the batch workload is quoted in FP32
+        return run_batch(args, torch, ac)
     dtype = DTYPES[args.dtype]
     T0, D0 = DEFAULT_PARAMS.get(args.workload, (64, 1))
     T = args.block_dim or T0

@@ -170,6 +170,75 @@ int argcsr_csr_spmv(int32_t n_rows, int32_t n_cols, int64_t nnz,
                     int32_t dtype, int32_t lanes_per_row, const void* x, void* y,
                     void* stream);
 
+/* ---- many matrices in one launch -------------------------------------- */
+
+/* Opaque batch: device-side descriptors of several converted matrices and a
+ * work list of their row groups, library-owned (free with
+ * argcsr_batch_destroy). */
+typedef struct argcsr_batch argcsr_batch;
+
+/*
+ * argcsr_batch_create -- prepares y_m = A_m x_m for m = 0..n_mats-1 as ONE
+ * persistent kernel over a global queue of (matrix, group) work items
+ * (groups with long chunk loops go to whole workgroups first, the others to
+ * single waves in matrix and row order), and captures [queue reset, kernel] in a
+ * hipGraph.  The same per-group computation as argcsr_spmv is used, so each
+ * y_m is bitwise identical to argcsr_spmv on A_m alone.
+ *   mats   host array of n_mats converted matrices, all of one dtype; block
+ *          dims may differ (64, 128, 256)
+ *   xs, ys host arrays of n_mats device pointers (x_m, y_m as for
+ *          argcsr_spmv); the pointers are baked into the graph: later runs
+ *          read the same x buffers and write the same y buffers
+ * Synchronous (copies the group tables to the host to build the work list).
+ * Errors: EINVAL (mixed dtypes, NULL pointers), EUNSUPPORTED, EHIP, ENOMEM.
+ */
+int argcsr_batch_create(int32_t n_mats, const argcsr_matrix* mats, const void* const* xs,
+                        void* const* ys, argcsr_batch** out);
+
+/* Runs the batch on `stream` by replaying its hipGraph (asynchronous). */
+int argcsr_batch_graph_launch(argcsr_batch* b, void* stream);
+
+/* Runs the batch on `stream` with ordinary kernel launches (asynchronous). */
+int argcsr_batch_launch(argcsr_batch* b, void* stream);
+
+/* Work-list sizes and persistent grid of a batch (any pointer may be NULL). */
+int argcsr_batch_info(const argcsr_batch* b, int32_t* n_items, int32_t* n_heavy, int32_t* grid);
+
+/* Waits for the device, then frees the batch (NULL is a no-op). */
+int argcsr_batch_destroy(argcsr_batch* b);
+
+/* ---- parameter choice --------------------------------------------------- */
+
+typedef struct {
+  int32_t block_dim;           /* chosen T */
+  int32_t desired_chunk_size;  /* chosen D */
+  double model_us;             /* cost-model estimate of one SpMV */
+  double measured_us;          /* mean of timed SpMVs (warm caches); < 0 if not timed */
+  int32_t from_cache;          /* 1 if the choice came from the process cache */
+  int32_t n_candidates;        /* (T, D) pairs planned */
+  int32_t n_timed;             /* candidates converted and timed */
+} argcsr_tune_result;
+
+/*
+ * argcsr_autotune -- picks (block_dim, desired_chunk_size) for a matrix.
+ * The paper makes desiredChunkSize the key, matrix-dependent parameter and
+ * block size 128 its best on its GPU (Sec. 5).  Every pair in {64,128,256} x
+ * {1,2,4,8,16,32,64} is sized with argcsr_plan, ranked by a cost model
+ * (padded bytes, group count, long groups), and the best n_finalists are
+ * converted and timed on `stream`.  The choice is cached for the process
+ * under a signature of the row-length distribution.
+ *   arguments as for argcsr_convert; dtype is the value storage type
+ *   n_finalists  candidates to time (0: model only)
+ * Synchronous; allocates and frees temporary device memory.
+ * Errors: EINVAL, ENOMEM, EHIP, EOVERFLOW.
+ */
+int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                    const int32_t* row_ptr, const int32_t* col, const double* val, int32_t dtype,
+                    int32_t n_finalists, argcsr_tune_result* out, void* stream);
+
+/* Forgets all cached autotune choices. */
+int argcsr_autotune_clear_cache(void);
+
 #ifdef __cplusplus
 }
 #endif

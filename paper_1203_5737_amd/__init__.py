@@ -18,11 +18,11 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import (BF16, F16, F32, F64, ArgCsrError, MatrixDesc, check, lib)
+from ._lib import (BF16, F16, F32, F64, ArgCsrError, MatrixDesc, TuneResult, check, lib)
 
 __all__ = ["F64", "F32", "BF16", "F16", "ArgCsrError", "ArgCsrMatrix", "DeviceCsr",
            "plan", "convert", "spmv", "csr_spmv", "to_device_csr", "storage_dtype",
-           "vector_dtype"]
+           "vector_dtype", "Batch", "autotune", "autotune_clear_cache"]
 
 _STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}
 
@@ -175,3 +175,62 @@ def csr_spmv(A: DeviceCsr, x: torch.Tensor, y: Optional[torch.Tensor] = None,
                                 _ptr(vals), int(dtype), int(lanes_per_row), _ptr(x), _ptr(y),
                                 _stream(stream)), "argcsr_csr_spmv")
     return y
+
+
+class Batch:
+    """Several converted matrices computed by one persistent launch
+    (argcsr_batch_create); y_m = A_m x_m for every member.  The x and y
+    tensors are bound at creation and must stay alive (the batch keeps
+    references)."""
+
+    def __init__(self, mats, xs, ys):
+        if not (len(mats) == len(xs) == len(ys)) or not mats:
+            raise ValueError("mats, xs and ys must be non-empty and of equal length")
+        for A, x, y in zip(mats, xs, ys):
+            want = vector_dtype(A.dtype)
+            if x.dtype != want or y.dtype != want or x.numel() != A.n_cols or y.numel() != A.n_rows:
+                raise ValueError("x/y do not match their matrix")
+        self._keep = (list(mats), list(xs), list(ys))
+        n = len(mats)
+        descs = (MatrixDesc * n)(*[A.desc() for A in mats])
+        xp = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        yp = (ctypes.c_void_p * n)(*[_ptr(y).value for y in ys])
+        self._h = ctypes.c_void_p(0)
+        check(lib().argcsr_batch_create(n, descs, xp, yp, ctypes.byref(self._h)),
+              "argcsr_batch_create")
+
+    def launch(self, stream=None, graph: bool = True) -> None:
+        fn = lib().argcsr_batch_graph_launch if graph else lib().argcsr_batch_launch
+        check(fn(self._h, _stream(stream)), "argcsr_batch_launch")
+
+    def info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().argcsr_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "argcsr_batch_info")
+        return {"n_items": a.value, "n_heavy": b.value, "grid": c.value}
+
+    def close(self) -> None:
+        if self._h:
+            check(lib().argcsr_batch_destroy(self._h), "argcsr_batch_destroy")
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(A: DeviceCsr, dtype: int = F64, n_finalists: int = 4, stream=None) -> dict:
+    """(block_dim, desired_chunk_size) for A (argcsr_autotune)."""
+    r = TuneResult()
+    check(lib().argcsr_autotune(A.n_rows, A.n_cols, A.row_ptr_host.ctypes.data_as(ctypes.c_void_p),
+                                _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), int(dtype),
+                                int(n_finalists), ctypes.byref(r),
+                                _stream(stream) if n_finalists > 0 else ctypes.c_void_p(0)),
+          "argcsr_autotune")
+    return {k: getattr(r, k) for k, _ in TuneResult._fields_}
+
+
+def autotune_clear_cache() -> None:
+    check(lib().argcsr_autotune_clear_cache(), "argcsr_autotune_clear_cache")

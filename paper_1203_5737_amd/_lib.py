@@ -41,8 +41,16 @@ class MatrixDesc(ctypes.Structure):
                 ("heavy_groups", ctypes.c_void_p)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("block_dim", ctypes.c_int32), ("desired_chunk_size", ctypes.c_int32),
+                ("model_us", ctypes.c_double), ("measured_us", ctypes.c_double),
+                ("from_cache", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("n_timed", ctypes.c_int32)]
+
+
 _lib = None
 i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+pi32 = ctypes.POINTER(i32)
 
 SIGNATURES = {
     "argcsr_last_error": (ctypes.c_char_p, []),
@@ -52,6 +60,15 @@ SIGNATURES = {
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),
     "argcsr_csr_spmv": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, vp, vp, vp]),
+    "argcsr_batch_create": (ctypes.c_int, [i32, ctypes.POINTER(MatrixDesc), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+    "argcsr_batch_graph_launch": (ctypes.c_int, [vp, vp]),
+    "argcsr_batch_launch": (ctypes.c_int, [vp, vp]),
+    "argcsr_batch_info": (ctypes.c_int, [vp, pi32, pi32, pi32]),
+    "argcsr_batch_destroy": (ctypes.c_int, [vp]),
+    "argcsr_autotune": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, i32, i32,
+                                       ctypes.POINTER(TuneResult), vp]),
+    "argcsr_autotune_clear_cache": (ctypes.c_int, []),
 }
 
 

@@ -22,6 +22,8 @@ SOURCES = [
     "convert.hip",
     "spmv.hip",
     "csr_spmv.hip",
+    "batch.hip",
+    "tune.cpp",
 ]
 
 ARCH = "gfx950"

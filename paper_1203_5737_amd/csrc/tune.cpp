@@ -1,0 +1,197 @@
+// Autotuner for the conversion parameters (block_dim T, desired_chunk_size D).
+//
+// The paper finds D decisive and matrix dependent: larger D for regular
+// matrices, D = 1 as the robust default (Sec. 5).  Here every (T, D) in
+// {64,128,256} x {1,2,4,...,64} is planned on the host (steps 1-2 give the
+// group count, slot count and heavy-group count exactly), ranked by a cost
+// model, and the best `n_finalists` are converted and timed on the device.
+// Choices are cached per process under a signature of the row-length
+// distribution, so matrices of the same shape are tuned once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "plan.hpp"
+#include "schedule.hpp"
+
+namespace argcsr {
+namespace {
+
+constexpr int32_t kBlockDims[] = {64, 128, 256};
+constexpr int32_t kDesired[] = {1, 2, 4, 8, 16, 32, 64};
+constexpr int kTimedReps = 10;
+
+// Cost model, in microseconds on MI355X: streamed bytes at a sustained
+// 5 TB/s, plus a per-group cost (metadata and row-sum latency shared by the
+// resident waves), plus a per-heavy-group workgroup cost.
+constexpr double kStreamBytesPerUs = 5.0e6;
+constexpr double kUsPerGroup = 4.0e-4;
+constexpr double kUsPerHeavy = 2.0e-3;
+
+struct Candidate {
+  int32_t T, D, G, heavy;
+  int64_t S;
+  double model_us;
+  double measured_us;
+};
+
+std::mutex g_cache_mutex;
+std::map<std::string, argcsr_tune_result> g_cache;
+
+int value_bytes(int32_t dtype) {
+  return dtype == ARGCSR_F64 ? 8 : dtype == ARGCSR_F32 ? 4 : 2;
+}
+
+// dtype, log2 of n and nnz, and the share of rows in each power-of-two
+// row-length bucket (quantised to 1/32).
+std::string signature(int32_t n_rows, const int32_t* rp, int32_t dtype) {
+  int64_t hist[33] = {0};
+  for (int32_t r = 0; r < n_rows; ++r) {
+    const int64_t L = int64_t(rp[r + 1]) - rp[r];
+    int b = 0;
+    while (b < 32 && (int64_t(1) << b) <= L) ++b;
+    hist[b]++;
+  }
+  const int64_t nnz = n_rows > 0 ? rp[n_rows] : 0;
+  std::string key = std::to_string(dtype) + ":" +
+                    std::to_string(int(std::log2(double(n_rows) + 1.0))) + ":" +
+                    std::to_string(int(std::log2(double(nnz) + 1.0)));
+  for (int b = 0; b < 33; ++b) {
+    const int q = n_rows > 0 ? int(std::lround(32.0 * double(hist[b]) / double(n_rows))) : 0;
+    key += "," + std::to_string(hist[b] > 0 ? std::max(q, 1) : 0);
+  }
+  return key;
+}
+
+struct DeviceBuffers {
+  argcsr_matrix m{};
+  void* mem[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  ~DeviceBuffers() {
+    for (void* p : mem)
+      if (p) (void)hipFree(p);
+  }
+};
+
+int time_candidate(int32_t n_rows, int32_t n_cols, const int32_t* rp_host, const int32_t* rp,
+                   const int32_t* col, const double* val, int32_t dtype, Candidate* c,
+                   void* x, void* y, hipStream_t s) {
+  DeviceBuffers b;
+  argcsr_matrix& m = b.m;
+  m.n_rows = n_rows;
+  m.n_cols = n_cols;
+  m.block_dim = c->T;
+  m.desired_chunk_size = c->D;
+  m.dtype = dtype;
+  m.n_groups = c->G;
+  m.n_slots = c->S;
+  m.n_heavy = c->heavy;
+  const size_t sizes[5] = {sizeof(argcsr_group_info) * size_t(c->G), sizeof(int32_t) * size_t(n_rows),
+                           sizeof(int32_t) * size_t(c->S), size_t(value_bytes(dtype)) * size_t(c->S),
+                           sizeof(int32_t) * size_t(c->heavy)};
+  for (int i = 0; i < 5; ++i)
+    if (sizes[i] && hipMalloc(&b.mem[i], sizes[i]) != hipSuccess)
+      return fail(ARGCSR_ENOMEM, "autotune: device allocation of %zu bytes failed", sizes[i]);
+  m.groups = static_cast<argcsr_group_info*>(b.mem[0]);
+  m.threads_mapping = static_cast<int32_t*>(b.mem[1]);
+  m.columns = static_cast<int32_t*>(b.mem[2]);
+  m.values = b.mem[3];
+  m.heavy_groups = static_cast<int32_t*>(b.mem[4]);
+  int rc = argcsr_convert(n_rows, n_cols, rp_host, rp, col, val, &m, s);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  ARGCSR_HIP(hipEventCreate(&e0));
+  ARGCSR_HIP(hipEventCreate(&e1));
+  for (int i = 0; i < 3 && rc == ARGCSR_OK; ++i) rc = argcsr_spmv(&m, x, y, s);
+  if (rc == ARGCSR_OK && hipEventRecord(e0, s) != hipSuccess) rc = ARGCSR_EHIP;
+  for (int i = 0; i < kTimedReps && rc == ARGCSR_OK; ++i) rc = argcsr_spmv(&m, x, y, s);
+  float ms = 0.f;
+  if (rc == ARGCSR_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = fail(ARGCSR_EHIP, "autotune: event timing failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->measured_us = 1e3 * double(ms) / kTimedReps;
+  return rc;
+}
+
+}  // namespace
+}  // namespace argcsr
+
+extern "C" int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                               const int32_t* row_ptr, const int32_t* col, const double* val,
+                               int32_t dtype, int32_t n_finalists, argcsr_tune_result* out,
+                               void* stream) {
+  using namespace argcsr;
+  clear_error();
+  if (!out) return fail(ARGCSR_EINVAL, "out is NULL");
+  if (dtype < ARGCSR_F64 || dtype > ARGCSR_F16) return fail(ARGCSR_EINVAL, "unknown dtype %d", dtype);
+  int rc = check_row_ptr(n_rows, row_ptr_host);
+  if (rc) return rc;
+  const std::string key = signature(n_rows, row_ptr_host, dtype);
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mutex);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      *out = it->second;
+      out->from_cache = 1;
+      return ARGCSR_OK;
+    }
+  }
+  const int sv = value_bytes(dtype), sx = dtype == ARGCSR_F64 ? 8 : 4;
+  std::vector<Candidate> cands;
+  for (int32_t T : kBlockDims) {
+    for (int32_t D : kDesired) {
+      int32_t G = 0, H = 0;
+      int64_t S = 0;
+      if (argcsr_plan(n_rows, row_ptr_host, T, D, &G, &S, &H) != ARGCSR_OK) continue;
+      const double bytes = double(S) * (sv + 4) + 16.0 * G + double(n_rows) * (4 + sx);
+      cands.push_back(Candidate{T, D, G, H, S,
+                                bytes / kStreamBytesPerUs + kUsPerGroup * G + kUsPerHeavy * H, -1.0});
+    }
+  }
+  clear_error();
+  if (cands.empty()) return fail(ARGCSR_EOVERFLOW, "no (block_dim, desired_chunk_size) fits int32");
+  std::stable_sort(cands.begin(), cands.end(),
+                   [](const Candidate& a, const Candidate& b) { return a.model_us < b.model_us; });
+  const int n_time = std::max(0, std::min<int>(n_finalists, int(cands.size())));
+  int best = 0;
+  if (n_time > 0 && n_rows > 0) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* x = nullptr;
+    void* y = nullptr;
+    if (hipMalloc(&x, size_t(sx) * std::max(n_cols, 1)) != hipSuccess ||
+        hipMalloc(&y, size_t(sx) * std::max(n_rows, 1)) != hipSuccess) {
+      if (x) (void)hipFree(x);
+      return fail(ARGCSR_ENOMEM, "autotune: vector allocation failed");
+    }
+    // x = 0: timing does not depend on the values
+    rc = hipMemsetAsync(x, 0, size_t(sx) * std::max(n_cols, 1), s) == hipSuccess ? ARGCSR_OK
+                                                                           : ARGCSR_EHIP;
+    for (int i = 0; i < n_time && rc == ARGCSR_OK; ++i)
+      rc = time_candidate(n_rows, n_cols, row_ptr_host, row_ptr, col, val, dtype, &cands[i], x, y, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    if (rc) return rc;
+    for (int i = 1; i < n_time; ++i)
+      if (cands[i].measured_us < cands[best].measured_us) best = i;
+  }
+  const Candidate& c = cands[best];
+  *out = argcsr_tune_result{c.T, c.D, c.model_us, c.measured_us, 0, int32_t(cands.size()), n_time};
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  g_cache[key] = *out;
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_autotune_clear_cache(void) {
+  std::lock_guard<std::mutex> lock(argcsr::g_cache_mutex);
+  argcsr::g_cache.clear();
+  return ARGCSR_OK;
+}

@@ -122,3 +122,50 @@ def test_gpu_entry_points_reject_bad_arguments_without_gpu(L):
     assert L.argcsr_spmv(ctypes.byref(d), None, None, None) == _lib.EINVAL
     assert L.argcsr_spmv(None, None, None, None) == _lib.EINVAL
     assert L.argcsr_csr_spmv(4, 4, 4, None, None, None, 0, 3, None, None, None) == _lib.EINVAL
+
+
+def heavy_chunk_for(T, S, G):
+    """The launch-schedule threshold (documented with argcsr_matrix.heavy_groups):
+    at least 4 rounds of 8 loaded steps per lane, and 4x the mean chunk size."""
+    by_rounds = {64: 32, 128: 16, 256: 8}.get(T)
+    if by_rounds is None or G == 0:
+        return by_rounds
+    return max(by_rounds, 4 * (-(-S // (G * T))))
+
+
+def test_plan_heavy_count_matches_oracle_groups(L, ora):
+    Ap, _ = synth.workload_powerlaw(200_000)
+    A2, _ = synth.workload_stencil27(16)
+    for A, T, D in [(Ap, 64, 1), (Ap, 128, 2), (Ap, 256, 1), (A2, 256, 27), (A2, 64, 1)]:
+        rp = np.ascontiguousarray(A.rp, dtype=np.int32)
+        g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
+        assert L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D,
+                             ctypes.byref(g), ctypes.byref(s), ctypes.byref(h)) == 0
+        ref = ora.convert(A.rp, A.col, A.val, T, D)
+        hc = heavy_chunk_for(T, ref.n_slots, ref.n_groups)
+        assert h.value == int((ref.groups[:, 3] > hc).sum())
+
+
+def test_autotune_model_ranking_on_host(L, ora):
+    """With no finalists timed the autotuner returns the cost model's best
+    pair; recompute the model from the oracle's sizes and compare."""
+    import paper_1203_5737_amd as ac
+    ac.autotune_clear_cache()
+    for A, dt in [(synth.workload_powerlaw(100_000)[0], ac.F64),
+                  (synth.workload_laplace64()[0], ac.F32)]:
+        d = ac.DeviceCsr(A.n_rows, A.n_cols, A.rp, None, None, None)
+        r = ac.autotune(d, dt, n_finalists=0)
+        sv, sx = (8, 8) if dt == ac.F64 else (4, 4)
+        best = None
+        for T in (64, 128, 256):
+            for D in (1, 2, 4, 8, 16, 32, 64):
+                rc, G, S = ora.sizes(A.rp, T, D)
+                ref = ora.convert(A.rp, A.col, A.val, T, D)
+                H = int((ref.groups[:, 3] > heavy_chunk_for(T, S, G)).sum())
+                model = (S * (sv + 4) + 16 * G + A.n_rows * (4 + sx)) / 5e6 + 4e-4 * G + 2e-3 * H
+                if best is None or model < best[0]:
+                    best = (model, T, D)
+        assert (r["block_dim"], r["desired_chunk_size"]) == best[1:]
+        assert abs(r["model_us"] - best[0]) < 1e-9 * max(1.0, best[0])
+        assert r["n_candidates"] == 21 and r["n_timed"] == 0 and r["from_cache"] == 0
+        assert ac.autotune(d, dt, n_finalists=0)["from_cache"] == 1
