@@ -37,6 +37,8 @@ extern "C" {
 #define ARGCSR_EBUSY      (-6)  /* no free slot; retry later               */
 #define ARGCSR_ENOTFOUND  (-7)  /* unknown handle, id or ticket            */
 #define ARGCSR_EUNSUPPORTED (-8) /* valid, but not supported on the GPU    */
+#define ARGCSR_ENOCONV    (-9)  /* CG stopped at its iteration limit       */
+#define ARGCSR_PENDING     1    /* request status: not finished yet        */
 
 /* ---- value storage types ------------------------------------------------ */
 /* FP64 stores FP64 values and takes FP64 x, y.  The reduced types store
@@ -238,6 +240,87 @@ int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
 
 /* Forgets all cached autotune choices. */
 int argcsr_autotune_clear_cache(void);
+
+/* ---- serving ----------------------------------------------------------- */
+
+/* A request server: converted matrices stay resident on one GPU inside a
+ * device arena of budget_bytes; SpMV and CG-solve requests are batched
+ * continuously (every scheduler step advances all active requests; new ones
+ * join as slots and memory free up).  Library-owned; one scheduler thread per
+ * server.  Results of a request do not depend on the other requests in
+ * flight (no shared reductions). */
+typedef struct argcsr_server argcsr_server;
+
+typedef struct {
+  int64_t budget_bytes;        /* device arena: resident matrices + request vectors */
+  int32_t max_active;          /* requests advanced together, 1..512 */
+  int32_t device;              /* HIP device ordinal */
+  int32_t block_dim;           /* conversion T: 0 (= 64), 64, 128 or 256 */
+  int32_t desired_chunk_size;  /* conversion D: 0 = mean row length in [1, 64] */
+  double cg_tol;               /* CG stops when |b - A x| <= cg_tol |b| (FP64 A) */
+  double cg_inner_tol;         /* residual reduction of one FP32-matrix inner cycle */
+  int32_t cg_max_inner;        /* inner iterations per refinement cycle */
+  int32_t cg_max_iter;         /* inner iterations per solve; then ARGCSR_ENOCONV */
+} argcsr_server_config;
+
+typedef enum {
+  ARGCSR_REQ_ADMIT = 0,  /* make matrix_id resident from host CSR (n_rows, n_cols,
+                            row_ptr, col, val); a no-op if it already is */
+  ARGCSR_REQ_SPMV = 1,   /* out[n_rows] (float) = A in[n_cols] (float), FP32 values */
+  ARGCSR_REQ_CG = 2,     /* out[n] (double) = x with A x = in (double b[n]), A SPD */
+  ARGCSR_REQ_EVICT = 3   /* drop matrix_id (EBUSY while requests use it) */
+} argcsr_request_kind;
+
+typedef struct {
+  int32_t kind;                /* argcsr_request_kind */
+  int32_t n_rows, n_cols;      /* ADMIT */
+  int64_t matrix_id;
+  const int32_t* row_ptr;      /* ADMIT, host, valid until the request completes */
+  const int32_t* col;
+  const double* val;
+  const void* in;              /* SPMV / CG input, host, valid until completion */
+  void* out;                   /* SPMV / CG output, host */
+} argcsr_request;
+
+typedef struct {
+  int32_t status;              /* ARGCSR_PENDING, ARGCSR_OK or an error code */
+  int32_t iterations;          /* CG: inner iterations (FP32 matrix) */
+  int32_t refinements;         /* CG: outer residual evaluations (FP64 matrix) */
+  int32_t reserved;
+  double relres;               /* CG: final |b - A x| / |b| with the FP64 matrix */
+  int64_t t_submit_ns, t_start_ns, t_done_ns;   /* steady clock */
+} argcsr_result;
+
+typedef struct {
+  int64_t submitted, completed, failed;   /* SPMV + CG requests */
+  int64_t admissions, evictions, steps;
+  int64_t resident_matrices, resident_bytes, arena_bytes;
+} argcsr_server_stats;
+
+/* Creates a server and starts its scheduler thread.  Allocates the arena
+ * (budget_bytes of device memory) up front.  Errors: EINVAL, ENOMEM, EHIP. */
+int argcsr_server_create(const argcsr_server_config* cfg, argcsr_server** out);
+
+/* Queues a request (thread-safe, non-blocking) and returns its ticket.
+ * Requests are taken in submission order; an SPMV/CG request for a matrix
+ * that is not resident when it is started fails with ENOTFOUND.  A matrix
+ * with queued or active requests is never evicted. */
+int argcsr_server_submit(argcsr_server* s, const argcsr_request* r, uint64_t* ticket);
+
+/* Current result of a ticket (status ARGCSR_PENDING while in flight). */
+int argcsr_server_poll(argcsr_server* s, uint64_t ticket, argcsr_result* res);
+
+/* Blocks until the ticket finishes or timeout_ns passes (EBUSY). */
+int argcsr_server_wait(argcsr_server* s, uint64_t ticket, int64_t timeout_ns, argcsr_result* res);
+
+/* Forgets a finished ticket's result. */
+int argcsr_server_release(argcsr_server* s, uint64_t ticket);
+
+int argcsr_server_get_stats(argcsr_server* s, argcsr_server_stats* out);
+
+/* Stops the scheduler (requests still queued fail with ENOTFOUND) and frees
+ * the server. */
+int argcsr_server_destroy(argcsr_server* s);
 
 #ifdef __cplusplus
 }

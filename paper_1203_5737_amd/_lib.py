@@ -11,12 +11,15 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libargcsr.so")
 
-OK, EINVAL, EOVERFLOW, ENOMEM, EHIP, EBUDGET, EBUSY, ENOTFOUND, EUNSUPPORTED = (
-    0, -1, -2, -3, -4, -5, -6, -7, -8)
+OK, EINVAL, EOVERFLOW, ENOMEM, EHIP, EBUDGET, EBUSY, ENOTFOUND, EUNSUPPORTED, ENOCONV = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+PENDING = 1
+REQ_ADMIT, REQ_SPMV, REQ_CG, REQ_EVICT = 0, 1, 2, 3
 F64, F32, BF16, F16 = 0, 1, 2, 3
 
 _NAMES = {OK: "OK", EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EHIP: "EHIP",
-          EBUDGET: "EBUDGET", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND", EUNSUPPORTED: "EUNSUPPORTED"}
+          EBUDGET: "EBUDGET", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND", EUNSUPPORTED: "EUNSUPPORTED",
+          ENOCONV: "ENOCONV"}
 
 
 class ArgCsrError(RuntimeError):
@@ -48,6 +51,34 @@ class TuneResult(ctypes.Structure):
                 ("n_timed", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("block_dim", ctypes.c_int32),
+                ("desired_chunk_size", ctypes.c_int32), ("cg_tol", ctypes.c_double),
+                ("cg_inner_tol", ctypes.c_double), ("cg_max_inner", ctypes.c_int32),
+                ("cg_max_iter", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("matrix_id", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("t_submit_ns", ctypes.c_int64),
+                ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "completed", "failed", "admissions", "evictions", "steps",
+        "resident_matrices", "resident_bytes", "arena_bytes")]
+
+
 _lib = None
 i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
 pi32 = ctypes.POINTER(i32)
@@ -69,6 +100,14 @@ SIGNATURES = {
     "argcsr_autotune": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, i32, i32,
                                        ctypes.POINTER(TuneResult), vp]),
     "argcsr_autotune_clear_cache": (ctypes.c_int, []),
+    "argcsr_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
+    "argcsr_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(Request),
+                                            ctypes.POINTER(ctypes.c_uint64)]),
+    "argcsr_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "argcsr_server_wait": (ctypes.c_int, [vp, ctypes.c_uint64, i64, ctypes.POINTER(Result)]),
+    "argcsr_server_release": (ctypes.c_int, [vp, ctypes.c_uint64]),
+    "argcsr_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
+    "argcsr_server_destroy": (ctypes.c_int, [vp]),
 }
 
 

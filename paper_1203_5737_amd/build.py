@@ -24,6 +24,7 @@ SOURCES = [
     "csr_spmv.hip",
     "batch.hip",
     "tune.cpp",
+    "serve.hip",
 ]
 
 ARCH = "gfx950"

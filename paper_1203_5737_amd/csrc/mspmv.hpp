@@ -1,0 +1,144 @@
+// y_m = A_m x_m for a set of matrices in ONE persistent launch, driven by
+// per-matrix prefix tables instead of a per-group work list: work item i of
+// the normal queue is group i - group_begin[m] of the matrix m with
+// group_begin[m] <= i < group_begin[m+1]; heavy item h is
+// heavy_groups_m[h - heavy_begin[m]].  The prefix tables are staged in LDS
+// once per workgroup and searched there.  Used by the serving loop, whose
+// set of matrices changes from step to step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "schedule.hpp"
+#include "spmv_kernels.hpp"
+
+namespace argcsr {
+
+constexpr int kMaxLaunchMats = 512;   // matrices per multi-matrix launch
+constexpr int kMspmvGrab = 4;         // normal items taken per queue access
+
+struct MatWork {
+  const argcsr_group_info* groups;
+  const int32_t* tm;
+  const int32_t* columns;
+  const void* values;
+  const int32_t* heavy;               // heavy group indices (may be NULL if n_heavy == 0)
+  const void* x;
+  void* y;
+  int32_t block_dim;
+  int32_t heavy_chunk;                // groups with chunk_size above are in `heavy`
+  int32_t group_begin;                // prefix over the launch's matrices
+  int32_t heavy_begin;
+};
+
+struct LaunchQueue {
+  int32_t heavy_next;
+  int32_t normal_next;
+};
+
+__global__ void reset_launch_queue_kernel(LaunchQueue* q, int32_t count) {
+  const int32_t i = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < count) {
+    q[i].heavy_next = 0;
+    q[i].normal_next = 0;
+  }
+}
+
+// largest m in [0, n) with begin[m] <= i (begin[0] == 0, begin non-decreasing)
+__device__ __forceinline__ int32_t find_owner(const int32_t* begin, int32_t n, int32_t i) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
+    const MatWork* __restrict__ mw, int32_t n_mats, int32_t total_groups, int32_t total_heavy,
+    LaunchQueue* q) {
+  using Vt = Val<DT>;
+  using S = typename Vt::storage;
+  using A = typename Vt::acc;
+  __shared__ int32_t gbeg[kMaxLaunchMats];
+  __shared__ int32_t hbeg[kMaxLaunchMats];
+  __shared__ int32_t ends[kSpmvWaves][256];
+  __shared__ A part_mem[(kSpmvWaves - 1) * 256];
+  __shared__ int32_t grabbed;
+  for (int32_t m = threadIdx.x; m < n_mats; m += blockDim.x) {
+    gbeg[m] = mw[m].group_begin;
+    hbeg[m] = mw[m].heavy_begin;
+  }
+  __syncthreads();
+  const int wv = wave_uniform(int(threadIdx.x >> 6));
+  const int lane = lane_id();
+
+  for (;;) {                                        // heavy groups, whole workgroup
+    if (threadIdx.x == 0) grabbed = atomicAdd(&q->heavy_next, 1);
+    __syncthreads();
+    const int32_t h = grabbed;
+    __syncthreads();
+    if (h >= total_heavy) break;
+    const int32_t m = find_owner(hbeg, n_mats, h);
+    const MatWork& w = mw[m];
+    const argcsr_group_info gi = w.groups[w.heavy[h - hbeg[m]]];
+    const S* vals = static_cast<const S*>(w.values);
+    const A* x = static_cast<const A*>(w.x);
+    A* y = static_cast<A*>(w.y);
+    switch (w.block_dim) {
+      case 64:
+        spmv_group_split<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
+                                   w.columns, vals, x, y, ends[0],
+                                   reinterpret_cast<A(*)[64]>(part_mem), wv);
+        break;
+      case 128:
+        spmv_group_split<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
+                                   w.columns, vals, x, y, ends[0],
+                                   reinterpret_cast<A(*)[128]>(part_mem), wv);
+        break;
+      default:
+        spmv_group_split<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
+                                   w.columns, vals, x, y, ends[0],
+                                   reinterpret_cast<A(*)[256]>(part_mem), wv);
+        break;
+    }
+    __syncthreads();
+  }
+
+  for (;;) {                                        // all other groups, one wave each
+    int32_t i0 = 0;
+    if (lane == 0) i0 = atomicAdd(&q->normal_next, kMspmvGrab);
+    i0 = wave_uniform(__shfl(i0, 0, 64));
+    if (i0 >= total_groups) break;
+    const int32_t i1 = min(i0 + kMspmvGrab, total_groups);
+    int32_t m = find_owner(gbeg, n_mats, i0);
+    for (int32_t i = i0; i < i1; ++i) {
+      while (m + 1 < n_mats && gbeg[m + 1] <= i) ++m;
+      const MatWork& w = mw[m];
+      const argcsr_group_info gi = w.groups[i - gbeg[m]];
+      if (gi.chunk_size > w.heavy_chunk) continue;     // done by a heavy workgroup
+      const S* vals = static_cast<const S*>(w.values);
+      const A* x = static_cast<const A*>(w.x);
+      A* y = static_cast<A*>(w.y);
+      switch (w.block_dim) {
+        case 64:
+          spmv_group<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                               vals, x, y, ends[wv]);
+          break;
+        case 128:
+          spmv_group<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                               vals, x, y, ends[wv]);
+          break;
+        default:
+          spmv_group<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                               vals, x, y, ends[wv]);
+          break;
+      }
+    }
+  }
+}
+
+}  // namespace argcsr

@@ -1,0 +1,765 @@
+// Serving loop: device-resident ARG-CSR matrices admitted under a memory
+// budget, and continuous batching of SpMV and CG-solve requests.
+//
+// One scheduler thread owns all device work (one stream).  Clients submit
+// requests into a queue and poll or wait on tickets.  Each scheduler step:
+//   1. takes queued requests in order: ADMIT converts a matrix and keeps it
+//      resident (evicting least-recently-used idle matrices if the budget is
+//      short); SPMV/CG requests enter free slots as slots and memory allow;
+//   2. advances every active request by one step in a few launches for all
+//      of them together: one multi-matrix ARG-CSR SpMV per precision (FP32
+//      values for SpMV requests and inner CG iterations, FP64 values for the
+//      outer residual of CG), then the CG vector kernels;
+//   3. reads back the per-request scalars, retires finished requests and
+//      copies their results to the caller's host memory.
+// CG (for SPD matrices) keeps x, r, p, d and every dot product, alpha and
+// beta in FP64; inner iterations use the FP32 matrix; every inner cycle ends
+// with an outer refinement step r = b - A x with the FP64 matrix, and a solve
+// finishes when that true residual satisfies |r| <= tol |b|.
+// Requests never share reductions, so a result does not depend on which
+// other requests were in flight.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "mspmv.hpp"
+#include "plan.hpp"
+#include "schedule.hpp"
+#include "serve_kernels.hpp"
+
+namespace argcsr {
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr size_t kAlign = 256;
+
+// Best-fit sub-allocator over one device allocation (the budget).
+class Arena {
+ public:
+  int init(size_t bytes) {
+    bytes_ = bytes;
+    if (hipMalloc(&base_, bytes) != hipSuccess) {
+      base_ = nullptr;
+      return fail(ARGCSR_ENOMEM, "server arena of %zu bytes could not be allocated", bytes);
+    }
+    free_[0] = bytes;
+    return ARGCSR_OK;
+  }
+  ~Arena() {
+    if (base_) (void)hipFree(base_);
+  }
+  void* alloc(size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign;
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes && (best == free_.end() || it->second < best->second)) best = it;
+    if (best == free_.end()) return nullptr;
+    const size_t off = best->first, len = best->second;
+    free_.erase(best);
+    if (len > bytes) free_[off + bytes] = len - bytes;
+    used_[off] = bytes;
+    in_use_ += bytes;
+    return static_cast<char*>(base_) + off;
+  }
+  void release(void* p) {
+    if (!p) return;
+    const size_t off = size_t(static_cast<char*>(p) - static_cast<char*>(base_));
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    size_t start = off, len = u->second;
+    in_use_ -= len;
+    used_.erase(u);
+    auto next = free_.lower_bound(start);
+    if (next != free_.end() && next->first == start + len) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == start) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    free_[start] = len;
+  }
+  size_t in_use() const { return in_use_; }
+  size_t capacity() const { return bytes_; }
+
+ private:
+  void* base_ = nullptr;
+  size_t bytes_ = 0, in_use_ = 0;
+  std::map<size_t, size_t> free_;   // offset -> length
+  std::map<size_t, size_t> used_;
+};
+
+struct Resident {
+  int64_t id = 0;
+  argcsr_matrix m64{};        // FP64 values
+  float* values32 = nullptr;  // FP32 values, same layout (groups, mapping, columns shared)
+  std::vector<void*> blocks;
+  size_t bytes = 0;
+  int64_t last_use = 0;
+};
+
+enum ReqStatus : int32_t { kPending = 1 };
+
+struct Request {
+  uint64_t ticket = 0;
+  argcsr_request q{};
+  argcsr_result res{};
+  // active state
+  int32_t slot = -1;
+  int32_t phase = kPhaseStart;
+  int32_t inner_in_cycle = 0;
+  double cycle_rr0 = 0.0;
+  std::vector<void*> blocks;
+  float* x32 = nullptr;
+  float* y32 = nullptr;
+  double* v64[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // b x r p d q64
+  float* p32 = nullptr;
+  float* q32 = nullptr;
+  Resident* mat = nullptr;
+};
+
+}  // namespace
+}  // namespace argcsr
+
+struct argcsr_server {
+  argcsr_server_config cfg{};
+  argcsr::Arena arena;
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<argcsr::Request*> incoming;                      // guarded by mu
+  std::unordered_map<uint64_t, argcsr_result> results;        // guarded by mu
+  std::unordered_map<int64_t, int32_t> refs;                  // matrix id -> queued/active requests (mu)
+  argcsr_server_stats stats{};                                // guarded by mu
+  // scheduler-thread state
+  std::deque<argcsr::Request*> pending;
+  std::vector<argcsr::Request*> active;
+  std::vector<int32_t> free_slots;
+  std::unordered_map<int64_t, std::unique_ptr<argcsr::Resident>> resident;
+  // per-step device buffers
+  void* d_desc = nullptr;
+  size_t d_desc_bytes = 0;
+  void* h_desc = nullptr;      // pinned staging
+  argcsr::CgScalars* d_scalars = nullptr;
+  argcsr::CgScalars* h_scalars = nullptr;   // pinned
+  argcsr::LaunchQueue* d_queues = nullptr;
+};
+
+namespace argcsr {
+namespace {
+
+void publish(argcsr_server* s, Request* r) {
+  r->res.t_done_ns = now_ns();
+  std::lock_guard<std::mutex> lock(s->mu);
+  s->results[r->ticket] = r->res;
+  if (r->q.kind == ARGCSR_REQ_SPMV || r->q.kind == ARGCSR_REQ_CG) {
+    auto it = s->refs.find(r->q.matrix_id);
+    if (it != s->refs.end() && --it->second == 0) s->refs.erase(it);
+    if (r->res.status == ARGCSR_OK) s->stats.completed++;
+    else s->stats.failed++;
+  }
+  s->cv_done.notify_all();
+}
+
+bool matrix_idle(argcsr_server* s, int64_t id) {
+  std::lock_guard<std::mutex> lock(s->mu);
+  return s->refs.find(id) == s->refs.end();
+}
+
+void evict(argcsr_server* s, Resident* m) {
+  for (void* p : m->blocks) s->arena.release(p);
+  std::lock_guard<std::mutex> lock(s->mu);
+  s->stats.evictions++;
+  s->stats.resident_matrices--;
+  s->stats.resident_bytes -= int64_t(m->bytes);
+}
+
+// Allocates from the arena, evicting least-recently-used idle matrices
+// (never `keep`) until the request fits.
+void* alloc_evicting(argcsr_server* s, size_t bytes, int64_t keep) {
+  for (;;) {
+    if (void* p = s->arena.alloc(bytes)) return p;
+    Resident* victim = nullptr;
+    for (auto& kv : s->resident) {
+      Resident* m = kv.second.get();
+      if (m->id == keep || !matrix_idle(s, m->id)) continue;
+      bool used = false;
+      for (Request* r : s->active) used |= r->mat == m;
+      if (used) continue;
+      if (!victim || m->last_use < victim->last_use) victim = m;
+    }
+    if (!victim) return nullptr;
+    const int64_t id = victim->id;
+    evict(s, victim);
+    s->resident.erase(id);
+  }
+}
+
+int admit(argcsr_server* s, Request* r) {
+  const argcsr_request& q = r->q;
+  if (s->resident.count(q.matrix_id)) {
+    s->resident[q.matrix_id]->last_use = now_ns();
+    return ARGCSR_OK;
+  }
+  int rc = check_row_ptr(q.n_rows, q.row_ptr);
+  if (rc) return rc;
+  if (q.n_rows < 0 || q.n_cols < 0) return fail(ARGCSR_EINVAL, "negative dimension");
+  const int64_t nnz = q.n_rows > 0 ? q.row_ptr[q.n_rows] : 0;
+  if (nnz > 0 && (!q.col || !q.val)) return fail(ARGCSR_EINVAL, "NULL CSR arrays");
+  int32_t T = s->cfg.block_dim > 0 ? s->cfg.block_dim : 64;
+  int32_t D = s->cfg.desired_chunk_size;
+  if (D <= 0) {
+    const double mean = q.n_rows > 0 ? double(nnz) / q.n_rows : 1.0;
+    D = int32_t(std::min(64.0, std::max(1.0, std::round(mean))));
+  }
+  auto m = std::make_unique<Resident>();
+  m->id = q.matrix_id;
+  argcsr_matrix& A = m->m64;
+  A.n_rows = q.n_rows;
+  A.n_cols = q.n_cols;
+  A.block_dim = T;
+  A.desired_chunk_size = D;
+  A.dtype = ARGCSR_F64;
+  rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, &A.n_groups, &A.n_slots, &A.n_heavy);
+  if (rc) return rc;
+  std::vector<size_t> sizes;
+  auto grab = [&](size_t bytes) -> void* {
+    void* p = alloc_evicting(s, bytes, q.matrix_id);
+    if (p) {
+      m->blocks.push_back(p);
+      sizes.push_back((std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign);
+    }
+    return p;
+  };
+  auto give_back = [&]() {
+    for (void* p : m->blocks) s->arena.release(p);
+  };
+  A.groups = static_cast<argcsr_group_info*>(grab(sizeof(argcsr_group_info) * size_t(A.n_groups)));
+  A.threads_mapping = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(q.n_rows)));
+  A.columns = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(A.n_slots)));
+  A.values = grab(sizeof(double) * size_t(A.n_slots));
+  m->values32 = static_cast<float*>(grab(sizeof(float) * size_t(A.n_slots)));
+  A.heavy_groups = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(std::max(A.n_heavy, 1))));
+  // CSR staging, released after the conversion
+  const size_t resident_blocks = m->blocks.size();
+  int32_t* d_rp = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(q.n_rows + 1)));
+  int32_t* d_col = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(std::max<int64_t>(nnz, 1))));
+  double* d_val = static_cast<double*>(grab(sizeof(double) * size_t(std::max<int64_t>(nnz, 1))));
+  if (m->blocks.size() != resident_blocks + 3 || !A.groups || !A.threads_mapping || !A.columns ||
+      !A.values || !m->values32 || !A.heavy_groups) {
+    give_back();
+    return fail(ARGCSR_EBUDGET, "matrix %lld (%lld slots) does not fit the %zu-byte budget",
+                (long long)q.matrix_id, (long long)A.n_slots, s->arena.capacity());
+  }
+  rc = ARGCSR_OK;
+  if (hipMemcpyAsync(d_rp, q.row_ptr, sizeof(int32_t) * size_t(q.n_rows + 1),
+                     hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+      (nnz > 0 && (hipMemcpyAsync(d_col, q.col, sizeof(int32_t) * size_t(nnz),
+                                  hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+                   hipMemcpyAsync(d_val, q.val, sizeof(double) * size_t(nnz),
+                                  hipMemcpyHostToDevice, s->stream) != hipSuccess)))
+    rc = fail(ARGCSR_EHIP, "CSR upload failed");
+  if (rc == ARGCSR_OK)
+    rc = argcsr_convert(q.n_rows, q.n_cols, q.row_ptr, d_rp, d_col, d_val, &A, s->stream);
+  if (rc == ARGCSR_OK && A.n_slots > 0) {
+    const int64_t blocks = std::min<int64_t>((A.n_slots + kVecBlock - 1) / kVecBlock, 8192);
+    round_values_kernel<<<int(blocks), kVecBlock, 0, s->stream>>>(
+        static_cast<const double*>(A.values), m->values32, A.n_slots);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
+      rc = fail(ARGCSR_EHIP, "value rounding failed");
+  }
+  for (size_t i = resident_blocks; i < m->blocks.size(); ++i) s->arena.release(m->blocks[i]);
+  m->blocks.resize(resident_blocks);
+  if (rc) {
+    give_back();
+    return rc;
+  }
+  m->bytes = 0;
+  for (size_t i = 0; i < resident_blocks; ++i) m->bytes += sizes[i];
+  if (A.n_heavy == 0) A.heavy_groups = nullptr;
+  m->last_use = now_ns();
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->stats.admissions++;
+    s->stats.resident_matrices++;
+    s->stats.resident_bytes += int64_t(m->bytes);
+  }
+  s->resident[q.matrix_id] = std::move(m);
+  return ARGCSR_OK;
+}
+
+void release_request(argcsr_server* s, Request* r) {
+  for (void* p : r->blocks) s->arena.release(p);
+  r->blocks.clear();
+  if (r->slot >= 0) s->free_slots.push_back(r->slot);
+  r->slot = -1;
+}
+
+// Moves a queued SPMV/CG request into a slot: allocates its vectors and
+// uploads its input.  Returns ARGCSR_EBUSY if memory is short right now.
+int activate(argcsr_server* s, Request* r) {
+  auto it = s->resident.find(r->q.matrix_id);
+  if (it == s->resident.end())
+    return fail(ARGCSR_ENOTFOUND, "matrix %lld is not resident (admit it first)",
+                (long long)r->q.matrix_id);
+  Resident* m = it->second.get();
+  const argcsr_matrix& A = m->m64;
+  if (!r->q.in || !r->q.out) return fail(ARGCSR_EINVAL, "request input or output is NULL");
+  auto grab = [&](size_t bytes) -> void* {
+    void* p = alloc_evicting(s, bytes, m->id);
+    if (p) r->blocks.push_back(p);
+    return p;
+  };
+  if (r->q.kind == ARGCSR_REQ_SPMV) {
+    r->x32 = static_cast<float*>(grab(sizeof(float) * size_t(std::max(A.n_cols, 1))));
+    r->y32 = static_cast<float*>(grab(sizeof(float) * size_t(std::max(A.n_rows, 1))));
+    if (!r->x32 || !r->y32) {
+      for (void* p : r->blocks) s->arena.release(p);
+      r->blocks.clear();
+      return ARGCSR_EBUSY;
+    }
+    ARGCSR_HIP(hipMemcpyAsync(r->x32, r->q.in, sizeof(float) * size_t(A.n_cols),
+                              hipMemcpyHostToDevice, s->stream));
+  } else {
+    if (A.n_rows != A.n_cols) return fail(ARGCSR_EINVAL, "CG needs a square matrix");
+    const size_t n = size_t(std::max(A.n_rows, 1));
+    bool ok = true;
+    for (int k = 0; k < 6; ++k) ok &= (r->v64[k] = static_cast<double*>(grab(sizeof(double) * n))) != nullptr;
+    ok &= (r->p32 = static_cast<float*>(grab(sizeof(float) * n))) != nullptr;
+    ok &= (r->q32 = static_cast<float*>(grab(sizeof(float) * n))) != nullptr;
+    if (!ok) {
+      for (void* p : r->blocks) s->arena.release(p);
+      r->blocks.clear();
+      return ARGCSR_EBUSY;
+    }
+    ARGCSR_HIP(hipMemcpyAsync(r->v64[0], r->q.in, sizeof(double) * size_t(A.n_rows),
+                              hipMemcpyHostToDevice, s->stream));
+    ARGCSR_HIP(hipMemsetAsync(r->v64[1], 0, sizeof(double) * size_t(A.n_rows), s->stream));
+    r->phase = kPhaseStart;
+  }
+  r->mat = m;
+  m->last_use = now_ns();
+  r->slot = s->free_slots.back();
+  s->free_slots.pop_back();
+  r->res.t_start_ns = now_ns();
+  return ARGCSR_OK;
+}
+
+void fill_matwork(MatWork& w, const argcsr_matrix& A, const void* values, const void* x, void* y,
+                  int32_t& groups, int32_t& heavy) {
+  w.groups = A.groups;
+  w.tm = A.threads_mapping;
+  w.columns = A.columns;
+  w.values = values;
+  w.heavy = A.heavy_groups;
+  w.x = x;
+  w.y = y;
+  w.block_dim = A.block_dim;
+  w.heavy_chunk = A.heavy_groups ? A.heavy_chunk : INT32_MAX;
+  w.group_begin = groups;
+  w.heavy_begin = heavy;
+  groups += A.n_groups;
+  heavy += A.heavy_groups ? A.n_heavy : 0;
+}
+
+int ensure_desc(argcsr_server* s, size_t bytes) {
+  if (bytes <= s->d_desc_bytes) return ARGCSR_OK;
+  if (s->d_desc) {
+    ARGCSR_HIP(hipStreamSynchronize(s->stream));
+    (void)hipFree(s->d_desc);
+    (void)hipHostFree(s->h_desc);
+    s->d_desc = s->h_desc = nullptr;
+  }
+  const size_t want = std::max(bytes * 2, size_t(1) << 20);
+  ARGCSR_HIP(hipMalloc(&s->d_desc, want));
+  ARGCSR_HIP(hipHostMalloc(&s->h_desc, want, hipHostMallocDefault));
+  s->d_desc_bytes = want;
+  return ARGCSR_OK;
+}
+
+template <int DT>
+void launch_mspmv(argcsr_server* s, const MatWork* d_w, int32_t n, int32_t groups, int32_t heavy,
+                  LaunchQueue* q) {
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mspmv_kernel<DT>, kSpmvWaves * 64, 0);
+  per_cu = std::max(1, std::min(per_cu, 8));
+  const int64_t work = int64_t(heavy) + (int64_t(groups) + kMspmvGrab * kSpmvWaves - 1) /
+                                            (kMspmvGrab * kSpmvWaves);
+  const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * per_cu, work)));
+  mspmv_kernel<DT><<<grid, kSpmvWaves * 64, 0, s->stream>>>(d_w, n, groups, heavy, q);
+}
+
+// One step for every active request.
+int step(argcsr_server* s) {
+  std::vector<Request*> f32, f64, cg;
+  for (Request* r : s->active) {
+    if (r->q.kind == ARGCSR_REQ_SPMV) f32.push_back(r);
+    else {
+      cg.push_back(r);
+      if (r->phase == kPhaseInner) f32.push_back(r);
+      else if (r->phase == kPhaseOuter) f64.push_back(r);
+    }
+  }
+  int32_t tiles = 0;
+  for (Request* r : cg) tiles += (r->mat->m64.n_rows + kTile - 1) / kTile;
+  // descriptor block: MatWork f32 | MatWork f64 | CgVec | tile table | partials
+  const size_t o_f64 = sizeof(MatWork) * f32.size();
+  const size_t o_vec = o_f64 + sizeof(MatWork) * f64.size();
+  const size_t o_tile = o_vec + sizeof(CgVec) * cg.size();
+  const size_t o_part = (o_tile + sizeof(int32_t) * size_t(tiles) + 15) / 16 * 16;
+  const size_t total = o_part + sizeof(double) * size_t(std::max(tiles, 1));
+  int rc = ensure_desc(s, total);
+  if (rc) return rc;
+  char* h = static_cast<char*>(s->h_desc);
+  char* d = static_cast<char*>(s->d_desc);
+  int32_t g32 = 0, h32 = 0, g64 = 0, h64 = 0;
+  for (size_t i = 0; i < f32.size(); ++i) {
+    Request* r = f32[i];
+    const argcsr_matrix& A = r->mat->m64;
+    MatWork& w = reinterpret_cast<MatWork*>(h)[i];
+    if (r->q.kind == ARGCSR_REQ_SPMV) fill_matwork(w, A, r->mat->values32, r->x32, r->y32, g32, h32);
+    else fill_matwork(w, A, r->mat->values32, r->p32, r->q32, g32, h32);
+  }
+  for (size_t i = 0; i < f64.size(); ++i) {
+    Request* r = f64[i];
+    MatWork& w = reinterpret_cast<MatWork*>(h + o_f64)[i];
+    fill_matwork(w, r->mat->m64, r->mat->m64.values, r->v64[1], r->v64[5], g64, h64);
+  }
+  int32_t t = 0;
+  int32_t* tile_req = reinterpret_cast<int32_t*>(h + o_tile);
+  for (size_t i = 0; i < cg.size(); ++i) {
+    Request* r = cg[i];
+    CgVec& v = reinterpret_cast<CgVec*>(h + o_vec)[i];
+    v = CgVec{r->v64[0], r->v64[1], r->v64[2], r->v64[3], r->v64[4], r->v64[5],
+              r->p32, r->q32, r->mat->m64.n_rows, r->phase, t, r->slot};
+    const int32_t nt = (r->mat->m64.n_rows + kTile - 1) / kTile;
+    for (int32_t k = 0; k < nt; ++k) tile_req[t + k] = int32_t(i);
+    t += nt;
+  }
+  ARGCSR_HIP(hipMemcpyAsync(d, h, o_part, hipMemcpyHostToDevice, s->stream));
+  const MatWork* d_w32 = reinterpret_cast<const MatWork*>(d);
+  const MatWork* d_w64 = reinterpret_cast<const MatWork*>(d + o_f64);
+  const CgVec* d_vec = reinterpret_cast<const CgVec*>(d + o_vec);
+  const int32_t* d_tiles = reinterpret_cast<const int32_t*>(d + o_tile);
+  double* d_part = reinterpret_cast<double*>(d + o_part);
+  const int ncg = int(cg.size());
+  if (!f64.empty()) cg_pre_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles);
+  reset_launch_queue_kernel<<<1, 64, 0, s->stream>>>(s->d_queues, 2);
+  if (!f32.empty()) launch_mspmv<ARGCSR_F32>(s, d_w32, int32_t(f32.size()), g32, h32, s->d_queues);
+  if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64, s->d_queues + 1);
+  if (ncg > 0) {
+    const int sb = (ncg + 63) / 64;
+    cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, d_part);
+    cg_alpha_kernel<<<sb, 64, 0, s->stream>>>(d_vec, ncg, d_part, s->d_scalars);
+    cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_part);
+    cg_beta_kernel<<<sb, 64, 0, s->stream>>>(d_vec, ncg, d_part, s->d_scalars);
+    cg_direction_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars);
+    ARGCSR_HIP(hipMemcpyAsync(s->h_scalars, s->d_scalars, sizeof(CgScalars) * size_t(s->cfg.max_active),
+                              hipMemcpyDeviceToHost, s->stream));
+  }
+  ARGCSR_HIP(hipGetLastError());
+  ARGCSR_HIP(hipStreamSynchronize(s->stream));
+
+  // retire / advance
+  std::vector<Request*> keep;
+  for (Request* r : s->active) {
+    bool done = false;
+    if (r->q.kind == ARGCSR_REQ_SPMV) {
+      rc = hipMemcpy(r->q.out, r->y32, sizeof(float) * size_t(r->mat->m64.n_rows),
+                     hipMemcpyDeviceToHost) == hipSuccess ? ARGCSR_OK : ARGCSR_EHIP;
+      r->res.status = rc;
+      done = true;
+    } else {
+      const CgScalars& sc = s->h_scalars[r->slot];
+      if (r->phase == kPhaseInner) {
+        r->res.iterations++;
+        r->inner_in_cycle++;
+        const bool cycle_done = sc.pq <= 0.0 ||
+                                sc.rr <= s->cfg.cg_inner_tol * s->cfg.cg_inner_tol * r->cycle_rr0 ||
+                                r->inner_in_cycle >= s->cfg.cg_max_inner ||
+                                r->res.iterations >= s->cfg.cg_max_iter;
+        if (cycle_done) r->phase = kPhaseOuter;
+      } else {
+        if (r->phase == kPhaseOuter) r->res.refinements++;
+        r->res.relres = sc.bnorm2 > 0.0 ? std::sqrt(sc.rr / sc.bnorm2) : 0.0;
+        if (r->res.relres <= s->cfg.cg_tol || r->res.iterations >= s->cfg.cg_max_iter) {
+          const bool conv = r->res.relres <= s->cfg.cg_tol;
+          rc = hipMemcpy(r->q.out, r->v64[1], sizeof(double) * size_t(r->mat->m64.n_rows),
+                         hipMemcpyDeviceToHost) == hipSuccess ? ARGCSR_OK : ARGCSR_EHIP;
+          r->res.status = rc != ARGCSR_OK ? rc : conv ? ARGCSR_OK : ARGCSR_ENOCONV;
+          done = true;
+        } else {
+          r->phase = kPhaseInner;
+          r->inner_in_cycle = 0;
+          r->cycle_rr0 = sc.rr;
+        }
+      }
+    }
+    if (done) {
+      release_request(s, r);
+      publish(s, r);
+      delete r;
+    } else {
+      keep.push_back(r);
+    }
+  }
+  s->active.swap(keep);
+  std::lock_guard<std::mutex> lock(s->mu);
+  s->stats.steps++;
+  return ARGCSR_OK;
+}
+
+void scheduler(argcsr_server* s) {
+  (void)hipSetDevice(s->cfg.device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lock(s->mu);
+      if (s->active.empty() && s->pending.empty() && s->incoming.empty() && !s->stop)
+        s->cv_work.wait_for(lock, std::chrono::milliseconds(2));
+      if (s->stop && s->incoming.empty()) break;
+      while (!s->incoming.empty()) {
+        s->pending.push_back(s->incoming.front());
+        s->incoming.pop_front();
+      }
+    }
+    // admissions and new requests, in submission order
+    while (!s->pending.empty()) {
+      Request* r = s->pending.front();
+      if (r->q.kind == ARGCSR_REQ_ADMIT) {
+        s->pending.pop_front();
+        r->res.t_start_ns = now_ns();
+        r->res.status = admit(s, r);
+        publish(s, r);
+        delete r;
+        continue;
+      }
+      if (r->q.kind == ARGCSR_REQ_EVICT) {
+        s->pending.pop_front();
+        auto it = s->resident.find(r->q.matrix_id);
+        bool used = false;
+        for (Request* a : s->active) used |= it != s->resident.end() && a->mat == it->second.get();
+        if (it == s->resident.end()) r->res.status = ARGCSR_ENOTFOUND;
+        else if (used || !matrix_idle(s, r->q.matrix_id)) r->res.status = ARGCSR_EBUSY;
+        else {
+          evict(s, it->second.get());
+          s->resident.erase(it);
+          r->res.status = ARGCSR_OK;
+        }
+        publish(s, r);
+        delete r;
+        continue;
+      }
+      if (s->free_slots.empty()) break;           // wait for a slot
+      const int rc = activate(s, r);
+      if (rc == ARGCSR_EBUSY) {
+        if (!s->active.empty()) break;            // memory frees up as requests finish
+        r->res.status = fail(ARGCSR_EBUDGET, "request does not fit the budget");
+      } else if (rc != ARGCSR_OK) {
+        r->res.status = rc;
+      }
+      s->pending.pop_front();
+      if (rc == ARGCSR_OK) {
+        s->active.push_back(r);
+      } else {
+        release_request(s, r);
+        publish(s, r);
+        delete r;
+      }
+    }
+    if (!s->active.empty()) {
+      const int rc = step(s);
+      if (rc != ARGCSR_OK) {                       // device error: fail everything in flight
+        for (Request* r : s->active) {
+          r->res.status = rc;
+          release_request(s, r);
+          publish(s, r);
+          delete r;
+        }
+        s->active.clear();
+      }
+    }
+  }
+  // shut down: fail what is left
+  for (Request* r : s->active) {
+    r->res.status = ARGCSR_ENOTFOUND;
+    release_request(s, r);
+    publish(s, r);
+    delete r;
+  }
+  for (Request* r : s->pending) {
+    r->res.status = ARGCSR_ENOTFOUND;
+    publish(s, r);
+    delete r;
+  }
+  s->active.clear();
+  s->pending.clear();
+}
+
+}  // namespace
+}  // namespace argcsr
+
+extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_server** out) {
+  using namespace argcsr;
+  clear_error();
+  if (!cfg || !out) return fail(ARGCSR_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (cfg->budget_bytes <= 0 || cfg->max_active < 1 || cfg->max_active > kMaxLaunchMats ||
+      !(cfg->cg_tol > 0) || !(cfg->cg_inner_tol > 0) || cfg->cg_max_inner < 1 ||
+      cfg->cg_max_iter < 1 || (cfg->block_dim != 0 && cfg->block_dim != 64 &&
+                               cfg->block_dim != 128 && cfg->block_dim != 256))
+    return fail(ARGCSR_EINVAL, "invalid server configuration");
+  auto* s = new (std::nothrow) argcsr_server();
+  if (!s) return fail(ARGCSR_ENOMEM, "host allocation failed");
+  s->cfg = *cfg;
+  int rc = ARGCSR_OK;
+  if (hipSetDevice(cfg->device) != hipSuccess) rc = fail(ARGCSR_EHIP, "hipSetDevice failed");
+  if (!rc) rc = s->arena.init(size_t(cfg->budget_bytes));
+  if (!rc && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(ARGCSR_EHIP, "hipStreamCreate failed");
+  if (!rc && (hipMalloc(&s->d_scalars, sizeof(CgScalars) * size_t(cfg->max_active)) != hipSuccess ||
+              hipHostMalloc(&s->h_scalars, sizeof(CgScalars) * size_t(cfg->max_active),
+                            hipHostMallocDefault) != hipSuccess ||
+              hipMalloc(&s->d_queues, sizeof(LaunchQueue) * 2) != hipSuccess))
+    rc = fail(ARGCSR_ENOMEM, "server buffers could not be allocated");
+  if (rc) {
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->d_scalars) (void)hipFree(s->d_scalars);
+    if (s->h_scalars) (void)hipHostFree(s->h_scalars);
+    if (s->d_queues) (void)hipFree(s->d_queues);
+    delete s;
+    return rc;
+  }
+  for (int32_t k = cfg->max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
+  s->worker = std::thread(scheduler, s);
+  *out = s;
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_server_submit(argcsr_server* s, const argcsr_request* q, uint64_t* ticket) {
+  using namespace argcsr;
+  clear_error();
+  if (!s || !q || !ticket) return fail(ARGCSR_EINVAL, "NULL argument");
+  if (q->kind < ARGCSR_REQ_ADMIT || q->kind > ARGCSR_REQ_EVICT)
+    return fail(ARGCSR_EINVAL, "unknown request kind %d", q->kind);
+  auto* r = new (std::nothrow) Request();
+  if (!r) return fail(ARGCSR_ENOMEM, "host allocation failed");
+  r->q = *q;
+  r->res.status = kPending;
+  r->res.t_submit_ns = now_ns();
+  std::lock_guard<std::mutex> lock(s->mu);
+  if (s->stop) {
+    delete r;
+    return fail(ARGCSR_EINVAL, "server is shutting down");
+  }
+  r->ticket = s->next_ticket++;
+  s->results[r->ticket] = r->res;
+  if (q->kind == ARGCSR_REQ_SPMV || q->kind == ARGCSR_REQ_CG) {
+    s->refs[q->matrix_id]++;
+    s->stats.submitted++;
+  }
+  s->incoming.push_back(r);
+  *ticket = r->ticket;
+  s->cv_work.notify_one();
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_server_poll(argcsr_server* s, uint64_t ticket, argcsr_result* res) {
+  using namespace argcsr;
+  clear_error();
+  if (!s || !res) return fail(ARGCSR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(s->mu);
+  auto it = s->results.find(ticket);
+  if (it == s->results.end()) return fail(ARGCSR_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  *res = it->second;
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_server_wait(argcsr_server* s, uint64_t ticket, int64_t timeout_ns,
+                                  argcsr_result* res) {
+  using namespace argcsr;
+  clear_error();
+  if (!s || !res) return fail(ARGCSR_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lock(s->mu);
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns);
+  for (;;) {
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return fail(ARGCSR_ENOTFOUND, "unknown ticket");
+    if (it->second.status != kPending) {
+      *res = it->second;
+      return ARGCSR_OK;
+    }
+    if (s->cv_done.wait_until(lock, deadline) == std::cv_status::timeout) {
+      *res = s->results[ticket];
+      return res->status == kPending ? fail(ARGCSR_EBUSY, "timed out") : ARGCSR_OK;
+    }
+  }
+}
+
+extern "C" int argcsr_server_release(argcsr_server* s, uint64_t ticket) {
+  using namespace argcsr;
+  clear_error();
+  if (!s) return fail(ARGCSR_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> lock(s->mu);
+  auto it = s->results.find(ticket);
+  if (it == s->results.end()) return fail(ARGCSR_ENOTFOUND, "unknown ticket");
+  if (it->second.status == kPending) return fail(ARGCSR_EBUSY, "request still in flight");
+  s->results.erase(it);
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_server_get_stats(argcsr_server* s, argcsr_server_stats* out) {
+  using namespace argcsr;
+  clear_error();
+  if (!s || !out) return fail(ARGCSR_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lock(s->mu);
+  *out = s->stats;
+  out->arena_bytes = int64_t(s->arena.capacity());
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_server_destroy(argcsr_server* s) {
+  using namespace argcsr;
+  clear_error();
+  if (!s) return ARGCSR_OK;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamDestroy(s->stream);
+  if (s->d_desc) (void)hipFree(s->d_desc);
+  if (s->h_desc) (void)hipHostFree(s->h_desc);
+  (void)hipFree(s->d_scalars);
+  (void)hipHostFree(s->h_scalars);
+  (void)hipFree(s->d_queues);
+  delete s;
+  return ARGCSR_OK;
+}

@@ -1,0 +1,197 @@
+// Vector kernels of the serving loop's conjugate-gradient solves.
+//
+// Every active CG request owns FP64 vectors b, x, r, p, d, q64 and FP32
+// p32, q32 of its own length.  A step processes all requests at once: the
+// vectors are cut into tiles of kTile elements, a per-tile request table maps
+// workgroups to (request, tile), and every reduction is done per tile in a
+// fixed order, then per request over its tiles in tile order by one thread.
+// No value of one request ever enters another request's arithmetic, so each
+// result is bitwise the same whether the request runs alone or in a mix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace argcsr {
+
+constexpr int kVecBlock = 256;
+constexpr int kVecPerThread = 8;
+constexpr int kTile = kVecBlock * kVecPerThread;
+
+enum CgPhase : int32_t {
+  kPhaseStart = 0,   // r = b, p = r, d = 0, rr = |b|^2 = bnorm2
+  kPhaseInner = 1,   // one CG iteration on the FP32 matrix
+  kPhaseOuter = 2,   // x += d, r = b - A64 x (FP64 matrix), restart: p = r, d = 0
+};
+
+struct CgVec {
+  const double* b;
+  double* x;
+  double* r;
+  double* p;
+  double* d;
+  const double* q64;     // A64 x (outer phase)
+  float* p32;            // FP32 copy of p, the FP32 SpMV's input
+  const float* q32;      // A32 p32 (inner phase)
+  int32_t n;
+  int32_t phase;
+  int32_t tile_begin;    // first global tile of this request
+  int32_t slot;          // index into the scalar array
+};
+
+struct CgScalars {
+  double rr;             // current recursive (inner) or true (outer) |r|^2
+  double alpha;
+  double beta;
+  double bnorm2;         // |b|^2
+  double pq;             // p . A32 p of the last inner iteration
+  double pad[3];
+};
+
+// Fixed-order block sum: each thread's values in index order, then a
+// tree over the 256 threads.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kVecBlock / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// x += d for requests entering the outer phase (before the FP64 SpMV reads x).
+__global__ __launch_bounds__(kVecBlock) void cg_pre_kernel(const CgVec* __restrict__ v,
+                                                          const int32_t* __restrict__ tile_req) {
+  const CgVec w = v[tile_req[blockIdx.x]];
+  if (w.phase != kPhaseOuter) return;
+  const int32_t base = (int32_t(blockIdx.x) - w.tile_begin) * kTile;
+  for (int k = 0; k < kVecPerThread; ++k) {
+    const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
+    if (i < w.n) w.x[i] = w.x[i] + w.d[i];
+  }
+}
+
+// inner: partial sums of p . q32
+__global__ __launch_bounds__(kVecBlock) void cg_dot_kernel(const CgVec* __restrict__ v,
+                                                          const int32_t* __restrict__ tile_req,
+                                                          double* __restrict__ partial) {
+  __shared__ double red[kVecBlock];
+  const CgVec w = v[tile_req[blockIdx.x]];
+  if (w.phase != kPhaseInner) return;
+  const int32_t base = (int32_t(blockIdx.x) - w.tile_begin) * kTile;
+  double s = 0.0;
+  for (int k = 0; k < kVecPerThread; ++k) {
+    const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
+    if (i < w.n) s = __builtin_fma(w.p[i], double(w.q32[i]), s);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__device__ __forceinline__ double tiles_sum(const double* partial, int32_t begin, int32_t n) {
+  double s = 0.0;
+  const int32_t tiles = (n + kTile - 1) / kTile;
+  for (int32_t t = 0; t < tiles; ++t) s += partial[begin + t];
+  return s;
+}
+
+// inner: alpha = rr / (p . q)
+__global__ void cg_alpha_kernel(const CgVec* __restrict__ v, int32_t n_req,
+                                const double* __restrict__ partial, CgScalars* __restrict__ sc) {
+  const int32_t k = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k >= n_req) return;
+  const CgVec w = v[k];
+  if (w.phase != kPhaseInner) return;
+  CgScalars& s = sc[w.slot];
+  const double pq = tiles_sum(partial, w.tile_begin, w.n);
+  s.pq = pq;
+  s.alpha = pq > 0.0 ? s.rr / pq : 0.0;         // pq <= 0: no step (host leaves the cycle)
+}
+
+// inner: d += alpha p, r -= alpha q32; start/outer: r = b (- q64), d = 0,
+// p = r, p32 = (float) r.  All phases: partial sums of r . r.
+__global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec* __restrict__ v,
+                                                             const int32_t* __restrict__ tile_req,
+                                                             const CgScalars* __restrict__ sc,
+                                                             double* __restrict__ partial) {
+  __shared__ double red[kVecBlock];
+  const CgVec w = v[tile_req[blockIdx.x]];
+  const int32_t base = (int32_t(blockIdx.x) - w.tile_begin) * kTile;
+  double s = 0.0;
+  if (w.phase == kPhaseInner) {
+    const double alpha = sc[w.slot].alpha;
+    for (int k = 0; k < kVecPerThread; ++k) {
+      const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
+      if (i < w.n) {
+        w.d[i] = __builtin_fma(alpha, w.p[i], w.d[i]);
+        const double ri = __builtin_fma(-alpha, double(w.q32[i]), w.r[i]);
+        w.r[i] = ri;
+        s = __builtin_fma(ri, ri, s);
+      }
+    }
+  } else {
+    const bool outer = w.phase == kPhaseOuter;
+    for (int k = 0; k < kVecPerThread; ++k) {
+      const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
+      if (i < w.n) {
+        const double ri = outer ? w.b[i] - w.q64[i] : w.b[i];
+        w.r[i] = ri;
+        w.p[i] = ri;
+        w.p32[i] = float(ri);
+        w.d[i] = 0.0;
+        s = __builtin_fma(ri, ri, s);
+      }
+    }
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// inner: rr_new = r . r, beta = rr_new / rr; start/outer: rr = r . r
+// (and |b|^2 at the start).
+__global__ void cg_beta_kernel(const CgVec* __restrict__ v, int32_t n_req,
+                               const double* __restrict__ partial, CgScalars* __restrict__ sc) {
+  const int32_t k = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k >= n_req) return;
+  const CgVec w = v[k];
+  CgScalars& s = sc[w.slot];
+  const double rr = tiles_sum(partial, w.tile_begin, w.n);
+  if (w.phase == kPhaseInner) {
+    s.beta = s.rr > 0.0 ? rr / s.rr : 0.0;
+  } else if (w.phase == kPhaseStart) {
+    s.bnorm2 = rr;
+  }
+  s.rr = rr;
+}
+
+// inner: p = r + beta p, p32 = (float) p
+__global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const CgVec* __restrict__ v,
+                                                                const int32_t* __restrict__ tile_req,
+                                                                const CgScalars* __restrict__ sc) {
+  const CgVec w = v[tile_req[blockIdx.x]];
+  if (w.phase != kPhaseInner) return;
+  const double beta = sc[w.slot].beta;
+  const int32_t base = (int32_t(blockIdx.x) - w.tile_begin) * kTile;
+  for (int k = 0; k < kVecPerThread; ++k) {
+    const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
+    if (i < w.n) {
+      const double pi = __builtin_fma(beta, w.p[i], w.r[i]);
+      w.p[i] = pi;
+      w.p32[i] = float(pi);
+    }
+  }
+}
+
+// FP64 values -> FP32 values of the same layout (nearest-even).
+__global__ __launch_bounds__(kVecBlock) void round_values_kernel(const double* __restrict__ v64,
+                                                                float* __restrict__ v32,
+                                                                int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    v32[i] = float(v64[i]);
+}
+
+}  // namespace argcsr

@@ -1,0 +1,152 @@
+"""GPU: the request server -- resident matrices under a budget, continuous
+batching of SpMV and CG requests, mixed-precision CG to a 1e-10 true
+relative residual, and results that are bitwise the same alone and in a mix.
+
+CG is pinned the only way its result is fixed: any x whose true residual
+|b - A x| / |b|, recomputed here with the FP64 oracle, is at most 1e-10."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def srv_mod():
+    from paper_1203_5737_amd import _lib, serve
+    _lib.lib()
+    return serve
+
+
+def pool(count, n_lo=2e3, n_hi=3e4):
+    return [synth.serve_pool_matrix(i, n_lo, n_hi)[0] for i in range(count)]
+
+
+def true_relres(A, x, b):
+    r = b - oracle.csr_spmv(A.rp, A.col, A.val, x)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+def spmv_ok(A, x32, y):
+    stored = oracle.stored_as_f64(oracle.round_array(A.val, oracle.F32), oracle.F32)
+    xx = x32.astype(np.float64)
+    ref = oracle.csr_spmv(A.rp, A.col, stored, xx)
+    L = np.diff(A.rp)
+    scale = np.bincount(np.repeat(np.arange(A.n_rows), L), weights=np.abs(stored * xx[A.col]),
+                        minlength=A.n_rows)
+    u = 2.0 ** -24
+    return bool(np.all(np.abs(y.astype(np.float64) - ref) <= (L + 1) * u / (1 - (L + 1) * u) * scale))
+
+
+def run_requests(srv, mats, reqs):
+    """reqs: list of (kind, matrix index, input); returns outputs and results."""
+    tickets = []
+    for kind, m, inp in reqs:
+        if kind == "spmv":
+            tickets.append(srv.spmv(m, inp, mats[m].n_rows))
+        else:
+            tickets.append(srv.cg(m, inp))
+    outs, res = [], []
+    for t, out in tickets:
+        r = srv.wait(t, 120.0)
+        assert r["status"] == 0, r
+        outs.append(out.copy())
+        res.append(r)
+        srv.release(t)
+    return outs, res
+
+
+def make_requests(mats, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(count):
+        m = int(rng.integers(0, len(mats)))
+        if k % 2 == 0:
+            reqs.append(("spmv", m, rng.uniform(-1, 1, mats[m].n_cols).astype(np.float32)))
+        else:
+            reqs.append(("cg", m, rng.uniform(-1, 1, mats[m].n_rows)))
+    return reqs
+
+
+def admit_all(srv, mats):
+    for i, A in enumerate(mats):
+        t = srv.admit(i, A.rp, A.col, A.val, A.n_cols)
+        assert srv.wait(t, 120.0)["status"] == 0
+        srv.release(t)
+
+
+def test_serve_results_and_alone_vs_mix(srv_mod):
+    print("\n[gpu] serve mix", flush=True)
+    mats = pool(6)
+    reqs = make_requests(mats, 24, 1)
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=32) as srv:
+        admit_all(srv, mats)
+        mix_out, mix_res = run_requests(srv, mats, reqs)          # all in flight together
+        st = srv.stats()
+        assert st["completed"] == 24 and st["steps"] > 0
+    for (kind, m, inp), out, r in zip(reqs, mix_out, mix_res):
+        if kind == "spmv":
+            assert spmv_ok(mats[m], inp, out)
+        else:
+            assert r["relres"] <= 1e-10 and r["refinements"] >= 1 and r["iterations"] > 0
+            assert true_relres(mats[m], out, inp) <= 1e-10
+    print("[gpu] serve alone", flush=True)
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=1) as srv:  # one request at a time
+        admit_all(srv, mats)
+        alone_out, alone_res = run_requests(srv, mats, reqs)
+    for a, b, ra, rb in zip(mix_out, alone_out, mix_res, alone_res):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+        assert ra["iterations"] == rb["iterations"]
+
+
+def test_serve_requests_join_while_others_run(srv_mod):
+    print("\n[gpu] serve continuous", flush=True)
+    mats = pool(3, 5e4, 8e4)
+    rng = np.random.default_rng(2)
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=8) as srv:
+        admit_all(srv, mats)
+        first = [srv.cg(m, rng.uniform(-1, 1, mats[m].n_rows)) for m in range(3)]
+        late = [srv.spmv(m, rng.uniform(-1, 1, mats[m].n_cols), mats[m].n_rows) for m in range(3)]
+        r_late = [srv.wait(t, 120.0) for t, _ in late]
+        r_first = [srv.wait(t, 120.0) for t, _ in first]
+        assert all(r["status"] == 0 for r in r_late + r_first)
+        # the SpMVs entered while the solves were still iterating and left first
+        assert max(r["t_done_ns"] for r in r_late) < max(r["t_done_ns"] for r in r_first)
+        assert min(r["t_start_ns"] for r in r_late) < min(r["t_done_ns"] for r in r_first)
+
+
+def test_serve_budget_eviction_and_errors(srv_mod):
+    print("\n[gpu] serve budget", flush=True)
+    from paper_1203_5737_amd import _lib
+    mats = pool(4, 2e4, 2.5e4)
+    big = synth.shifted_laplacian("2d", 600_000, np.random.default_rng(3))
+    with srv_mod.Server(budget_bytes=6 << 20, max_active=4) as srv:    # ~2 matrices fit
+        admit_all(srv, mats)                      # later admissions evict earlier ones
+        st = srv.stats()
+        assert st["evictions"] >= 1 and st["resident_bytes"] <= 6 << 20
+        t = srv.admit(99, big.rp, big.col, big.val, big.n_cols)
+        assert srv.wait(t)["status"] == _lib.EBUDGET
+        t, _ = srv.cg(0, np.ones(mats[0].n_rows))   # matrix 0 was evicted
+        assert srv.wait(t)["status"] == _lib.ENOTFOUND
+        t = srv.admit(0, mats[0].rp, mats[0].col, mats[0].val, mats[0].n_cols)
+        assert srv.wait(t)["status"] == 0
+        t, x = srv.cg(0, np.ones(mats[0].n_rows))
+        r = srv.wait(t)
+        assert r["status"] == 0 and true_relres(mats[0], x, np.ones(mats[0].n_rows)) <= 1e-10
+        rect = synth.random_csr(np.full(50, 3), 80, np.random.default_rng(4), np.random.default_rng(5))
+        t = srv.admit(7, rect.rp, rect.col, rect.val, 80)
+        assert srv.wait(t)["status"] == 0
+        t, _ = srv.cg(7, np.ones(50))             # CG needs a square matrix
+        assert srv.wait(t)["status"] == _lib.EINVAL
+        t = srv.evict(7)
+        assert srv.wait(t)["status"] == 0
+        t = srv.evict(7)
+        assert srv.wait(t)["status"] == _lib.ENOTFOUND
+        with pytest.raises(_lib.ArgCsrError):
+            srv.poll(123456789)
+    with pytest.raises(_lib.ArgCsrError):
+        srv_mod.Server(budget_bytes=1 << 20, max_active=0)
