@@ -219,6 +219,85 @@ def run_batch(args, torch, ac):
     print(json.dumps(out))
 
 
+def run_serve(args, torch, ac):
+    """Open-loop serving: Poisson arrivals at --rate req/s of SpMV and CG
+    requests (50/50) on a pool of SPD shifted 2D/3D Laplacians with n
+    log-uniform in [1e4, 1e6]; request matrix ~ Zipf(1.1) over the pool.
+    Latency runs from the scheduled arrival to the result in host memory."""
+    import threading
+    import synth
+    from paper_1203_5737_amd import serve
+    rng = np.random.default_rng(np.random.SeedSequence([12035737, 4, 999999]))
+    P = args.pool
+    pool = [synth.serve_pool_matrix(i)[0] for i in range(P)]
+    zipf_w = 1.0 / np.arange(1, P + 1) ** 1.1
+    zipf_w /= zipf_w.sum()
+    n_req = args.requests + args.warm_requests
+    mats = rng.choice(P, size=n_req, p=zipf_w)
+    kinds = rng.random(n_req) < 0.5                      # True: CG
+    gaps = rng.exponential(1.0 / args.rate, n_req)
+    inputs = [rng.uniform(-1, 1, pool[m].n_rows) if cg else
+              rng.uniform(-1, 1, pool[m].n_cols).astype(np.float32)
+              for m, cg in zip(mats, kinds)]
+    srv = serve.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_active=args.max_active,
+                       cg_tol=1e-10)
+    records = []
+    t0 = time.monotonic_ns() + 50_000_000
+    arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
+    for k in range(n_req):
+        while time.monotonic_ns() < arrivals[k]:
+            pass
+        m = int(mats[k])
+        A = pool[m]
+        # ADMIT is a no-op for a resident matrix; it converts the matrix again
+        # after an eviction.  Its result says whether it converted (cold).
+        ta = srv.admit(m, A.rp, A.col, A.val, A.n_cols)
+        if kinds[k]:
+            t, _ = srv.cg(m, inputs[k])
+        else:
+            t, _ = srv.spmv(m, inputs[k], pool[m].n_rows)
+        records.append((t, ta, int(arrivals[k]), bool(kinds[k]), m))
+    results = []
+    for t, ta, arr, cg, m in records:
+        r = srv.wait(t, 600.0)
+        cold = srv.wait(ta, 600.0)["iterations"] == 1
+        srv.release(ta)
+        results.append((r, arr, cold, cg, m))
+    wall = (max(r["t_done_ns"] for r, *_ in results) - t0) * 1e-9
+    stats = srv.stats()
+    srv.close()
+    meas = results[args.warm_requests:]
+    ok = [x for x in meas if x[0]["status"] == 0]
+    lat = lambda xs: np.array([(r["t_done_ns"] - arr) * 1e-6 for r, arr, *_ in xs])
+    def pct(xs):
+        a = lat(xs)
+        return {"n": int(a.size), "p50_ms": float(np.percentile(a, 50)) if a.size else None,
+                "p99_ms": float(np.percentile(a, 99)) if a.size else None}
+    all_lat = lat(ok)
+    sp_bytes = sum(useful_bytes(pool[m], 1) * (1 if not cg else max(1, r["iterations"]))
+                   for r, _, _, cg, m in ok)
+    out = {
+        "metric": METRIC, "value": float(np.percentile(all_lat, 50)), "unit": "ms (p50 latency)",
+        "n_gpus": 1, "steps": len(meas), "warmup": args.warm_requests,
+        "ms_per_step": float(all_lat.mean()), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 SpMV / f64 CG", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson {args.rate:g} req/s, 50% SpMV / 50% CG to 1e-10, "
+                               f"pool of {P} SPD shifted 2D/3D Laplacians, n log-uniform [1e4,1e6], "
+                               f"Zipf(1.1) popularity, {args.budget_gb:g} GB budget",
+                   "max_active": args.max_active},
+        "latency": {"all": pct(ok), "p99_ms": float(np.percentile(all_lat, 99)),
+                    "warm": pct([x for x in ok if not x[2]]), "cold": pct([x for x in ok if x[2]]),
+                    "spmv": pct([x for x in ok if not x[3]]), "cg": pct([x for x in ok if x[3]])},
+        "throughput_req_s": len(results) / wall,
+        "aggregate_spmv_gbps_lower_bound": sp_bytes / wall / 1e9,
+        "failed": len(meas) - len(ok),
+        "cg_max_relres": max((r["relres"] for r, _, _, cg, _ in ok if cg), default=None),
+        "cg_mean_iterations": float(np.mean([r["iterations"] for r, _, _, cg, _ in ok if cg] or [0])),
+        "server": stats,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +311,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the CSR and warm timings")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=1000.0, help="serve: arrivals per second")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests")
+    ap.add_argument("--warm-requests", type=int, default=200, help="serve: unmeasured first requests")
+    ap.add_argument("--pool", type=int, default=64, help="serve: distinct matrices")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: device memory budget")
+    ap.add_argument("--max-active", type=int, default=64, help="serve: requests per step")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -245,6 +330,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     ac._lib.lib()                                    # fails loudly if not built
+    if args.workload == "serve":
+        return run_serve(args, torch, ac)
     if args.workload == "batch":
         if args.dtype == "f64" and "--dtype" not in sys.argv:
             args.dtype = "f32"                        # the batch workload is quoted in FP32

@@ -284,7 +284,8 @@ typedef struct {
 
 typedef struct {
   int32_t status;              /* ARGCSR_PENDING, ARGCSR_OK or an error code */
-  int32_t iterations;          /* CG: inner iterations (FP32 matrix) */
+  int32_t iterations;          /* CG: inner iterations (FP32 matrix); ADMIT: 1 if the
+                                  matrix was converted now, 0 if already resident */
   int32_t refinements;         /* CG: outer residual evaluations (FP64 matrix) */
   int32_t reserved;
   double relres;               /* CG: final |b - A x| / |b| with the FP64 matrix */

@@ -554,7 +554,9 @@ void scheduler(argcsr_server* s) {
       if (r->q.kind == ARGCSR_REQ_ADMIT) {
         s->pending.pop_front();
         r->res.t_start_ns = now_ns();
+        const bool was_resident = s->resident.count(r->q.matrix_id) != 0;
         r->res.status = admit(s, r);
+        r->res.iterations = (r->res.status == ARGCSR_OK && !was_resident) ? 1 : 0;
         publish(s, r);
         delete r;
         continue;
