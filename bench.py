@@ -137,6 +137,29 @@ def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
             "single_thread_ms": st * 1e3}
 
 
+def f32_variant(A, x, dev, timer, torch, ac, steps):
+    """The same matrix with FP32 values, x and y (T=256, D=1), against plain
+    CSR in FP32, timed the same way."""
+    B = useful_bytes(A, 1)
+    M = ac.convert(dev, 256, 1, 1)
+    xd = torch.from_numpy(x).to("cuda", torch.float32)
+    yd = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
+    f = lambda: ac.spmv(M, xd, yd)
+    timer.run(f, 5)
+    t, _ = timer.run(f, steps)
+    vals = dev.val.to(torch.float32)
+    best = None
+    for V in (8, 16, 32, 64):
+        g = lambda V=V: ac.csr_spmv(dev, xd, yd, values=vals, dtype=1, lanes_per_row=V)
+        timer.run(g, 3)
+        c, _ = timer.run(g, max(10, steps // 5))
+        if best is None or c.mean() < best[1].mean():
+            best = (V, c)
+    return {"block_dim": 256, "desired_chunk_size": 1, "mean_ms": float(t.mean()),
+            "gbps": B / (t.mean() * 1e-3) / 1e9, "csr_gbps": B / (best[1].mean() * 1e-3) / 1e9,
+            "csr_lanes_per_row": best[0], "speedup_vs_csr": float(best[1].mean() / t.mean())}
+
+
 def traffic_for(workload: str, dtype_name: str, T: int, D: int):
     """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE for
     the current kernel source (None when absent or the kernel has changed)."""
@@ -403,6 +426,8 @@ def main():
         csr_gbps = B / (t.mean() * 1e-3) / 1e9
         out["csr"] = stats(t) | {"gbps": csr_gbps, "lanes_per_row": V}
         out["speedup_vs_csr"] = gbps / csr_gbps
+        if dtype == 0 and args.workload == "powerlaw":
+            out["f32"] = f32_variant(A, x, dev, timer, torch, ac, args.steps)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, x, useful_bytes(A, 0))   # the oracle is FP64

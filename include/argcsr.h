@@ -109,7 +109,7 @@ int argcsr_version(void);
  * c >= 1 with sum over its rows of max(1, ceil(L_r / c)) <= block_dim.
  *   n_rows            >= 0
  *   row_ptr_host      host int32[n_rows+1], CSR row offsets (Sec. 2)
- *   block_dim         >= 1 (the GPU entry points accept 64, 128, 256)
+ *   block_dim         1..1024 (the SpMV entry points accept 64, 128, 256)
  *   desired_chunk_size >= 1
  *   n_groups, n_slots out: group count and slot count (sum c_g*block_dim)
  *   n_heavy           out (may be NULL): length of the heavy_groups schedule

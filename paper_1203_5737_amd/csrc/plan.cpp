@@ -3,11 +3,16 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <thread>
 
 #include "common.hpp"
 #include "schedule.hpp"
 
 namespace argcsr {
+
+namespace {
+constexpr int32_t kMaxGroupRows = 1024;   // plan/convert accept block_dim <= 1024
+}  // namespace
 
 int check_row_ptr(int32_t n_rows, const int32_t* rp) {
   if (n_rows < 0) return fail(ARGCSR_EINVAL, "n_rows < 0");
@@ -39,28 +44,39 @@ int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
 
 int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
                        int32_t block_dim) {
-  int64_t longest = 0;
+  const uint32_t T = uint32_t(block_dim);
+  uint32_t longest = 0;
   for (int32_t l = 0; l < size; ++l)
-    longest = std::max<int64_t>(longest, int64_t(rp[first + l + 1]) - rp[first + l]);
-  const int64_t total = int64_t(rp[first + size]) - rp[first];
-  auto chunks_needed = [&](int64_t c) {
-    int64_t need = 0;
-    for (int32_t l = 0; l < size; ++l) {
-      const int64_t L = int64_t(rp[first + l + 1]) - rp[first + l];
-      need += L > c ? (L + c - 1) / c : 1;
-    }
-    return need;
-  };
+    longest = std::max(longest, uint32_t(rp[first + l + 1] - rp[first + l]));
+  if (size == 1) return int32_t(longest > T ? (longest - 1) / T + 1 : 1);   // one row: ceil(L/T)
+  const uint64_t total = uint64_t(rp[first + size]) - uint64_t(rp[first]);
   // chunks_needed is non-increasing in c; at c = longest every row needs one
   // chunk (size <= block_dim), and no c below total/block_dim can fit.
-  int64_t lo = std::max<int64_t>(1, (total + block_dim - 1) / block_dim);
-  int64_t hi = std::max<int64_t>(1, longest);
+  uint32_t lo = uint32_t(std::max<uint64_t>(1, (total + T - 1) / T));
+  uint32_t hi = std::max<uint32_t>(1, longest);
+  if (lo >= hi) return int32_t(hi);
+  // for c >= lo only rows longer than lo can need more than one chunk
+  uint32_t longer[kMaxGroupRows];
+  int32_t n_longer = 0;
+  for (int32_t l = 0; l < size; ++l) {
+    const uint32_t L = uint32_t(rp[first + l + 1] - rp[first + l]);
+    if (L > lo) longer[n_longer++] = L;
+  }
+  auto chunks_needed = [&](uint32_t c) {
+    uint64_t need = uint64_t(size - n_longer);
+    for (int32_t k = 0; k < n_longer; ++k)
+      need += longer[k] > c ? (longer[k] - 1) / c + 1 : 1;
+    return need;
+  };
+  // the answer is usually the lower bound or just above it
+  for (int k = 0; k < 2 && lo < hi; ++k, ++lo)
+    if (chunks_needed(lo) <= T) return int32_t(lo);
   while (lo < hi) {
-    const int64_t mid = lo + (hi - lo) / 2;
-    if (chunks_needed(mid) <= block_dim) hi = mid;
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (chunks_needed(mid) <= T) hi = mid;
     else lo = mid + 1;
   }
-  return (int32_t)lo;
+  return int32_t(lo);
 }
 
 }  // namespace argcsr
@@ -71,19 +87,29 @@ extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
   using namespace argcsr;
   clear_error();
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
-  if (block_dim < 1 || desired_chunk_size < 1)
-    return fail(ARGCSR_EINVAL, "block_dim and desired_chunk_size must be >= 1");
+  if (block_dim < 1 || block_dim > kMaxGroupRows || desired_chunk_size < 1)
+    return fail(ARGCSR_EINVAL, "block_dim must be in [1, %d] and desired_chunk_size >= 1",
+                kMaxGroupRows);
   int rc = check_row_ptr(n_rows, row_ptr_host);
   if (rc) return rc;
   std::vector<argcsr_group_info> groups;
   rc = group_rows(n_rows, row_ptr_host, block_dim, desired_chunk_size, &groups);
   if (rc) return rc;
+  // step 2 is independent per group: split large matrices over host threads
   std::vector<int32_t> chunk(groups.size());
+  const size_t G = groups.size();
+  const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const unsigned n_threads = G >= 16384 ? hw : 1;
+  auto work = [&](unsigned t) {
+    for (size_t g = t * G / n_threads; g < (t + 1) * G / n_threads; ++g)
+      chunk[g] = min_chunk_size(row_ptr_host, groups[g].first_row, groups[g].size, block_dim);
+  };
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < n_threads; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& th : pool) th.join();
   int64_t slots = 0;
-  for (size_t g = 0; g < groups.size(); ++g) {
-    chunk[g] = min_chunk_size(row_ptr_host, groups[g].first_row, groups[g].size, block_dim);
-    slots += int64_t(chunk[g]) * block_dim;
-  }
+  for (size_t g = 0; g < G; ++g) slots += int64_t(chunk[g]) * block_dim;
   const int32_t heavy_chunk = heavy_chunk_for(block_dim, slots, (int32_t)groups.size());
   int32_t heavy = 0;
   for (int32_t c : chunk) heavy += c > heavy_chunk;
