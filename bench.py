@@ -39,7 +39,7 @@ KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_
                   "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp",
                   "paper_1203_5737_amd/csrc/schedule.hpp"]
 # (block_dim, desired_chunk_size) per workload unless given on the command line
-DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (64, 27), "laplace64": (64, 1)}
+DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (128, 27), "laplace64": (64, 1)}
 
 
 def kernel_source_hash() -> str:

@@ -61,34 +61,82 @@ __device__ __forceinline__ void chunk_partials(
   for (int w = 0; w < W; ++w) { acc[w] = 0; alive[w] = true; }
   const int32_t* cb = columns + offset + lane;
   const S* vb = values + offset + lane;
-  for (int j = j0; j < j1; j += U) {
+  if constexpr (sizeof(S) < 8) {
+    // 4- and 2-byte values: the next U steps are loaded before this batch's x
+    // gathers are issued (double buffering fits the register budget)
     int32_t cc[U][W];
     S vv[U][W];
+    auto load = [&](int j, int32_t (&c)[U][W], S (&v)[U][W]) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        if (j + u < j1) {   // streamed once: keep L2 for the x gathers
-          cc[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
-          vv[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
-        } else {
-          cc[u][w] = -1;
-          vv[u][w] = S(0);
+        for (int w = 0; w < W; ++w) {
+          if (j + u < j1) {   // streamed once: keep L2 for the x gathers
+            c[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
+            v[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
+          } else {
+            c[u][w] = -1;
+            v[u][w] = S(0);
+          }
         }
       }
-    }
-    bool any = false;
+    };
+    if (j0 < j1) load(j0, cc, vv);
+    for (int j = j0; j < j1; j += U) {
+      int32_t nc[U][W];
+      S nv[U][W];
+      const bool more = j + U < j1;
+      if (more) load(j + U, nc, nv);
+      bool any = false;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        alive[w] = alive[w] && (cc[u][w] >= 0);
-        if (alive[w]) acc[w] = __builtin_fma(Vt::load(vv[u][w]), x[cc[u][w]], acc[w]);
+        for (int w = 0; w < W; ++w) {
+          alive[w] = alive[w] && (cc[u][w] >= 0);
+          if (alive[w]) acc[w] = __builtin_fma(Vt::load(vv[u][w]), x[cc[u][w]], acc[w]);
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) any |= alive[w];
+      if (__ballot(any) == 0 || !more) break;     // every chunk reached its padding
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) { cc[u][w] = nc[u][w]; vv[u][w] = nv[u][w]; }
       }
     }
+  } else {
+    // 8-byte values: one batch of U steps at a time (double buffering would
+    // cost occupancy)
+    for (int j = j0; j < j1; j += U) {
+      int32_t cc[U][W];
+      S vv[U][W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) any |= alive[w];
-    if (__ballot(any) == 0) break;                // every chunk reached its padding
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          if (j + u < j1) {   // streamed once: keep L2 for the x gathers
+            cc[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
+            vv[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
+          } else {
+            cc[u][w] = -1;
+            vv[u][w] = S(0);
+          }
+        }
+      }
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          alive[w] = alive[w] && (cc[u][w] >= 0);
+          if (alive[w]) acc[w] = __builtin_fma(Vt::load(vv[u][w]), x[cc[u][w]], acc[w]);
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) any |= alive[w];
+      if (__ballot(any) == 0) break;              // every chunk reached its padding
+    }
   }
 }
 
