@@ -3,9 +3,9 @@
 // Work items are (matrix, group) pairs.  Heavy groups (a long chunk loop,
 // see schedule.hpp) are taken by whole workgroups from one queue and split
 // over their waves; all other groups are taken by single waves, kGrab at a
-// time, from a second queue in matrix and row order.  Queue counters are
-// zeroed by a one-block kernel enqueued before every launch (no memset, so
-// the pair can be captured in a hipGraph).  Each group is computed by the
+// time, from per-XCD segments of a second list in matrix and row order
+// (workqueue.hpp).  Queue counters are zeroed by a one-block kernel enqueued
+// before every launch (no memset, so the pair can be captured in a hipGraph).  Each group is computed by the
 // same deterministic routine as argcsr_spmv, so the results do not depend on
 // which wave takes which item.
 #include <hip/hip_runtime.h>
@@ -18,24 +18,13 @@
 #include "common.hpp"
 #include "schedule.hpp"
 #include "spmv_kernels.hpp"
+#include "workqueue.hpp"
 
 namespace argcsr {
 namespace {
 
 constexpr int kGrab = 4;                 // normal items taken per queue access
 constexpr int kMaxBlocksPerCu = 8;       // persistent grid: as many workgroups as fit, <= 8 per CU
-
-struct QueueState {
-  int32_t heavy_next;
-  int32_t normal_next;
-};
-
-__global__ void reset_queue_kernel(QueueState* q) {
-  if (threadIdx.x == 0) {
-    q->heavy_next = 0;
-    q->normal_next = 0;
-  }
-}
 
 template <int DT, int W, int U>
 __device__ __forceinline__ void run_item(const BatchMat& m, int32_t g, int32_t* ends) {
@@ -62,17 +51,16 @@ __device__ __forceinline__ void run_heavy(const BatchMat& m, int32_t g, int32_t*
 template <int DT>
 __global__ __launch_bounds__(kSpmvWaves * 64) void batch_spmv_kernel(
     const BatchMat* __restrict__ mats, const int2* __restrict__ heavy, int32_t n_heavy,
-    const int2* __restrict__ items, int32_t n_items, QueueState* q) {
+    const int2* __restrict__ items, int32_t n_items, WorkQueues* q) {
   using A = typename Val<DT>::acc;
   __shared__ int32_t ends[kSpmvWaves][256];
   __shared__ A part_mem[(kSpmvWaves - 1) * 256];
   __shared__ int32_t grabbed;
   const int wv = wave_uniform(int(threadIdx.x >> 6));
-  const int lane = lane_id();
 
   // heavy groups: the whole workgroup takes one at a time
   for (;;) {
-    if (threadIdx.x == 0) grabbed = atomicAdd(&q->heavy_next, 1);
+    if (threadIdx.x == 0) grabbed = atomicAdd(&q->heavy.next, 1);
     __syncthreads();
     const int32_t h = grabbed;
     __syncthreads();                      // all waves have read `grabbed`
@@ -88,12 +76,9 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void batch_spmv_kernel(
   }
 
   // all other groups: each wave takes kGrab items at a time
-  for (;;) {
-    int32_t i0 = 0;
-    if (lane == 0) i0 = atomicAdd(&q->normal_next, kGrab);
-    i0 = wave_uniform(__shfl(i0, 0, 64));
-    if (i0 >= n_items) break;
-    const int32_t i1 = min(i0 + kGrab, n_items);
+  QueueCursor cursor{int(blockIdx.x % kQueues), 0};
+  int32_t i0, i1;
+  while (cursor.take(q, n_items, kGrab, &i0, &i1)) {
     for (int32_t i = i0; i < i1; ++i) {
       const int2 it = items[i];
       const BatchMat m = mats[it.x];
@@ -116,8 +101,8 @@ const void* kernel_for(int32_t dtype) {
 }
 
 int launch_kernels(argcsr_batch* b, hipStream_t s) {
-  auto* q = static_cast<QueueState*>(b->queue);
-  reset_queue_kernel<<<1, 64, 0, s>>>(q);
+  auto* q = static_cast<WorkQueues*>(b->queue);
+  reset_work_queues_kernel<<<1, 64, 0, s>>>(q, 1);
   const dim3 grid(b->grid), block(kSpmvWaves * 64);
   switch (b->dtype) {
     case ARGCSR_F64:
@@ -191,7 +176,7 @@ int build_batch(int32_t n, const argcsr_matrix* mats, const void* const* xs, voi
   ARGCSR_HIP(hipMalloc(&b->d_mats, sizeof(BatchMat) * size_t(std::max(n, 1))));
   ARGCSR_HIP(hipMalloc(&b->d_items, sizeof(int2) * std::max<size_t>(items.size(), 1)));
   ARGCSR_HIP(hipMalloc(&b->d_heavy, sizeof(int2) * std::max<size_t>(heavy.size(), 1)));
-  ARGCSR_HIP(hipMalloc(&b->queue, sizeof(QueueState)));
+  ARGCSR_HIP(hipMalloc(&b->queue, sizeof(WorkQueues)));
   ARGCSR_HIP(hipMemcpy(b->d_mats, hm.data(), sizeof(BatchMat) * size_t(n), hipMemcpyHostToDevice));
   if (!items.empty())
     ARGCSR_HIP(hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(),

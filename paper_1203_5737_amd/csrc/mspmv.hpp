@@ -12,6 +12,7 @@
 #include "common.hpp"
 #include "schedule.hpp"
 #include "spmv_kernels.hpp"
+#include "workqueue.hpp"
 
 namespace argcsr {
 
@@ -32,19 +33,6 @@ struct MatWork {
   int32_t heavy_begin;
 };
 
-struct LaunchQueue {
-  int32_t heavy_next;
-  int32_t normal_next;
-};
-
-__global__ void reset_launch_queue_kernel(LaunchQueue* q, int32_t count) {
-  const int32_t i = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i < count) {
-    q[i].heavy_next = 0;
-    q[i].normal_next = 0;
-  }
-}
-
 // largest m in [0, n) with begin[m] <= i (begin[0] == 0, begin non-decreasing)
 __device__ __forceinline__ int32_t find_owner(const int32_t* begin, int32_t n, int32_t i) {
   int32_t lo = 0, hi = n - 1;
@@ -59,7 +47,7 @@ __device__ __forceinline__ int32_t find_owner(const int32_t* begin, int32_t n, i
 template <int DT>
 __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
     const MatWork* __restrict__ mw, int32_t n_mats, int32_t total_groups, int32_t total_heavy,
-    LaunchQueue* q) {
+    WorkQueues* q) {
   using Vt = Val<DT>;
   using S = typename Vt::storage;
   using A = typename Vt::acc;
@@ -74,10 +62,9 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
   }
   __syncthreads();
   const int wv = wave_uniform(int(threadIdx.x >> 6));
-  const int lane = lane_id();
 
   for (;;) {                                        // heavy groups, whole workgroup
-    if (threadIdx.x == 0) grabbed = atomicAdd(&q->heavy_next, 1);
+    if (threadIdx.x == 0) grabbed = atomicAdd(&q->heavy.next, 1);
     __syncthreads();
     const int32_t h = grabbed;
     __syncthreads();
@@ -108,12 +95,9 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
     __syncthreads();
   }
 
-  for (;;) {                                        // all other groups, one wave each
-    int32_t i0 = 0;
-    if (lane == 0) i0 = atomicAdd(&q->normal_next, kMspmvGrab);
-    i0 = wave_uniform(__shfl(i0, 0, 64));
-    if (i0 >= total_groups) break;
-    const int32_t i1 = min(i0 + kMspmvGrab, total_groups);
+  QueueCursor cursor{int(blockIdx.x % kQueues), 0};
+  int32_t i0, i1;
+  while (cursor.take(q, total_groups, kMspmvGrab, &i0, &i1)) {   // other groups, one wave each
     int32_t m = find_owner(gbeg, n_mats, i0);
     for (int32_t i = i0; i < i1; ++i) {
       while (m + 1 < n_mats && gbeg[m + 1] <= i) ++m;

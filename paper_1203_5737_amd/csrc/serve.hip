@@ -166,7 +166,7 @@ struct argcsr_server {
   void* h_desc = nullptr;      // pinned staging
   argcsr::CgScalars* d_scalars = nullptr;
   argcsr::CgScalars* h_scalars = nullptr;   // pinned
-  argcsr::LaunchQueue* d_queues = nullptr;
+  argcsr::WorkQueues* d_queues = nullptr;
 };
 
 namespace argcsr {
@@ -403,7 +403,7 @@ int ensure_desc(argcsr_server* s, size_t bytes) {
 
 template <int DT>
 void launch_mspmv(argcsr_server* s, const MatWork* d_w, int32_t n, int32_t groups, int32_t heavy,
-                  LaunchQueue* q) {
+                  WorkQueues* q) {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -470,15 +470,14 @@ int step(argcsr_server* s) {
   double* d_part = reinterpret_cast<double*>(d + o_part);
   const int ncg = int(cg.size());
   if (!f64.empty()) cg_pre_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles);
-  reset_launch_queue_kernel<<<1, 64, 0, s->stream>>>(s->d_queues, 2);
+  reset_work_queues_kernel<<<1, 64, 0, s->stream>>>(s->d_queues, 2);
   if (!f32.empty()) launch_mspmv<ARGCSR_F32>(s, d_w32, int32_t(f32.size()), g32, h32, s->d_queues);
   if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64, s->d_queues + 1);
   if (ncg > 0) {
-    const int sb = (ncg + 63) / 64;
     cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, d_part);
-    cg_alpha_kernel<<<sb, 64, 0, s->stream>>>(d_vec, ncg, d_part, s->d_scalars);
+    cg_alpha_kernel<<<ncg, kVecBlock, 0, s->stream>>>(d_vec, d_part, s->d_scalars);
     cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_part);
-    cg_beta_kernel<<<sb, 64, 0, s->stream>>>(d_vec, ncg, d_part, s->d_scalars);
+    cg_beta_kernel<<<ncg, kVecBlock, 0, s->stream>>>(d_vec, d_part, s->d_scalars);
     cg_direction_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars);
     ARGCSR_HIP(hipMemcpyAsync(s->h_scalars, s->d_scalars, sizeof(CgScalars) * size_t(s->cfg.max_active),
                               hipMemcpyDeviceToHost, s->stream));
@@ -647,7 +646,7 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
   if (!rc && (hipMalloc(&s->d_scalars, sizeof(CgScalars) * size_t(cfg->max_active)) != hipSuccess ||
               hipHostMalloc(&s->h_scalars, sizeof(CgScalars) * size_t(cfg->max_active),
                             hipHostMallocDefault) != hipSuccess ||
-              hipMalloc(&s->d_queues, sizeof(LaunchQueue) * 2) != hipSuccess))
+              hipMalloc(&s->d_queues, sizeof(WorkQueues) * 2) != hipSuccess))
     rc = fail(ARGCSR_ENOMEM, "server buffers could not be allocated");
   if (rc) {
     if (s->stream) (void)hipStreamDestroy(s->stream);

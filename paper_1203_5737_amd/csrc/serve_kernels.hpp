@@ -63,7 +63,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // x += d for requests entering the outer phase (before the FP64 SpMV reads x).
-__global__ __launch_bounds__(kVecBlock) void cg_pre_kernel(const CgVec* __restrict__ v,
+static __global__ __launch_bounds__(kVecBlock) void cg_pre_kernel(const CgVec* __restrict__ v,
                                                           const int32_t* __restrict__ tile_req) {
   const CgVec w = v[tile_req[blockIdx.x]];
   if (w.phase != kPhaseOuter) return;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kVecBlock) void cg_pre_kernel(const CgVec* __restri
 }
 
 // inner: partial sums of p . q32
-__global__ __launch_bounds__(kVecBlock) void cg_dot_kernel(const CgVec* __restrict__ v,
+static __global__ __launch_bounds__(kVecBlock) void cg_dot_kernel(const CgVec* __restrict__ v,
                                                           const int32_t* __restrict__ tile_req,
                                                           double* __restrict__ partial) {
   __shared__ double red[kVecBlock];
@@ -91,29 +91,35 @@ __global__ __launch_bounds__(kVecBlock) void cg_dot_kernel(const CgVec* __restri
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__device__ __forceinline__ double tiles_sum(const double* partial, int32_t begin, int32_t n) {
-  double s = 0.0;
+// Sum of one request's tile partials, by one workgroup: thread t adds tiles
+// t, t+256, ... in order, then a fixed tree over the threads.  The order
+// depends only on the request's own tile count.
+__device__ __forceinline__ double tiles_sum(const double* partial, int32_t begin, int32_t n,
+                                           double* red) {
   const int32_t tiles = (n + kTile - 1) / kTile;
-  for (int32_t t = 0; t < tiles; ++t) s += partial[begin + t];
-  return s;
+  double s = 0.0;
+  for (int32_t t = int32_t(threadIdx.x); t < tiles; t += kVecBlock) s += partial[begin + t];
+  return block_sum(s, red);
 }
 
-// inner: alpha = rr / (p . q)
-__global__ void cg_alpha_kernel(const CgVec* __restrict__ v, int32_t n_req,
-                                const double* __restrict__ partial, CgScalars* __restrict__ sc) {
-  const int32_t k = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
-  if (k >= n_req) return;
-  const CgVec w = v[k];
+// inner: alpha = rr / (p . q); one workgroup per request
+static __global__ __launch_bounds__(kVecBlock) void cg_alpha_kernel(const CgVec* __restrict__ v,
+                                                            const double* __restrict__ partial,
+                                                            CgScalars* __restrict__ sc) {
+  __shared__ double red[kVecBlock];
+  const CgVec w = v[blockIdx.x];
   if (w.phase != kPhaseInner) return;
-  CgScalars& s = sc[w.slot];
-  const double pq = tiles_sum(partial, w.tile_begin, w.n);
-  s.pq = pq;
-  s.alpha = pq > 0.0 ? s.rr / pq : 0.0;         // pq <= 0: no step (host leaves the cycle)
+  const double pq = tiles_sum(partial, w.tile_begin, w.n, red);
+  if (threadIdx.x == 0) {
+    CgScalars& s = sc[w.slot];
+    s.pq = pq;
+    s.alpha = pq > 0.0 ? s.rr / pq : 0.0;       // pq <= 0: no step (host leaves the cycle)
+  }
 }
 
 // inner: d += alpha p, r -= alpha q32; start/outer: r = b (- q64), d = 0,
 // p = r, p32 = (float) r.  All phases: partial sums of r . r.
-__global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec* __restrict__ v,
+static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec* __restrict__ v,
                                                              const int32_t* __restrict__ tile_req,
                                                              const CgScalars* __restrict__ sc,
                                                              double* __restrict__ partial) {
@@ -151,24 +157,23 @@ __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec* __res
 }
 
 // inner: rr_new = r . r, beta = rr_new / rr; start/outer: rr = r . r
-// (and |b|^2 at the start).
-__global__ void cg_beta_kernel(const CgVec* __restrict__ v, int32_t n_req,
-                               const double* __restrict__ partial, CgScalars* __restrict__ sc) {
-  const int32_t k = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
-  if (k >= n_req) return;
-  const CgVec w = v[k];
-  CgScalars& s = sc[w.slot];
-  const double rr = tiles_sum(partial, w.tile_begin, w.n);
-  if (w.phase == kPhaseInner) {
-    s.beta = s.rr > 0.0 ? rr / s.rr : 0.0;
-  } else if (w.phase == kPhaseStart) {
-    s.bnorm2 = rr;
+// (and |b|^2 at the start).  One workgroup per request.
+static __global__ __launch_bounds__(kVecBlock) void cg_beta_kernel(const CgVec* __restrict__ v,
+                                                           const double* __restrict__ partial,
+                                                           CgScalars* __restrict__ sc) {
+  __shared__ double red[kVecBlock];
+  const CgVec w = v[blockIdx.x];
+  const double rr = tiles_sum(partial, w.tile_begin, w.n, red);
+  if (threadIdx.x == 0) {
+    CgScalars& s = sc[w.slot];
+    if (w.phase == kPhaseInner) s.beta = s.rr > 0.0 ? rr / s.rr : 0.0;
+    else if (w.phase == kPhaseStart) s.bnorm2 = rr;
+    s.rr = rr;
   }
-  s.rr = rr;
 }
 
 // inner: p = r + beta p, p32 = (float) p
-__global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const CgVec* __restrict__ v,
+static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const CgVec* __restrict__ v,
                                                                 const int32_t* __restrict__ tile_req,
                                                                 const CgScalars* __restrict__ sc) {
   const CgVec w = v[tile_req[blockIdx.x]];
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const CgVec* __
 }
 
 // FP64 values -> FP32 values of the same layout (nearest-even).
-__global__ __launch_bounds__(kVecBlock) void round_values_kernel(const double* __restrict__ v64,
+static __global__ __launch_bounds__(kVecBlock) void round_values_kernel(const double* __restrict__ v64,
                                                                 float* __restrict__ v32,
                                                                 int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
