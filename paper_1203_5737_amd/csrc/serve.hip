@@ -33,6 +33,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.hpp"
 #include "common.hpp"
 #include "mspmv.hpp"
 #include "plan.hpp"
@@ -47,67 +48,33 @@ int64_t now_ns() {
              std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-constexpr size_t kAlign = 256;
-
-// Best-fit sub-allocator over one device allocation (the budget).
+// The device memory budget: one allocation carved up by a RangeAllocator.
 class Arena {
  public:
   int init(size_t bytes) {
-    bytes_ = bytes;
     if (hipMalloc(&base_, bytes) != hipSuccess) {
       base_ = nullptr;
       return fail(ARGCSR_ENOMEM, "server arena of %zu bytes could not be allocated", bytes);
     }
-    free_[0] = bytes;
+    ranges_.reset(bytes);
     return ARGCSR_OK;
   }
   ~Arena() {
     if (base_) (void)hipFree(base_);
   }
   void* alloc(size_t bytes) {
-    bytes = (std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign;
-    auto best = free_.end();
-    for (auto it = free_.begin(); it != free_.end(); ++it)
-      if (it->second >= bytes && (best == free_.end() || it->second < best->second)) best = it;
-    if (best == free_.end()) return nullptr;
-    const size_t off = best->first, len = best->second;
-    free_.erase(best);
-    if (len > bytes) free_[off + bytes] = len - bytes;
-    used_[off] = bytes;
-    in_use_ += bytes;
-    return static_cast<char*>(base_) + off;
+    const size_t off = ranges_.alloc(bytes);
+    return off == RangeAllocator::kNone ? nullptr : static_cast<char*>(base_) + off;
   }
   void release(void* p) {
-    if (!p) return;
-    const size_t off = size_t(static_cast<char*>(p) - static_cast<char*>(base_));
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    size_t start = off, len = u->second;
-    in_use_ -= len;
-    used_.erase(u);
-    auto next = free_.lower_bound(start);
-    if (next != free_.end() && next->first == start + len) {
-      len += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == start) {
-        start = prev->first;
-        len += prev->second;
-        free_.erase(prev);
-      }
-    }
-    free_[start] = len;
+    if (p) ranges_.release(size_t(static_cast<char*>(p) - static_cast<char*>(base_)));
   }
-  size_t in_use() const { return in_use_; }
-  size_t capacity() const { return bytes_; }
+  size_t in_use() const { return ranges_.in_use(); }
+  size_t capacity() const { return ranges_.capacity(); }
 
  private:
   void* base_ = nullptr;
-  size_t bytes_ = 0, in_use_ = 0;
-  std::map<size_t, size_t> free_;   // offset -> length
-  std::map<size_t, size_t> used_;
+  RangeAllocator ranges_;
 };
 
 struct Resident {
