@@ -3,6 +3,8 @@
 
 #include <cstdint>
 
+#include "argcsr.h"
+
 namespace argcsr {
 
 constexpr int kSpmvWaves = 4;   // waves per SpMV workgroup
@@ -28,6 +30,18 @@ __host__ __device__ constexpr int32_t heavy_chunk_for(int32_t block_dim, int64_t
                              (int64_t(n_groups) * block_dim);
   const int64_t by_mean = kHeavyMeanFactor * mean_chunk;
   return by_rounds > by_mean ? by_rounds : int32_t(by_mean < INT32_MAX ? by_mean : INT32_MAX);
+}
+
+// Runs (argcsr_run_info): group g opens a run iff it is the first group, it
+// or its predecessor is heavy, or its offset lies in another window of
+// ARGCSR_RUN_SLOTS slots than its predecessor's.  One wave takes a run: its
+// slots are contiguous, so its chunk loads cover several short groups at once.
+constexpr int32_t kRunSlots = ARGCSR_RUN_SLOTS;
+static_assert(kRunSlots == kLoadSteps * 64, "a run window is one batch of loads");
+__host__ __device__ constexpr bool opens_run(int32_t g, int32_t offset_prev, int32_t chunk_prev,
+                                             int32_t offset, int32_t chunk, int32_t heavy_chunk) {
+  return g == 0 || chunk > heavy_chunk || chunk_prev > heavy_chunk ||
+         offset / kRunSlots != offset_prev / kRunSlots;
 }
 
 }  // namespace argcsr

@@ -2,7 +2,8 @@
 // partial sums, then per-row sums of the partial sums).
 //
 // Mapping to CDNA4 (a wave has 64 lanes):
-//   - one wave per group; with T = 64*W chunks per group, lane i owns chunks
+//   - one wave per group, or per run of consecutive short groups (the runs
+//     schedule); with T = 64*W chunks per group, lane i owns chunks
 //     i, i+64, ..., i+64*(W-1) ("sub-blocks" w = 0..W-1).  A group's slots
 //     for step j are T consecutive values/columns, so every load is a
 //     contiguous, fully coalesced wave-wide access (the paper's column-major
@@ -32,6 +33,15 @@ void launch(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
   const bool sched = A->heavy_groups != nullptr && A->n_heavy > 0;
   const int32_t n_heavy = sched ? A->n_heavy : 0;
   const int32_t heavy_chunk = sched ? A->heavy_chunk : INT32_MAX;
+  if (A->runs != nullptr && A->n_runs > 0) {
+    const int blocks = n_heavy + (A->n_runs + kSpmvWaves - 1) / kSpmvWaves;
+    argcsr_spmv_runs_kernel<DT, W, U><<<blocks, kSpmvWaves * 64, 0, s>>>(
+        A->groups, A->runs, A->n_runs, A->threads_mapping, A->columns,
+        static_cast<const typename Vt::storage*>(A->values),
+        static_cast<const typename Vt::acc*>(x), static_cast<typename Vt::acc*>(y),
+        A->heavy_groups, n_heavy);
+    return;
+  }
   const int blocks = n_heavy + (A->n_groups + kSpmvWaves - 1) / kSpmvWaves;
   argcsr_spmv_kernel<DT, W, U><<<blocks, kSpmvWaves * 64, 0, s>>>(
       A->groups, A->n_groups, A->threads_mapping, A->columns,
@@ -67,6 +77,8 @@ int check_matrix(const argcsr_matrix* A) {
                           A->heavy_chunk != heavy_chunk_for(A->block_dim, A->n_slots,
                                                             A->n_groups)))
     return fail(ARGCSR_EINVAL, "heavy-group schedule does not match the matrix");
+  if (A->runs && (A->n_runs < 1 || A->n_runs > A->n_groups))
+    return fail(ARGCSR_EINVAL, "run schedule does not match the matrix");
   return ARGCSR_OK;
 }
 
