@@ -61,26 +61,6 @@ typedef struct {
   int32_t chunk_size;
 } argcsr_group_info;
 
-/* A run of consecutive groups processed by one wave (launch schedule, not
- * part of the paper's format).  Group g opens a new run iff g == 0, or g or
- * g-1 is heavy (see argcsr_matrix), or offset_g / ARGCSR_RUN_SLOTS differs
- * from offset_{g-1} / ARGCSR_RUN_SLOTS.  So the groups of a run all start in
- * one window of ARGCSR_RUN_SLOTS slots: for block_dim <= ARGCSR_RUN_SLOTS a
- * run holds at most ARGCSR_RUN_SLOTS / block_dim groups and at most
- * ARGCSR_RUN_SLOTS rows (larger block dims give one group per run), and a
- * heavy group is always a run of its own.  Run k covers groups
- * [runs[k].first_group, runs[k+1].first_group), slots [runs[k].offset,
- * runs[k+1].offset) and rows [runs[k].first_row, runs[k+1].first_row); entry
- * n_runs is the sentinel {n_groups, n_slots, n_rows, 0}. */
-#define ARGCSR_RUN_SLOTS 512
-#define ARGCSR_RUN_HEAVY 1      /* flags bit: the run is one heavy group */
-typedef struct {
-  int32_t first_group;
-  int32_t offset;
-  int32_t first_row;
-  int32_t flags;
-} argcsr_run_info;
-
 /* A converted matrix.  All arrays are caller-owned device memory:
  *   groups[n_groups]            group table (Listing 1)
  *   threads_mapping[n_rows]     per group, inclusive prefix sum of the number
@@ -94,10 +74,6 @@ typedef struct {
  *                               waves of a workgroup and started first.  May
  *                               be NULL (then every group is processed by one
  *                               wave, in order).
- *   runs[n_runs + 1]            launch schedule (not part of the paper's
- *                               format): the runs of groups that one wave
- *                               processes together (argcsr_run_info).  May be
- *                               NULL (then each wave takes one group).
  * block_dim (chunks per group, the paper's blockDim.x) must be 64, 128 or
  * 256 on the GPU; desired_chunk_size (the paper's desiredChunkSize) >= 1. */
 typedef struct {
@@ -116,9 +92,6 @@ typedef struct {
   int32_t n_heavy;             /* set by argcsr_plan / argcsr_convert */
   int32_t heavy_chunk;         /* set by argcsr_convert */
   int32_t* heavy_groups;
-  int32_t n_runs;              /* set by argcsr_plan / argcsr_convert */
-  int32_t reserved;
-  argcsr_run_info* runs;
 } argcsr_matrix;
 
 /* Message describing the calling thread's most recent failure ("" if none). */
@@ -140,14 +113,12 @@ int argcsr_version(void);
  *   desired_chunk_size >= 1
  *   n_groups, n_slots out: group count and slot count (sum c_g*block_dim)
  *   n_heavy           out (may be NULL): length of the heavy_groups schedule
- *   n_runs            out (may be NULL): number of runs (the runs schedule
- *                     has n_runs + 1 entries)
  * Errors: EINVAL (bad sizes, row_ptr not starting at 0 or decreasing),
  * EOVERFLOW (slot count > INT32_MAX).  Allocates only host memory.
  */
 int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
                 int32_t desired_chunk_size, int32_t* n_groups, int64_t* n_slots,
-                int32_t* n_heavy, int32_t* n_runs);
+                int32_t* n_heavy);
 
 /*
  * argcsr_convert -- CSR -> ARG-CSR on the GPU (Sec. 3, all four steps).
@@ -160,9 +131,9 @@ int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
  *   col           device int32[nnz], 0 <= col < n_cols
  *   val           device double[nnz]
  *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, dtype,
- *                     n_groups, n_slots, n_heavy and n_runs as returned by
+ *                     n_groups, n_slots and n_heavy as returned by
  *                     argcsr_plan, and the device buffers of those sizes
- *                     (heavy_groups and runs may be NULL);
+ *                     (heavy_groups may be NULL);
  *                 out: nnz, heavy_chunk, and the buffers filled.
  * Reduced dtypes round each value to nearest-even directly from FP64.
  * Synchronous: waits for its kernels (it reads back a validation flag).
@@ -210,13 +181,11 @@ typedef struct argcsr_batch argcsr_batch;
 
 /*
  * argcsr_batch_create -- prepares y_m = A_m x_m for m = 0..n_mats-1 as ONE
- * persistent kernel over a global queue of work items (groups with long
- * chunk loops go to whole workgroups first; the others, cut into runs as in
- * argcsr_run_info, go to single waves in matrix and row order), and captures
- * [queue reset, kernel] in a hipGraph.  The same per-group computation as
- * argcsr_spmv is used, so each y_m is bitwise identical to argcsr_spmv on
- * A_m alone when A_m has its heavy_groups schedule (or has no heavy group).
- * The matrices' own runs tables are not needed.
+ * persistent kernel over a global queue of (matrix, group) work items
+ * (groups with long chunk loops go to whole workgroups first, the others to
+ * single waves in matrix and row order), and captures [queue reset, kernel] in a
+ * hipGraph.  The same per-group computation as argcsr_spmv is used, so each
+ * y_m is bitwise identical to argcsr_spmv on A_m alone.
  *   mats   host array of n_mats converted matrices, all of one dtype; block
  *          dims may differ (64, 128, 256)
  *   xs, ys host arrays of n_mats device pointers (x_m, y_m as for
@@ -234,8 +203,7 @@ int argcsr_batch_graph_launch(argcsr_batch* b, void* stream);
 /* Runs the batch on `stream` with ordinary kernel launches (asynchronous). */
 int argcsr_batch_launch(argcsr_batch* b, void* stream);
 
-/* Work-list sizes (runs for single waves, heavy groups) and persistent grid
- * of a batch (any pointer may be NULL). */
+/* Work-list sizes and persistent grid of a batch (any pointer may be NULL). */
 int argcsr_batch_info(const argcsr_batch* b, int32_t* n_items, int32_t* n_heavy, int32_t* grid);
 
 /* Waits for the device, then frees the batch (NULL is a no-op). */

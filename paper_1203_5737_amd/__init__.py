@@ -90,39 +90,36 @@ class ArgCsrMatrix:
     heavy_groups: Optional[torch.Tensor] = None   # int32 [n_heavy] launch schedule
     n_heavy: int = 0
     heavy_chunk: int = 0
-    runs: Optional[torch.Tensor] = None           # int32 [n_runs + 1, 4] launch schedule
-    n_runs: int = 0
 
     def desc(self) -> MatrixDesc:
         return MatrixDesc(self.n_rows, self.n_cols, self.block_dim, self.desired_chunk_size,
                           self.dtype, self.n_groups, self.nnz, self.n_slots,
                           _ptr(self.groups), _ptr(self.threads_mapping), _ptr(self.columns),
                           _ptr(self.values), self.n_heavy, self.heavy_chunk,
-                          _ptr(self.heavy_groups), self.n_runs, 0, _ptr(self.runs))
+                          _ptr(self.heavy_groups))
 
     def nbytes(self) -> int:
         ts = [self.groups, self.threads_mapping, self.columns, self.values]
-        ts += [t for t in (self.heavy_groups, self.runs) if t is not None]
+        if self.heavy_groups is not None:
+            ts.append(self.heavy_groups)
         return sum(t.numel() * t.element_size() for t in ts)
 
 
 def plan(row_ptr_host, block_dim: int, desired_chunk_size: int):
-    """(n_groups, n_slots, n_heavy, n_runs) of the converted matrix (host only)."""
+    """(n_groups, n_slots, n_heavy) of the converted matrix (host only)."""
     rp = np.ascontiguousarray(np.asarray(row_ptr_host, dtype=np.int32))
-    g, s, h, r = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
     check(lib().argcsr_plan(int(rp.shape[0] - 1), rp.ctypes.data_as(ctypes.c_void_p),
                             int(block_dim), int(desired_chunk_size), ctypes.byref(g),
-                            ctypes.byref(s), ctypes.byref(h), ctypes.byref(r)), "argcsr_plan")
-    return g.value, s.value, h.value, r.value
+                            ctypes.byref(s), ctypes.byref(h)), "argcsr_plan")
+    return g.value, s.value, h.value
 
 
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
-            dtype: int = F64, stream=None, schedule: bool = True,
-            runs: bool = True) -> ArgCsrMatrix:
+            dtype: int = F64, stream=None, schedule: bool = True) -> ArgCsrMatrix:
     """CSR -> ARG-CSR on the GPU (argcsr_convert); allocates the result.
-    `schedule` also builds the heavy-group launch schedule, `runs` the run
-    schedule (several short groups per wave)."""
-    G, S, H, R = plan(A.row_ptr_host, block_dim, desired_chunk_size)
+    `schedule` also builds the heavy-group launch schedule."""
+    G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size)
     dev = A.row_ptr.device
     out = ArgCsrMatrix(
         A.n_rows, A.n_cols, int(block_dim), int(desired_chunk_size), int(dtype), G, A.nnz, S,
@@ -131,9 +128,7 @@ def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
         torch.empty(S, dtype=torch.int32, device=dev),
         torch.empty(S, dtype=_STORAGE[dtype], device=dev),
         torch.empty(H, dtype=torch.int32, device=dev) if schedule else None,
-        H if schedule else 0, 0,
-        torch.empty((R + 1, 4), dtype=torch.int32, device=dev) if runs else None,
-        R if runs else 0)
+        H if schedule else 0)
     d = out.desc()
     if schedule and H == 0:
         d.heavy_groups = None
@@ -145,10 +140,6 @@ def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
     out.heavy_chunk = int(d.heavy_chunk)
     if not schedule:
         out.n_heavy = 0
-    if runs:
-        out.n_runs = int(d.n_runs)
-    if out.n_runs == 0:
-        out.runs = None
     return out
 
 

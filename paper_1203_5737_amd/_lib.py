@@ -41,9 +41,7 @@ class MatrixDesc(ctypes.Structure):
                 ("groups", ctypes.c_void_p), ("threads_mapping", ctypes.c_void_p),
                 ("columns", ctypes.c_void_p), ("values", ctypes.c_void_p),
                 ("n_heavy", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
-                ("heavy_groups", ctypes.c_void_p),
-                ("n_runs", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("runs", ctypes.c_void_p)]
+                ("heavy_groups", ctypes.c_void_p)]
 
 
 class TuneResult(ctypes.Structure):
@@ -89,7 +87,7 @@ SIGNATURES = {
     "argcsr_last_error": (ctypes.c_char_p, []),
     "argcsr_version": (ctypes.c_int, []),
     "argcsr_plan": (ctypes.c_int, [i32, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
-                                   ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+                                   ctypes.POINTER(i32)]),
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),
     "argcsr_csr_spmv": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, vp, vp, vp]),

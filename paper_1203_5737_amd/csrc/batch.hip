@@ -1,10 +1,10 @@
 // Many ARG-CSR matrices in one persistent launch over a global work queue.
 //
-// Heavy groups (a long chunk loop, see schedule.hpp) are taken by whole
-// workgroups from one queue and split over their waves; all other groups,
-// cut into runs by the rule of argcsr_run_info, are taken by single waves a
-// run at a time, kGrab runs per queue access, from per-XCD segments of a
-// second list in matrix and row order (workqueue.hpp).  Queue counters are zeroed by a one-block kernel enqueued
+// Work items are (matrix, group) pairs.  Heavy groups (a long chunk loop,
+// see schedule.hpp) are taken by whole workgroups from one queue and split
+// over their waves; all other groups are taken by single waves, kGrab at a
+// time, from per-XCD segments of a second list in matrix and row order
+// (workqueue.hpp).  Queue counters are zeroed by a one-block kernel enqueued
 // before every launch (no memset, so the pair can be captured in a hipGraph).  Each group is computed by the
 // same deterministic routine as argcsr_spmv, so the results do not depend on
 // which wave takes which item.
@@ -27,15 +27,14 @@ constexpr int kGrab = 4;                 // normal items taken per queue access
 constexpr int kMaxBlocksPerCu = 8;       // persistent grid: as many workgroups as fit, <= 8 per CU
 
 template <int DT, int W, int U>
-__device__ __forceinline__ void run_item(const BatchMat& m, const RunItem& it, int32_t* ends,
-                                         int32_t* stage) {
+__device__ __forceinline__ void run_item(const BatchMat& m, int32_t g, int32_t* ends) {
   using Vt = Val<DT>;
-  const argcsr_run_info run{it.first_group, it.offset, it.first_row, 0};
-  const argcsr_run_info next{it.end_group, it.end_offset, it.end_row, 0};
-  spmv_run<DT, W, U>(run, next, m.groups, m.tm, m.columns,
-                     static_cast<const typename Vt::storage*>(m.values),
-                     static_cast<const typename Vt::acc*>(m.x),
-                     static_cast<typename Vt::acc*>(m.y), ends, stage);
+  const argcsr_group_info gi = m.groups[g];
+  spmv_group<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, m.tm, m.columns,
+                       static_cast<const typename Vt::storage*>(m.values),
+                       XGather<typename Vt::acc>(static_cast<const typename Vt::acc*>(m.x),
+                                                 m.n_cols),
+                       m.serial != 0, static_cast<typename Vt::acc*>(m.y), ends);
 }
 
 template <int DT, int W, int U>
@@ -46,17 +45,17 @@ __device__ __forceinline__ void run_heavy(const BatchMat& m, int32_t g, int32_t*
   const argcsr_group_info gi = m.groups[g];
   spmv_group_split<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, m.tm, m.columns,
                              static_cast<const typename Vt::storage*>(m.values),
-                             static_cast<const A*>(m.x), static_cast<A*>(m.y), ends,
+                             XGather<A>(static_cast<const A*>(m.x), m.n_cols), m.serial != 0,
+                             static_cast<A*>(m.y), ends,
                              reinterpret_cast<A(*)[64 * W]>(part_mem), wv);
 }
 
 template <int DT>
 __global__ __launch_bounds__(kSpmvWaves * 64) void batch_spmv_kernel(
     const BatchMat* __restrict__ mats, const int2* __restrict__ heavy, int32_t n_heavy,
-    const RunItem* __restrict__ items, int32_t n_items, WorkQueues* q) {
+    const int2* __restrict__ items, int32_t n_items, WorkQueues* q) {
   using A = typename Val<DT>::acc;
   __shared__ int32_t ends[kSpmvWaves][256];
-  __shared__ int32_t stage[kSpmvWaves][kRunSlots];
   __shared__ A part_mem[(kSpmvWaves - 1) * 256];
   __shared__ int32_t grabbed;
   const int wv = wave_uniform(int(threadIdx.x >> 6));
@@ -78,17 +77,17 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void batch_spmv_kernel(
     __syncthreads();                      // part_mem / ends free for the next heavy item
   }
 
-  // all other groups: each wave takes kGrab runs at a time
+  // all other groups: each wave takes kGrab items at a time
   QueueCursor cursor{int(blockIdx.x % kQueues), 0};
   int32_t i0, i1;
   while (cursor.take(q, n_items, kGrab, &i0, &i1)) {
     for (int32_t i = i0; i < i1; ++i) {
-      const RunItem it = items[i];
-      const BatchMat m = mats[it.mat];
+      const int2 it = items[i];
+      const BatchMat m = mats[it.x];
       switch (m.block_dim) {
-        case 64: run_item<DT, 1, 8>(m, it, ends[wv], stage[wv]); break;
-        case 128: run_item<DT, 2, 4>(m, it, ends[wv], stage[wv]); break;
-        default: run_item<DT, 4, 2>(m, it, ends[wv], stage[wv]); break;
+        case 64: run_item<DT, 1, 8>(m, it.y, ends[wv]); break;
+        case 128: run_item<DT, 2, 4>(m, it.y, ends[wv]); break;
+        default: run_item<DT, 4, 2>(m, it.y, ends[wv]); break;
       }
     }
   }
@@ -148,7 +147,7 @@ int build_batch(int32_t n, const argcsr_matrix* mats, const void* const* xs, voi
   b->n_mats = n;
   b->dtype = mats[0].dtype;
   std::vector<BatchMat> hm(n);
-  std::vector<RunItem> items;
+  std::vector<int2> items;
   std::vector<int2> heavy;
   std::vector<argcsr_group_info> g;
   for (int32_t m = 0; m < n; ++m) {
@@ -160,26 +159,17 @@ int build_batch(int32_t n, const argcsr_matrix* mats, const void* const* xs, voi
     if (A.n_groups > 0 && (!xs[m] || !ys[m]))
       return fail(ARGCSR_EINVAL, "matrix %d: x or y is NULL", m);
     hm[m] = BatchMat{A.groups, A.threads_mapping, A.columns, A.values, xs[m], ys[m],
-                     A.block_dim, A.n_groups};
+                     A.block_dim, A.n_groups, A.n_cols,
+                     serial_gathers(A.dtype == ARGCSR_F64 ? 8 : A.dtype == ARGCSR_F32 ? 4 : 2,
+                                    A.block_dim, A.n_slots, A.n_groups) ? 1 : 0};
     g.resize(size_t(A.n_groups));
     if (A.n_groups > 0)
       ARGCSR_HIP(hipMemcpy(g.data(), A.groups, sizeof(argcsr_group_info) * g.size(),
                            hipMemcpyDeviceToHost));
     const int32_t hc = heavy_chunk_for(A.block_dim, A.n_slots, A.n_groups);
-    for (int32_t k = 0; k < A.n_groups;) {
-      if (g[k].chunk_size > hc) {
-        heavy.push_back(int2{m, k});
-        ++k;
-        continue;
-      }
-      int32_t e = k + 1;   // the run opened by group k ends where the next one opens
-      while (e < A.n_groups && !opens_run(e, g[e - 1].offset, g[e - 1].chunk_size, g[e].offset,
-                                          g[e].chunk_size, hc))
-        ++e;
-      const argcsr_group_info& last = g[e - 1];
-      items.push_back(RunItem{m, k, e, g[k].offset, last.offset + last.chunk_size * A.block_dim,
-                              g[k].first_row, last.first_row + last.size, 0});
-      k = e;
+    for (int32_t k = 0; k < A.n_groups; ++k) {
+      if (g[k].chunk_size > hc) heavy.push_back(int2{m, k});
+      else items.push_back(int2{m, k});
     }
   }
   // matrix-major, row order: waves working at the same time gather from the
@@ -188,12 +178,12 @@ int build_batch(int32_t n, const argcsr_matrix* mats, const void* const* xs, voi
   b->n_heavy = int32_t(heavy.size());
 
   ARGCSR_HIP(hipMalloc(&b->d_mats, sizeof(BatchMat) * size_t(std::max(n, 1))));
-  ARGCSR_HIP(hipMalloc(&b->d_items, sizeof(RunItem) * std::max<size_t>(items.size(), 1)));
+  ARGCSR_HIP(hipMalloc(&b->d_items, sizeof(int2) * std::max<size_t>(items.size(), 1)));
   ARGCSR_HIP(hipMalloc(&b->d_heavy, sizeof(int2) * std::max<size_t>(heavy.size(), 1)));
   ARGCSR_HIP(hipMalloc(&b->queue, sizeof(WorkQueues)));
   ARGCSR_HIP(hipMemcpy(b->d_mats, hm.data(), sizeof(BatchMat) * size_t(n), hipMemcpyHostToDevice));
   if (!items.empty())
-    ARGCSR_HIP(hipMemcpy(b->d_items, items.data(), sizeof(RunItem) * items.size(),
+    ARGCSR_HIP(hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(),
                          hipMemcpyHostToDevice));
   if (!heavy.empty())
     ARGCSR_HIP(hipMemcpy(b->d_heavy, heavy.data(), sizeof(int2) * heavy.size(),

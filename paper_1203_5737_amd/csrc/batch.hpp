@@ -19,17 +19,8 @@ struct BatchMat {
   void* y;
   int32_t block_dim;
   int32_t n_groups;
-};
-
-// A run of short groups of one matrix (see argcsr_run_info), taken by one
-// wave: groups [first_group, end_group), slots [offset, end_offset), rows
-// [first_row, end_row).
-struct RunItem {
-  int32_t mat;
-  int32_t first_group, end_group;
-  int32_t offset, end_offset;
-  int32_t first_row, end_row;
-  int32_t pad;
+  int32_t n_cols;
+  int32_t serial;            // gather mode (serial_gathers)
 };
 
 }  // namespace argcsr
@@ -37,12 +28,12 @@ struct RunItem {
 struct argcsr_batch {
   int32_t n_mats = 0;
   int32_t dtype = 0;
-  int32_t n_items = 0;       // runs of groups processed by one wave
+  int32_t n_items = 0;       // groups processed by one wave
   int32_t n_heavy = 0;       // groups processed by a whole workgroup
   int32_t grid = 0;          // persistent workgroups
   argcsr::BatchMat* d_mats = nullptr;
-  argcsr::RunItem* d_items = nullptr;   // matrix-major, row order
-  int2* d_heavy = nullptr;   // (matrix, group)
+  int2* d_items = nullptr;   // (matrix, group), longest first
+  int2* d_heavy = nullptr;
   void* queue = nullptr;     // two int32 counters
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;

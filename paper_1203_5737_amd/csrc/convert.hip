@@ -35,7 +35,6 @@ struct Status {                       // device-side results read back by the ho
   int pad;
   long long total_slots;
   long long total_heavy;
-  long long total_runs;
 };
 
 __global__ __launch_bounds__(256) void validate_columns_kernel(
@@ -205,53 +204,6 @@ __global__ __launch_bounds__(kScanBlock) void heavy_scatter_kernel(
       heavy[pos++] = int32_t(base + i);
 }
 
-// Run schedule: group g opens a run by opens_run(); per-tile counts, then
-// each tile writes the runs it opens in ascending order, and the first
-// thread writes the sentinel entry n_runs.
-__device__ __forceinline__ bool group_opens_run(const argcsr_group_info* groups, int64_t g,
-                                                int32_t heavy_chunk) {
-  const argcsr_group_info cur = groups[g];
-  const argcsr_group_info prev = g > 0 ? groups[g - 1] : argcsr_group_info{0, 0, 0, 0};
-  return opens_run(int32_t(g), prev.offset, prev.chunk_size, cur.offset, cur.chunk_size,
-                   heavy_chunk);
-}
-
-__global__ __launch_bounds__(kScanBlock) void run_count_kernel(
-    const argcsr_group_info* __restrict__ groups, int32_t n_groups, int32_t heavy_chunk,
-    int64_t* __restrict__ tile_sums) {
-  int64_t s = 0;
-  const int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n_groups) s += group_opens_run(groups, base + i, heavy_chunk);
-  int64_t total;
-  (void)block_exclusive_scan(s, &total);
-  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kScanBlock) void run_scatter_kernel(
-    const argcsr_group_info* __restrict__ groups, int32_t n_groups, int32_t heavy_chunk,
-    const int64_t* __restrict__ tile_base, int32_t n_runs, int32_t n_slots, int32_t n_rows,
-    argcsr_run_info* __restrict__ runs) {
-  const int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
-  bool opens[kScanItems];
-  int64_t s = 0;
-  for (int i = 0; i < kScanItems; ++i) {
-    opens[i] = base + i < n_groups && group_opens_run(groups, base + i, heavy_chunk);
-    s += opens[i];
-  }
-  int64_t total;
-  int64_t pos = tile_base[blockIdx.x] + block_exclusive_scan(s, &total);
-  for (int i = 0; i < kScanItems; ++i) {
-    if (opens[i]) {
-      const argcsr_group_info gi = groups[base + i];
-      runs[pos++] = argcsr_run_info{int32_t(base + i), gi.offset, gi.first_row,
-                                    gi.chunk_size > heavy_chunk ? ARGCSR_RUN_HEAVY : 0};
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    runs[n_runs] = argcsr_run_info{n_groups, n_slots, n_rows, 0};
-}
-
 // Step 4, one wave per group.  For every chunk k the wave first records in
 // LDS where its elements start in the CSR arrays and how many there are
 // (0 for free chunks), then writes all c*T slots in slot order.
@@ -344,7 +296,6 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   out->heavy_chunk = heavy_chunk_for(T, out->n_slots, G);
   if (G == 0) {
     out->n_heavy = 0;
-    out->n_runs = 0;   // the caller's runs buffer (1 entry) is left untouched
     if (out->n_slots != 0) return fail(ARGCSR_EINVAL, "out->n_slots must be 0 for an empty matrix");
     return ARGCSR_OK;
   }
@@ -355,12 +306,11 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
   void* ws = nullptr;
-  rc = device_workspace(sizeof(Status) + 3 * sizeof(int64_t) * size_t(n_tiles), &ws);
+  rc = device_workspace(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), &ws);
   if (rc) return rc;
   Status* st = static_cast<Status*>(ws);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
   int64_t* heavy_tiles = tile_sums + n_tiles;
-  int64_t* run_tiles = heavy_tiles + n_tiles;
   // uses the caller's slot count; it is checked against the device total
   // before anything is written to the caller's heavy_groups buffer
   const int32_t heavy_chunk = out->heavy_chunk;
@@ -383,8 +333,6 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   offsets_apply_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, T, tile_sums);
   heavy_count_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, heavy_chunk, heavy_tiles);
   tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(heavy_tiles, n_tiles, &st->total_heavy);
-  run_count_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, heavy_chunk, run_tiles);
-  tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(run_tiles, n_tiles, &st->total_runs);
   ARGCSR_HIP(hipGetLastError());
 
   Status host_st{};
@@ -400,18 +348,10 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   if (out->heavy_groups && host_st.total_heavy != out->n_heavy)
     return fail(ARGCSR_EINVAL, "out->n_heavy = %d but the matrix has %lld heavy groups",
                 out->n_heavy, host_st.total_heavy);
-  if (out->runs && host_st.total_runs != out->n_runs)
-    return fail(ARGCSR_EINVAL, "out->n_runs = %d but the matrix has %lld runs", out->n_runs,
-                host_st.total_runs);
   out->n_heavy = int32_t(host_st.total_heavy);
-  out->n_runs = int32_t(host_st.total_runs);
   if (out->heavy_groups && out->n_heavy > 0)
     heavy_scatter_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, heavy_chunk, heavy_tiles,
                                                         out->heavy_groups);
-  if (out->runs)
-    run_scatter_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, heavy_chunk, run_tiles,
-                                                      out->n_runs, int32_t(out->n_slots), n_rows,
-                                                      out->runs);
 
   switch (out->dtype) {
     case ARGCSR_F64: launch_fill<ARGCSR_F64>(wave_blocks, s, row_ptr, col, val, out); break;

@@ -28,6 +28,8 @@ struct MatWork {
   const void* x;
   void* y;
   int32_t block_dim;
+  int32_t n_cols;
+  int32_t serial;                     // gather mode (serial_gathers)
   int32_t heavy_chunk;                // groups with chunk_size above are in `heavy`
   int32_t group_begin;                // prefix over the launch's matrices
   int32_t heavy_begin;
@@ -73,22 +75,22 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
     const MatWork& w = mw[m];
     const argcsr_group_info gi = w.groups[w.heavy[h - hbeg[m]]];
     const S* vals = static_cast<const S*>(w.values);
-    const A* x = static_cast<const A*>(w.x);
+    const XGather<A> x(static_cast<const A*>(w.x), w.n_cols);
     A* y = static_cast<A*>(w.y);
     switch (w.block_dim) {
       case 64:
         spmv_group_split<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
-                                   w.columns, vals, x, y, ends[0],
+                                   w.columns, vals, x, w.serial != 0, y, ends[0],
                                    reinterpret_cast<A(*)[64]>(part_mem), wv);
         break;
       case 128:
         spmv_group_split<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
-                                   w.columns, vals, x, y, ends[0],
+                                   w.columns, vals, x, w.serial != 0, y, ends[0],
                                    reinterpret_cast<A(*)[128]>(part_mem), wv);
         break;
       default:
         spmv_group_split<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
-                                   w.columns, vals, x, y, ends[0],
+                                   w.columns, vals, x, w.serial != 0, y, ends[0],
                                    reinterpret_cast<A(*)[256]>(part_mem), wv);
         break;
     }
@@ -105,20 +107,20 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
       const argcsr_group_info gi = w.groups[i - gbeg[m]];
       if (gi.chunk_size > w.heavy_chunk) continue;     // done by a heavy workgroup
       const S* vals = static_cast<const S*>(w.values);
-      const A* x = static_cast<const A*>(w.x);
+      const XGather<A> x(static_cast<const A*>(w.x), w.n_cols);
       A* y = static_cast<A*>(w.y);
       switch (w.block_dim) {
         case 64:
           spmv_group<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                               vals, x, y, ends[wv]);
+                               vals, x, w.serial != 0, y, ends[wv]);
           break;
         case 128:
           spmv_group<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                               vals, x, y, ends[wv]);
+                               vals, x, w.serial != 0, y, ends[wv]);
           break;
         default:
           spmv_group<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                               vals, x, y, ends[wv]);
+                               vals, x, w.serial != 0, y, ends[wv]);
           break;
       }
     }

@@ -83,8 +83,7 @@ int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
 
 extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
                            int32_t block_dim, int32_t desired_chunk_size,
-                           int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy,
-                           int32_t* n_runs) {
+                           int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy) {
   using namespace argcsr;
   clear_error();
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
@@ -112,21 +111,11 @@ extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
   int64_t slots = 0;
   for (size_t g = 0; g < G; ++g) slots += int64_t(chunk[g]) * block_dim;
   const int32_t heavy_chunk = heavy_chunk_for(block_dim, slots, (int32_t)groups.size());
-  int32_t heavy = 0, runs = 0;
-  int64_t offset = 0, offset_prev = 0;
-  for (size_t g = 0; g < G; ++g) {
-    heavy += chunk[g] > heavy_chunk;
-    // offsets beyond INT32_MAX are rejected below; the count is then unused
-    const int32_t o = int32_t(std::min<int64_t>(offset, INT32_MAX));
-    const int32_t op = int32_t(std::min<int64_t>(offset_prev, INT32_MAX));
-    runs += opens_run(int32_t(g), op, g ? chunk[g - 1] : 0, o, chunk[g], heavy_chunk);
-    offset_prev = offset;
-    offset += int64_t(chunk[g]) * block_dim;
-  }
+  int32_t heavy = 0;
+  for (int32_t c : chunk) heavy += c > heavy_chunk;
   *n_groups = (int32_t)groups.size();
   *n_slots = slots;
   if (n_heavy) *n_heavy = heavy;
-  if (n_runs) *n_runs = runs;
   if (slots > INT32_MAX)
     return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", (long long)slots);
   return ARGCSR_OK;

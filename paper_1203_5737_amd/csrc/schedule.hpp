@@ -3,11 +3,11 @@
 
 #include <cstdint>
 
-#include "argcsr.h"
-
 namespace argcsr {
 
 constexpr int kSpmvWaves = 4;   // waves per SpMV workgroup
+// x is gathered through 32-bit buffer offsets; a column -1 must land past the end
+constexpr int64_t kMaxVectorBytes = 0xFFFFFFF0ll;
 constexpr int kLoadSteps = 8;   // chunk steps loaded ahead per lane (U * W)
 
 // A group is "heavy" when one wave would need many more rounds of loads for
@@ -32,16 +32,18 @@ __host__ __device__ constexpr int32_t heavy_chunk_for(int32_t block_dim, int64_t
   return by_rounds > by_mean ? by_rounds : int32_t(by_mean < INT32_MAX ? by_mean : INT32_MAX);
 }
 
-// Runs (argcsr_run_info): group g opens a run iff it is the first group, it
-// or its predecessor is heavy, or its offset lies in another window of
-// ARGCSR_RUN_SLOTS slots than its predecessor's.  One wave takes a run: its
-// slots are contiguous, so its chunk loads cover several short groups at once.
-constexpr int32_t kRunSlots = ARGCSR_RUN_SLOTS;
-static_assert(kRunSlots == kLoadSteps * 64, "a run window is one batch of loads");
-__host__ __device__ constexpr bool opens_run(int32_t g, int32_t offset_prev, int32_t chunk_prev,
-                                             int32_t offset, int32_t chunk, int32_t heavy_chunk) {
-  return g == 0 || chunk > heavy_chunk || chunk_prev > heavy_chunk ||
-         offset / kRunSlots != offset_prev / kRunSlots;
+// Gather mode of the chunk loop: serial (one gather at a time, each FMA
+// right after it) for 8-byte values when the mean chunk loop spans at least
+// two load batches -- there the value stream is the limit and the paced
+// gathers measured faster (27-point stencil, FP64: 140 vs 149 us) -- and
+// batched (all gathers of a batch in flight) otherwise (power-law rows,
+// FP64: 81 vs 86 us; every FP32 case).
+__host__ __device__ constexpr bool serial_gathers(int32_t value_bytes, int32_t block_dim,
+                                                  int64_t n_slots, int32_t n_groups) {
+  if (value_bytes != 8 || n_groups <= 0 || block_dim <= 0) return false;
+  const int64_t steps_per_batch = block_dim >= kLoadSteps * 64 ? 1 : kLoadSteps * 64 / block_dim;
+  const int64_t mean_chunk = n_slots / (int64_t(n_groups) * block_dim);
+  return mean_chunk >= 2 * steps_per_batch;
 }
 
 }  // namespace argcsr

@@ -195,6 +195,8 @@ int admit(argcsr_server* s, Request* r) {
   int rc = check_row_ptr(q.n_rows, q.row_ptr);
   if (rc) return rc;
   if (q.n_rows < 0 || q.n_cols < 0) return fail(ARGCSR_EINVAL, "negative dimension");
+  if (int64_t(q.n_cols) * 8 > kMaxVectorBytes)
+    return fail(ARGCSR_EUNSUPPORTED, "x of %d columns exceeds the gather range", q.n_cols);
   const int64_t nnz = q.n_rows > 0 ? q.row_ptr[q.n_rows] : 0;
   if (nnz > 0 && (!q.col || !q.val)) return fail(ARGCSR_EINVAL, "NULL CSR arrays");
   int32_t T = s->cfg.block_dim > 0 ? s->cfg.block_dim : 64;
@@ -211,7 +213,7 @@ int admit(argcsr_server* s, Request* r) {
   A.block_dim = T;
   A.desired_chunk_size = D;
   A.dtype = ARGCSR_F64;
-  rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, &A.n_groups, &A.n_slots, &A.n_heavy, nullptr);
+  rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, &A.n_groups, &A.n_slots, &A.n_heavy);
   if (rc) return rc;
   std::vector<size_t> sizes;
   auto grab = [&](size_t bytes) -> void* {
@@ -346,6 +348,8 @@ void fill_matwork(MatWork& w, const argcsr_matrix& A, const void* values, const 
   w.x = x;
   w.y = y;
   w.block_dim = A.block_dim;
+  w.n_cols = A.n_cols;
+  w.serial = serial_gathers(values == A.values ? 8 : 4, A.block_dim, A.n_slots, A.n_groups);
   w.heavy_chunk = A.heavy_groups ? A.heavy_chunk : INT32_MAX;
   w.group_begin = groups;
   w.heavy_begin = heavy;

@@ -2,8 +2,7 @@
 // partial sums, then per-row sums of the partial sums).
 //
 // Mapping to CDNA4 (a wave has 64 lanes):
-//   - one wave per group, or per run of consecutive short groups (the runs
-//     schedule); with T = 64*W chunks per group, lane i owns chunks
+//   - one wave per group; with T = 64*W chunks per group, lane i owns chunks
 //     i, i+64, ..., i+64*(W-1) ("sub-blocks" w = 0..W-1).  A group's slots
 //     for step j are T consecutive values/columns, so every load is a
 //     contiguous, fully coalesced wave-wide access (the paper's column-major
@@ -33,21 +32,14 @@ void launch(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
   const bool sched = A->heavy_groups != nullptr && A->n_heavy > 0;
   const int32_t n_heavy = sched ? A->n_heavy : 0;
   const int32_t heavy_chunk = sched ? A->heavy_chunk : INT32_MAX;
-  if (A->runs != nullptr && A->n_runs > 0) {
-    const int blocks = n_heavy + (A->n_runs + kSpmvWaves - 1) / kSpmvWaves;
-    argcsr_spmv_runs_kernel<DT, W, U><<<blocks, kSpmvWaves * 64, 0, s>>>(
-        A->groups, A->runs, A->n_runs, A->threads_mapping, A->columns,
-        static_cast<const typename Vt::storage*>(A->values),
-        static_cast<const typename Vt::acc*>(x), static_cast<typename Vt::acc*>(y),
-        A->heavy_groups, n_heavy);
-    return;
-  }
   const int blocks = n_heavy + (A->n_groups + kSpmvWaves - 1) / kSpmvWaves;
+  const bool serial = serial_gathers(int32_t(sizeof(typename Vt::storage)), A->block_dim,
+                                     A->n_slots, A->n_groups);
   argcsr_spmv_kernel<DT, W, U><<<blocks, kSpmvWaves * 64, 0, s>>>(
       A->groups, A->n_groups, A->threads_mapping, A->columns,
       static_cast<const typename Vt::storage*>(A->values),
-      static_cast<const typename Vt::acc*>(x), static_cast<typename Vt::acc*>(y),
-      A->heavy_groups, n_heavy, heavy_chunk);
+      static_cast<const typename Vt::acc*>(x), A->n_cols, static_cast<typename Vt::acc*>(y),
+      A->heavy_groups, n_heavy, heavy_chunk, serial ? 1 : 0);
 }
 
 template <int DT>
@@ -71,14 +63,15 @@ int check_matrix(const argcsr_matrix* A) {
   if (A->dtype < ARGCSR_F64 || A->dtype > ARGCSR_F16)
     return fail(ARGCSR_EINVAL, "unknown dtype %d", A->dtype);
   if (A->n_slots > INT32_MAX) return fail(ARGCSR_EOVERFLOW, "n_slots exceeds INT32_MAX");
+  if (int64_t(A->n_cols) * (A->dtype == ARGCSR_F64 ? 8 : 4) > kMaxVectorBytes)
+    return fail(ARGCSR_EUNSUPPORTED, "x of %d columns exceeds the %lld-byte gather range",
+                A->n_cols, (long long)kMaxVectorBytes);
   if (A->n_groups > 0 && (!A->groups || !A->threads_mapping || !A->columns || !A->values))
     return fail(ARGCSR_EINVAL, "NULL device buffer in matrix descriptor");
   if (A->heavy_groups && (A->n_heavy < 0 || A->n_heavy > A->n_groups ||
                           A->heavy_chunk != heavy_chunk_for(A->block_dim, A->n_slots,
                                                             A->n_groups)))
     return fail(ARGCSR_EINVAL, "heavy-group schedule does not match the matrix");
-  if (A->runs && (A->n_runs < 1 || A->n_runs > A->n_groups))
-    return fail(ARGCSR_EINVAL, "run schedule does not match the matrix");
   return ARGCSR_OK;
 }
 

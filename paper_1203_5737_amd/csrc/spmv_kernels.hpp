@@ -11,6 +11,36 @@
 
 namespace argcsr {
 
+// Word 3 of a gfx9 buffer descriptor: 32-bit data format, no swizzle.  With
+// stride 0 the hardware range check returns 0 for any load at or past
+// num_records bytes, so out-of-range lanes need no branch.
+constexpr int32_t kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), int16_t(0), int32_t(bytes),
+                                           kBufferWord3);
+}
+
+// Gathers x[c] as raw buffer loads: a lane that must not gather asks for
+// column -1, whose byte offset (uint32)(-1)*sizeof(A) lies past the end of
+// x, and reads 0.  No branch guards the loads, so all gathers of a batch are
+// in flight before the first wait.  Requires n_cols * sizeof(A) < 2^32 - 16
+// (checked on the host).
+template <typename A>
+struct XGather {
+  __amdgpu_buffer_rsrc_t rsrc;
+  const A* xp;
+  __device__ __forceinline__ XGather(const A* x, int32_t n_cols)
+      : rsrc(buffer_rsrc(x, uint32_t(n_cols) * uint32_t(sizeof(A)))), xp(x) {}
+  __device__ __forceinline__ A operator()(int32_t c, bool live) const {
+    const uint32_t off = uint32_t(live ? c : -1) * uint32_t(sizeof(A));
+    if constexpr (sizeof(A) == 8)
+      return __builtin_bit_cast(A, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
+    else
+      return __builtin_bit_cast(A, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off, 0, 0));
+  }
+};
+
 // This lane's threads-mapping entries (rows l = 64*w + lane of the group).
 template <int W>
 __device__ __forceinline__ void load_mapping(int32_t first, int32_t size,
@@ -46,59 +76,100 @@ __device__ __forceinline__ void row_end_mask(const int32_t (&tmv)[W], int32_t* e
 }
 
 // Partial sums of this lane's W chunks over steps j in [j0, j1): value *
-// x[column], stopping at a chunk's first artificial zero (column -1).
+// x[column], stopping at a chunk's first artificial zero (column -1).  A
+// batch of U steps is loaded at once.  Its gathers are either all put in
+// flight before the FMAs (the default), or, with `serial` (wave-uniform),
+// issued one at a time, each followed by its FMA: measured faster for
+// 8-byte values with long chunk loops, where the stream, not the gathers,
+// is the limit (see gather_mode).  The sums are the same in both modes.
 template <int DT, int W, int U>
 __device__ __forceinline__ void chunk_partials(
     int32_t offset, int32_t j0, int32_t j1, const int32_t* __restrict__ columns,
     const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc (&acc)[W]) {
+    const XGather<typename Val<DT>::acc>& gx, bool serial, typename Val<DT>::acc (&acc)[W]) {
   using Vt = Val<DT>;
   using S = typename Vt::storage;
+  using A = typename Vt::acc;
   constexpr int T = 64 * W;
   const int lane = lane_id();
   bool alive[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) { acc[w] = 0; alive[w] = true; }
+  for (int w = 0; w < W; ++w) { acc[w] = A(0); alive[w] = true; }
   const int32_t* cb = columns + offset + lane;
   const S* vb = values + offset + lane;
-  if constexpr (sizeof(S) < 8) {
-    // 4- and 2-byte values: the next U steps are loaded before this batch's x
-    // gathers are issued (double buffering fits the register budget)
-    int32_t cc[U][W];
-    S vv[U][W];
-    auto load = [&](int j, int32_t (&c)[U][W], S (&v)[U][W]) {
+  // steps j .. j+U-1 (steps past j1 read as padding); streamed once:
+  // non-temporal, keeping L2 for the x gathers
+  auto load = [&](int32_t j, int32_t (&c)[U][W], S (&v)[U][W]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        if (j + u < j1) {
+          c[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
+          v[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
+        } else {
+          c[u][w] = -1;
+          v[u][w] = S(0);
+        }
+      }
+    }
+  };
+  // returns whether some chunk has not reached its padding yet
+  auto consume = [&](const int32_t (&c)[U][W], const S (&v)[U][W]) {
+    if (serial) {
+      // one gather at a time, each FMA right after its load
 #pragma unroll
       for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          if (j + u < j1) {   // streamed once: keep L2 for the x gathers
-            c[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
-            v[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
-          } else {
-            c[u][w] = -1;
-            v[u][w] = S(0);
-          }
+          alive[w] = alive[w] && (c[u][w] >= 0);
+          if (alive[w]) acc[w] = __builtin_fma(Vt::load(v[u][w]), gx.xp[c[u][w]], acc[w]);
         }
       }
-    };
+    } else {
+      // which slots are live, then all gathers of the batch, then the FMAs
+      // in step order
+      bool live[U][W];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          alive[w] = alive[w] && (c[u][w] >= 0);
+          live[u][w] = alive[w];
+        }
+      }
+      A xv[U][W];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) xv[u][w] = gx(c[u][w], live[u][w]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const A p = __builtin_fma(Vt::load(v[u][w]), xv[u][w], acc[w]);
+          acc[w] = live[u][w] ? p : acc[w];
+        }
+      }
+    }
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) any |= alive[w];
+    return __ballot(any) != 0;
+  };
+  int32_t cc[U][W];
+  S vv[U][W];
+  if constexpr (sizeof(S) < 8) {
+    // 4- and 2-byte values: the next U steps are loaded before this batch's x
+    // gathers are issued (double buffering fits the register budget)
     if (j0 < j1) load(j0, cc, vv);
     for (int j = j0; j < j1; j += U) {
       int32_t nc[U][W];
       S nv[U][W];
       const bool more = j + U < j1;
       if (more) load(j + U, nc, nv);
-      bool any = false;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          alive[w] = alive[w] && (cc[u][w] >= 0);
-          if (alive[w]) acc[w] = __builtin_fma(Vt::load(vv[u][w]), x[cc[u][w]], acc[w]);
-        }
-      }
-#pragma unroll
-      for (int w = 0; w < W; ++w) any |= alive[w];
-      if (__ballot(any) == 0 || !more) break;     // every chunk reached its padding
+      if (!consume(cc, vv) || !more) break;      // every chunk reached its padding
 #pragma unroll
       for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -109,33 +180,8 @@ __device__ __forceinline__ void chunk_partials(
     // 8-byte values: one batch of U steps at a time (double buffering would
     // cost occupancy)
     for (int j = j0; j < j1; j += U) {
-      int32_t cc[U][W];
-      S vv[U][W];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          if (j + u < j1) {   // streamed once: keep L2 for the x gathers
-            cc[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
-            vv[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
-          } else {
-            cc[u][w] = -1;
-            vv[u][w] = S(0);
-          }
-        }
-      }
-      bool any = false;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          alive[w] = alive[w] && (cc[u][w] >= 0);
-          if (alive[w]) acc[w] = __builtin_fma(Vt::load(vv[u][w]), x[cc[u][w]], acc[w]);
-        }
-      }
-#pragma unroll
-      for (int w = 0; w < W; ++w) any |= alive[w];
-      if (__ballot(any) == 0) break;              // every chunk reached its padding
+      load(j, cc, vv);
+      if (!consume(cc, vv)) break;               // every chunk reached its padding
     }
   }
 }
@@ -183,185 +229,17 @@ __device__ __forceinline__ void spmv_group(
     int32_t first, int32_t size, int32_t offset, int32_t c,
     const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
     const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
+    const XGather<typename Val<DT>::acc>& gx, bool serial, typename Val<DT>::acc* __restrict__ y,
     int32_t* ends) {
   using A = typename Val<DT>::acc;
   int32_t tmv[W];
   load_mapping<W>(first, size, tm, tmv);           // in flight with the first chunk loads
   const int32_t n_mapped = tm[first + size - 1];    // chunks in use; the rest are free
   A acc[W];
-  chunk_partials<DT, W, U>(offset, 0, c, columns, values, x, acc);
+  chunk_partials<DT, W, U>(offset, 0, c, columns, values, gx, serial, acc);
   uint64_t emask[W];
   row_end_mask<W>(tmv, ends, emask);
   row_sums<DT, W>(first, size, n_mapped, emask, acc, y);
-}
-
-// One run of groups (argcsr_run_info) with the calling wave.  The run's
-// slots are contiguous, so its steps are loaded U at a time whatever group
-// they belong to: one batch of loads covers several short groups instead of
-// one wave per short group waiting on its own few loads.  Each chunk's
-// partial sum still runs over its own group's steps in order, stopping at
-// its first artificial zero, and each group's row sums are formed as in
-// spmv_group, so the results are bitwise those of spmv_group.  `stage` is
-// this wave's LDS copy of the run's threads mapping (kRunSlots ints).
-template <int DT, int W, int U>
-__device__ __forceinline__ void spmv_run(
-    const argcsr_run_info& run, const argcsr_run_info& next,
-    const argcsr_group_info* __restrict__ groups, const int32_t* __restrict__ tm,
-    const int32_t* __restrict__ columns, const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
-    int32_t* ends, int32_t* stage) {
-  using Vt = Val<DT>;
-  using S = typename Vt::storage;
-  using A = typename Vt::acc;
-  constexpr int T = 64 * W;
-  constexpr int kStage = kRunSlots / 64;
-  static_assert(kRunSlots % T == 0 && kRunSlots / T <= 64, "run window");
-  const int lane = lane_id();
-  const int32_t n_groups = next.first_group - run.first_group;   // <= kRunSlots / T
-  const int32_t row0 = run.first_row, n_rows = next.first_row - run.first_row;   // <= kRunSlots
-  const int32_t n_steps = (next.offset - run.offset) / T;
-
-  // the run's group table, group i in lane i; lanes beyond hold zeros
-  int32_t g_first = 0, g_size = 0, g_chunk = 0;
-  if (lane < n_groups) {
-    const argcsr_group_info gi = groups[run.first_group + lane];
-    g_first = gi.first_row;
-    g_size = gi.size;
-    g_chunk = gi.chunk_size;
-  }
-  int32_t tmr[kStage];
-#pragma unroll
-  for (int m = 0; m < kStage; ++m) {
-    const int32_t i = m * 64 + lane;
-    tmr[m] = i < n_rows ? __builtin_nontemporal_load(tm + row0 + i) : 0;
-  }
-
-  const int32_t* cb = columns + run.offset + lane;
-  const S* vb = values + run.offset + lane;
-  int32_t cc[U][W];
-  S vv[U][W];
-  auto load = [&](int32_t j, int32_t (&c)[U][W], S (&v)[U][W]) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        if (j + u < n_steps) {   // streamed once: keep L2 for the x gathers
-          c[u][w] = __builtin_nontemporal_load(cb + (j + u) * T + w * 64);
-          v[u][w] = __builtin_nontemporal_load(vb + (j + u) * T + w * 64);
-        } else {
-          c[u][w] = -1;
-          v[u][w] = S(0);
-        }
-      }
-    }
-  };
-  // 4- and 2-byte values: the next batch is loaded before this batch's
-  // products are summed (double buffering fits the register budget; for
-  // 8-byte values it would cost occupancy)
-  constexpr bool kDouble = sizeof(S) < 8;
-  load(0, cc, vv);
-#pragma unroll
-  for (int m = 0; m < kStage; ++m)
-    if (m * 64 + lane < n_rows) stage[m * 64 + lane] = tmr[m];
-  wave_lds_sync();
-
-  // row sums of run group g from the chunk partial sums in acc
-  auto finish = [&](int32_t g, const A (&acc)[W]) {
-    const int32_t first = __builtin_amdgcn_readlane(g_first, g);
-    const int32_t size = __builtin_amdgcn_readlane(g_size, g);
-    const int32_t base = first - row0;
-    int32_t tmv[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const int l = w * 64 + lane;
-      tmv[w] = l < size ? stage[base + l] : 0;
-    }
-    const int32_t n_mapped = stage[base + size - 1];
-    uint64_t emask[W];
-    row_end_mask<W>(tmv, ends, emask);
-    row_sums<DT, W>(first, size, n_mapped, emask, acc, y);
-  };
-
-  A acc[W];
-  bool alive[W];                 // state before the next step of the current group
-#pragma unroll
-  for (int w = 0; w < W; ++w) { acc[w] = A(0); alive[w] = true; }
-  int32_t g = 0;                                            // current group of the run
-  int32_t g_end = __builtin_amdgcn_readlane(g_chunk, 0);    // its end step
-  for (int32_t j = 0;;) {
-    // which slots of the batch a chunk still sums (up to its first -1)
-    bool live[U][W];
-    {
-      int32_t end = g_end, h = g;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          alive[w] = alive[w] && (cc[u][w] >= 0);
-          live[u][w] = alive[w];
-        }
-        if (j + u + 1 == end) {                             // group h ends at this step
-#pragma unroll
-          for (int w = 0; w < W; ++w) alive[w] = true;
-          ++h;
-          end += __builtin_amdgcn_readlane(g_chunk, h);
-        }
-      }
-    }
-    A xv[U][W];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int w = 0; w < W; ++w) xv[u][w] = live[u][w] ? x[cc[u][w]] : A(0);
-    }
-    int32_t nc[U][W];
-    S nv[U][W];
-    if constexpr (kDouble) {
-      if (j + U < n_steps) load(j + U, nc, nv);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (j + u < n_steps) {
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-          if (live[u][w]) acc[w] = __builtin_fma(Vt::load(vv[u][w]), xv[u][w], acc[w]);
-        if (j + u + 1 == g_end) {
-          finish(g, acc);
-#pragma unroll
-          for (int w = 0; w < W; ++w) acc[w] = A(0);
-          ++g;
-          g_end += __builtin_amdgcn_readlane(g_chunk, g);
-        }
-      }
-    }
-    j += U;
-    if (j >= n_steps) break;
-    // every chunk of the unfinished group reached its padding: skip its rest
-    bool any = false;
-#pragma unroll
-    for (int w = 0; w < W; ++w) any |= alive[w];
-    if (__ballot(any) == 0) {
-      finish(g, acc);
-#pragma unroll
-      for (int w = 0; w < W; ++w) { acc[w] = A(0); alive[w] = true; }
-      j = g_end;
-      ++g;
-      g_end += __builtin_amdgcn_readlane(g_chunk, g);
-      if (j >= n_steps) break;
-      load(j, cc, vv);            // (a prefetched batch is dropped)
-      continue;
-    }
-    if constexpr (kDouble) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) { cc[u][w] = nc[u][w]; vv[u][w] = nv[u][w]; }
-      }
-    } else {
-      load(j, cc, vv);
-    }
-  }
 }
 
 // One heavy group with all kSpmvWaves waves of the workgroup: wave q sums
@@ -373,7 +251,7 @@ __device__ __forceinline__ void spmv_group_split(
     int32_t first, int32_t size, int32_t offset, int32_t c,
     const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
     const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
+    const XGather<typename Val<DT>::acc>& gx, bool serial, typename Val<DT>::acc* __restrict__ y,
     int32_t* ends, typename Val<DT>::acc (*part)[64 * W], int wv) {
   using A = typename Val<DT>::acc;
   const int lane = lane_id();
@@ -382,7 +260,7 @@ __device__ __forceinline__ void spmv_group_split(
   int32_t tmv[W];
   load_mapping<W>(first, size, tm, tmv);
   A acc[W];
-  chunk_partials<DT, W, U>(offset, j0, j1, columns, values, x, acc);
+  chunk_partials<DT, W, U>(offset, j0, j1, columns, values, gx, serial, acc);
   if (wv > 0) {
 #pragma unroll
     for (int w = 0; w < W; ++w) part[wv - 1][w * 64 + lane] = acc[w];
@@ -408,17 +286,19 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void argcsr_spmv_kernel(
     const argcsr_group_info* __restrict__ groups, int32_t n_groups,
     const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
     const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
-    const int32_t* __restrict__ heavy, int32_t n_heavy, int32_t heavy_chunk) {
+    const typename Val<DT>::acc* __restrict__ x, int32_t n_cols,
+    typename Val<DT>::acc* __restrict__ y,
+    const int32_t* __restrict__ heavy, int32_t n_heavy, int32_t heavy_chunk, int32_t serial) {
   using A = typename Val<DT>::acc;
   __shared__ int32_t ends[kSpmvWaves][64 * W];
   __shared__ A part[kSpmvWaves - 1][64 * W];
   const int wv = wave_uniform(int(threadIdx.x >> 6));
+  const XGather<A> gx(x, n_cols);
   const int32_t b = int32_t(blockIdx.x);
   if (b < n_heavy) {
     const argcsr_group_info gi = groups[heavy[b]];
     spmv_group_split<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, tm, columns,
-                               values, x, y, ends[0], part, wv);
+                               values, gx, serial != 0, y, ends[0], part, wv);
     return;
   }
   const uint32_t nb = gridDim.x - uint32_t(n_heavy);
@@ -427,37 +307,7 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void argcsr_spmv_kernel(
   const argcsr_group_info gi = groups[g];
   if (gi.chunk_size > heavy_chunk) return;          // processed by a heavy block
   spmv_group<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, tm, columns, values,
-                       x, y, ends[wv]);
-}
-
-// Single-matrix launch over runs: blocks [0, n_heavy) as above; the other
-// blocks take kSpmvWaves consecutive runs, one per wave (heavy runs are left
-// to the heavy blocks when there are any).
-template <int DT, int W, int U>
-__global__ __launch_bounds__(kSpmvWaves * 64) void argcsr_spmv_runs_kernel(
-    const argcsr_group_info* __restrict__ groups, const argcsr_run_info* __restrict__ runs,
-    int32_t n_runs, const int32_t* __restrict__ tm, const int32_t* __restrict__ columns,
-    const typename Val<DT>::storage* __restrict__ values,
-    const typename Val<DT>::acc* __restrict__ x, typename Val<DT>::acc* __restrict__ y,
-    const int32_t* __restrict__ heavy, int32_t n_heavy) {
-  using A = typename Val<DT>::acc;
-  __shared__ int32_t ends[kSpmvWaves][64 * W];
-  __shared__ int32_t stage[kSpmvWaves][kRunSlots];
-  __shared__ A part[kSpmvWaves - 1][64 * W];
-  const int wv = wave_uniform(int(threadIdx.x >> 6));
-  const int32_t b = int32_t(blockIdx.x);
-  if (b < n_heavy) {
-    const argcsr_group_info gi = groups[heavy[b]];
-    spmv_group_split<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, tm, columns,
-                               values, x, y, ends[0], part, wv);
-    return;
-  }
-  const uint32_t nb = gridDim.x - uint32_t(n_heavy);
-  const int k = int(xcd_remap(uint32_t(b - n_heavy), nb)) * kSpmvWaves + wv;
-  if (k >= n_runs) return;
-  const argcsr_run_info run = runs[k], next = runs[k + 1];
-  if ((run.flags & ARGCSR_RUN_HEAVY) && n_heavy > 0) return;   // processed by a heavy block
-  spmv_run<DT, W, U>(run, next, groups, tm, columns, values, x, y, ends[wv], stage[wv]);
+                       gx, serial != 0, y, ends[wv]);
 }
 
 int check_matrix(const argcsr_matrix* A);

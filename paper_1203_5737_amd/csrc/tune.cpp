@@ -3,7 +3,7 @@
 // The paper finds D decisive and matrix dependent: larger D for regular
 // matrices, D = 1 as the robust default (Sec. 5).  Here every (T, D) in
 // {64,128,256} x {1,2,4,...,64} is planned on the host (steps 1-2 give the
-// group, slot, heavy-group and run counts exactly), ranked by a cost
+// group count, slot count and heavy-group count exactly), ranked by a cost
 // model, and the best `n_finalists` are converted and timed on the device.
 // Choices are cached per process under a signature of the row-length
 // distribution, so matrices of the same shape are tuned once.
@@ -29,14 +29,14 @@ constexpr int32_t kDesired[] = {1, 2, 4, 8, 16, 32, 64};
 constexpr int kTimedReps = 10;
 
 // Cost model, in microseconds on MI355X: streamed bytes at a sustained
-// 5 TB/s, plus a per-run cost (metadata and load latency of one wave's run,
-// shared by the resident waves), plus a per-heavy-group workgroup cost.
+// 5 TB/s, plus a per-group cost (metadata and row-sum latency shared by the
+// resident waves), plus a per-heavy-group workgroup cost.
 constexpr double kStreamBytesPerUs = 5.0e6;
-constexpr double kUsPerRun = 4.0e-4;
+constexpr double kUsPerGroup = 4.0e-4;
 constexpr double kUsPerHeavy = 2.0e-3;
 
 struct Candidate {
-  int32_t T, D, G, heavy, runs;
+  int32_t T, D, G, heavy;
   int64_t S;
   double model_us;
   double measured_us;
@@ -72,7 +72,7 @@ std::string signature(int32_t n_rows, const int32_t* rp, int32_t dtype) {
 
 struct DeviceBuffers {
   argcsr_matrix m{};
-  void* mem[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* mem[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   ~DeviceBuffers() {
     for (void* p : mem)
       if (p) (void)hipFree(p);
@@ -92,12 +92,10 @@ int time_candidate(int32_t n_rows, int32_t n_cols, const int32_t* rp_host, const
   m.n_groups = c->G;
   m.n_slots = c->S;
   m.n_heavy = c->heavy;
-  m.n_runs = c->runs;
-  const size_t sizes[6] = {sizeof(argcsr_group_info) * size_t(c->G), sizeof(int32_t) * size_t(n_rows),
+  const size_t sizes[5] = {sizeof(argcsr_group_info) * size_t(c->G), sizeof(int32_t) * size_t(n_rows),
                            sizeof(int32_t) * size_t(c->S), size_t(value_bytes(dtype)) * size_t(c->S),
-                           sizeof(int32_t) * size_t(c->heavy),
-                           sizeof(argcsr_run_info) * size_t(c->runs + 1)};
-  for (int i = 0; i < 6; ++i)
+                           sizeof(int32_t) * size_t(c->heavy)};
+  for (int i = 0; i < 5; ++i)
     if (sizes[i] && hipMalloc(&b.mem[i], sizes[i]) != hipSuccess)
       return fail(ARGCSR_ENOMEM, "autotune: device allocation of %zu bytes failed", sizes[i]);
   m.groups = static_cast<argcsr_group_info*>(b.mem[0]);
@@ -105,7 +103,6 @@ int time_candidate(int32_t n_rows, int32_t n_cols, const int32_t* rp_host, const
   m.columns = static_cast<int32_t*>(b.mem[2]);
   m.values = b.mem[3];
   m.heavy_groups = static_cast<int32_t*>(b.mem[4]);
-  m.runs = static_cast<argcsr_run_info*>(b.mem[5]);
   int rc = argcsr_convert(n_rows, n_cols, rp_host, rp, col, val, &m, s);
   if (rc) return rc;
   hipEvent_t e0, e1;
@@ -151,12 +148,12 @@ extern "C" int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* ro
   std::vector<Candidate> cands;
   for (int32_t T : kBlockDims) {
     for (int32_t D : kDesired) {
-      int32_t G = 0, H = 0, R = 0;
+      int32_t G = 0, H = 0;
       int64_t S = 0;
-      if (argcsr_plan(n_rows, row_ptr_host, T, D, &G, &S, &H, &R) != ARGCSR_OK) continue;
+      if (argcsr_plan(n_rows, row_ptr_host, T, D, &G, &S, &H) != ARGCSR_OK) continue;
       const double bytes = double(S) * (sv + 4) + 16.0 * G + double(n_rows) * (4 + sx);
-      cands.push_back(Candidate{T, D, G, H, R, S,
-                                bytes / kStreamBytesPerUs + kUsPerRun * R + kUsPerHeavy * H, -1.0});
+      cands.push_back(Candidate{T, D, G, H, S,
+                                bytes / kStreamBytesPerUs + kUsPerGroup * G + kUsPerHeavy * H, -1.0});
     }
   }
   clear_error();

@@ -36,34 +36,3 @@ def powerlaw_sample(n, seed=7, lmax=10_000):
     s, v, xr = synth.streams(1000 + seed)
     A = synth.powerlaw(n, 2.0, lmax, s, v)
     return A, synth.uniform_vector(A.n_cols, xr)
-
-
-def heavy_chunk_for(T, S, G):
-    """The launch-schedule threshold (documented with argcsr_matrix.heavy_groups):
-    at least 4 rounds of 8 loaded steps per lane, and 4x the mean chunk size."""
-    by_rounds = {64: 32, 128: 16, 256: 8}.get(T)
-    if by_rounds is None or G == 0:
-        return by_rounds
-    return max(by_rounds, 4 * (-(-S // (G * T))))
-
-
-RUN_SLOTS = 512
-RUN_HEAVY = 1
-
-
-def runs_table(groups, n_slots, n_rows, heavy_chunk):
-    """The run schedule documented with argcsr_run_info, from a group table
-    (first_row, size, offset, chunk_size per row of `groups`): group g opens a
-    run iff g == 0, g or g-1 is heavy, or its offset lies in another window of
-    RUN_SLOTS slots than g-1's.  Rows of the result: first_group, offset,
-    first_row, flags; the last row is the sentinel."""
-    groups = np.asarray(groups, dtype=np.int64).reshape(-1, 4)
-    hc = np.iinfo(np.int64).max if heavy_chunk is None else heavy_chunk
-    out = []
-    for g in range(groups.shape[0]):
-        heavy = groups[g, 3] > hc
-        if g == 0 or heavy or groups[g - 1, 3] > hc or \
-                groups[g, 2] // RUN_SLOTS != groups[g - 1, 2] // RUN_SLOTS:
-            out.append([g, groups[g, 2], groups[g, 0], RUN_HEAVY if heavy else 0])
-    out.append([groups.shape[0], n_slots, n_rows, 0])
-    return np.array(out, dtype=np.int64).reshape(-1, 4)

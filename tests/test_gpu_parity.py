@@ -13,7 +13,7 @@ import torch
 import oracle
 import synth
 from conftest import gpu_available
-from helpers import U32, abs_row_sums, gamma, powerlaw_sample, runs_table, scaled_error
+from helpers import U32, abs_row_sums, gamma, powerlaw_sample, scaled_error
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -50,13 +50,6 @@ def compare_conversion(ac, A, T, D, dtype):
     assert M.n_heavy == len(want_heavy)
     if M.n_heavy:
         assert np.array_equal(M.heavy_groups.cpu().numpy(), want_heavy)
-    # run schedule: the documented rule applied to the oracle's group table
-    want_runs = runs_table(ref.groups, ref.n_slots, A.n_rows, M.heavy_chunk)
-    if ref.n_groups:
-        assert M.n_runs == want_runs.shape[0] - 1
-        assert np.array_equal(M.runs.cpu().numpy(), want_runs)
-    else:
-        assert M.n_runs == 0 and M.runs is None
     return dev, M, ref
 
 
@@ -252,39 +245,6 @@ def test_spmv_heavy_schedule_on_and_off(ac):
         M0 = ac.convert(dev, T, 1, schedule=False)
         assert M0.heavy_groups is None
         check_f64(A, x, gpu_spmv(ac, M0, x))
-
-
-def test_spmv_runs_bitwise_equal_one_group_per_wave(ac):
-    """Several short groups per wave (runs) and one group per wave give the
-    same bits: each chunk sums its own group's steps in the same order.
-    Covers runs that mix short groups, long non-heavy groups spanning
-    several batches, padding-only tails, empty rows and heavy groups taken
-    by the runs kernel itself when there is no heavy list."""
-    rng = np.random.default_rng(21)
-    n = 30_000
-    L = rng.integers(0, 4, n)
-    L[rng.integers(0, n, 60)] = rng.integers(20, 400, 60)
-    L[rng.integers(0, n, 8)] = 5000
-    L[1000:1200] = 0
-    A = synth.random_csr(L, 40_000, rng, rng)
-    x = rng.uniform(-1, 1, A.n_cols)
-    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
-    for T, D in [(64, 1), (64, 3), (128, 1), (256, 2)]:
-        for dtype in (0, 1):
-            xv = x if dtype == 0 else x.astype(np.float32)
-            # the heavy split changes the summation order of heavy groups, so
-            # runs on/off are compared with the same heavy setting
-            for sched in (True, False):
-                M = ac.convert(dev, T, D, dtype, schedule=sched)
-                assert M.n_runs < M.n_groups and (M.n_heavy > 0) == sched
-                y_runs = gpu_spmv(ac, M, xv)
-                M1 = ac.convert(dev, T, D, dtype, schedule=sched, runs=False)
-                assert M1.runs is None
-                y_one = gpu_spmv(ac, M1, xv)     # FP32 results widen exactly to FP64
-                assert np.array_equal(y_runs.view(np.uint64), y_one.view(np.uint64)), \
-                    (T, D, dtype, sched)
-                if dtype == 0:
-                    check_f64(A, x, y_runs)
 
 
 def test_spmv_deterministic(ac):

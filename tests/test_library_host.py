@@ -12,7 +12,6 @@ from hypothesis import given, settings
 from hypothesis import strategies as st
 
 import synth
-from helpers import RUN_SLOTS, heavy_chunk_for, runs_table
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
@@ -76,7 +75,7 @@ def plan(L, rp, T, D):
     rp = np.ascontiguousarray(rp, dtype=np.int32)
     g, s = ctypes.c_int32(0), ctypes.c_int64(0)
     rc = L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D,
-                       ctypes.byref(g), ctypes.byref(s), None, None)
+                       ctypes.byref(g), ctypes.byref(s), None)
     return rc, g.value, s.value
 
 
@@ -125,30 +124,26 @@ def test_gpu_entry_points_reject_bad_arguments_without_gpu(L):
     assert L.argcsr_csr_spmv(4, 4, 4, None, None, None, 0, 3, None, None, None) == _lib.EINVAL
 
 
-def test_plan_schedule_counts_match_oracle_groups(L, ora):
-    """Heavy-group and run counts of argcsr_plan against the documented
-    rules applied to the oracle's group table."""
+def heavy_chunk_for(T, S, G):
+    """The launch-schedule threshold (documented with argcsr_matrix.heavy_groups):
+    at least 4 rounds of 8 loaded steps per lane, and 4x the mean chunk size."""
+    by_rounds = {64: 32, 128: 16, 256: 8}.get(T)
+    if by_rounds is None or G == 0:
+        return by_rounds
+    return max(by_rounds, 4 * (-(-S // (G * T))))
+
+
+def test_plan_heavy_count_matches_oracle_groups(L, ora):
     Ap, _ = synth.workload_powerlaw(200_000)
     A2, _ = synth.workload_stencil27(16)
-    rng = np.random.default_rng(11)
-    Lr = rng.integers(0, 4, 5000)
-    Lr[rng.integers(0, 5000, 5)] = 3000
-    A3 = synth.random_csr(Lr, 5000, rng, rng)
-    for A, T, D in [(Ap, 64, 1), (Ap, 128, 2), (Ap, 256, 1), (A2, 256, 27), (A2, 64, 1),
-                    (A3, 64, 1), (A3, 128, 1), (A3, 7, 2), (A3, 1024, 1)]:
+    for A, T, D in [(Ap, 64, 1), (Ap, 128, 2), (Ap, 256, 1), (A2, 256, 27), (A2, 64, 1)]:
         rp = np.ascontiguousarray(A.rp, dtype=np.int32)
-        g, s, h, r = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
         assert L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D,
-                             ctypes.byref(g), ctypes.byref(s), ctypes.byref(h),
-                             ctypes.byref(r)) == 0
+                             ctypes.byref(g), ctypes.byref(s), ctypes.byref(h)) == 0
         ref = ora.convert(A.rp, A.col, A.val, T, D)
         hc = heavy_chunk_for(T, ref.n_slots, ref.n_groups)
-        assert h.value == (int((ref.groups[:, 3] > hc).sum()) if hc is not None else 0)
-        runs = runs_table(ref.groups, ref.n_slots, A.n_rows, hc)
-        assert r.value == runs.shape[0] - 1, (T, D)
-        if T <= RUN_SLOTS:    # window bounds: groups and rows per run
-            assert np.diff(runs[:, 0]).max() <= RUN_SLOTS // T
-            assert np.diff(runs[:, 2]).max() <= RUN_SLOTS
+        assert h.value == int((ref.groups[:, 3] > hc).sum())
 
 
 def test_autotune_model_ranking_on_host(L, ora):
@@ -166,10 +161,8 @@ def test_autotune_model_ranking_on_host(L, ora):
             for D in (1, 2, 4, 8, 16, 32, 64):
                 rc, G, S = ora.sizes(A.rp, T, D)
                 ref = ora.convert(A.rp, A.col, A.val, T, D)
-                hc = heavy_chunk_for(T, S, G)
-                H = int((ref.groups[:, 3] > hc).sum())
-                R = runs_table(ref.groups, S, A.n_rows, hc).shape[0] - 1
-                model = (S * (sv + 4) + 16 * G + A.n_rows * (4 + sx)) / 5e6 + 4e-4 * R + 2e-3 * H
+                H = int((ref.groups[:, 3] > heavy_chunk_for(T, S, G)).sum())
+                model = (S * (sv + 4) + 16 * G + A.n_rows * (4 + sx)) / 5e6 + 4e-4 * G + 2e-3 * H
                 if best is None or model < best[0]:
                     best = (model, T, D)
         assert (r["block_dim"], r["desired_chunk_size"]) == best[1:]
