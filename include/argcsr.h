@@ -151,6 +151,8 @@ int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
  *   A   converted matrix (device buffers as filled by argcsr_convert)
  *   x   device FP64[n_cols] for ARGCSR_F64, FP32[n_cols] otherwise
  *   y   device FP64[n_rows] / FP32[n_rows]; must not alias x
+ * x is gathered with 32-bit byte offsets: n_cols * sizeof(x element) must
+ * not exceed 0xFFFFFFF0 (EUNSUPPORTED otherwise).
  * Asynchronous on `stream`.  Errors: EINVAL, EUNSUPPORTED, EHIP (launch).
  */
 int argcsr_spmv(const argcsr_matrix* A, const void* x, void* y, void* stream);

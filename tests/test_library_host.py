@@ -120,6 +120,12 @@ def test_gpu_entry_points_reject_bad_arguments_without_gpu(L):
     assert L.argcsr_spmv(ctypes.byref(d), None, None, None) == _lib.EUNSUPPORTED
     d.block_dim, d.dtype = 64, 9
     assert L.argcsr_spmv(ctypes.byref(d), None, None, None) == _lib.EINVAL
+    # x is gathered with 32-bit byte offsets: FP64 x of 2^29 columns is out of range
+    d.dtype, d.n_cols = 0, 1 << 29
+    assert L.argcsr_spmv(ctypes.byref(d), None, None, None) == _lib.EUNSUPPORTED
+    d.dtype = 1                               # the same x in FP32 fits
+    assert L.argcsr_spmv(ctypes.byref(d), None, None, None) == _lib.OK
+    d.n_cols = 10
     assert L.argcsr_spmv(None, None, None, None) == _lib.EINVAL
     assert L.argcsr_csr_spmv(4, 4, 4, None, None, None, 0, 3, None, None, None) == _lib.EINVAL
 
