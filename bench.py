@@ -375,6 +375,13 @@ def main():
     t0 = time.perf_counter()
     M = ac.convert(dev, T, D, dtype)
     convert_ms = min(convert_ms, (time.perf_counter() - t0) * 1e3)
+    # the same with conversion step 1 on the device (no host row_ptr pass)
+    convert_device_ms = float("inf")
+    for _ in range(2):
+        t0 = time.perf_counter()
+        Md = ac.convert(dev, T, D, dtype, device_grouping=True)
+        convert_device_ms = min(convert_device_ms, (time.perf_counter() - t0) * 1e3)
+        del Md
 
     vdt = ac.vector_dtype(dtype)
     xd = torch.from_numpy(x).to("cuda", vdt)
@@ -404,6 +411,7 @@ def main():
                              "format_bytes": Bf, "padding_ratio": M.n_slots / max(A.nnz, 1),
                              "n_groups": M.n_groups, "wall_ms_per_step": wall * 1e3 / args.steps},
         "convert_ms": convert_ms,
+        "convert_device_grouping_ms": convert_device_ms,
         "kernel_hash": kernel_source_hash(),
     }
 

@@ -121,18 +121,38 @@ int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
                 int32_t* n_heavy);
 
 /*
+ * argcsr_plan_device -- the sizes argcsr_plan computes (same grouping rule,
+ * same results), from a row_ptr that lives only in device memory: steps 1-2
+ * of Sec. 3 run as HIP kernels on `stream` (step 1 by binary lifting over
+ * the next-group-start function of the rows; see argcsr_convert).
+ *   row_ptr  device int32[n_rows+1]
+ *   other arguments as for argcsr_plan (n_heavy may be NULL)
+ * Synchronous (reads the counts back).  Uses stream-ordered device scratch
+ * of about 4*(log2(n_rows)+2)*n_rows bytes.  Errors: EINVAL (bad sizes,
+ * row_ptr not starting at 0 or decreasing), EOVERFLOW, ENOMEM, EHIP.
+ */
+int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
+                       int32_t desired_chunk_size, int32_t* n_groups, int64_t* n_slots,
+                       int32_t* n_heavy, void* stream);
+
+/*
  * argcsr_convert -- CSR -> ARG-CSR on the GPU (Sec. 3, all four steps).
- * Step 1 (grouping, inherently sequential) runs on the host from
- * row_ptr_host; steps 2-4 (chunk size, threads mapping, offsets, fill) run
- * as HIP kernels on `stream`.  The result equals, byte for byte, the
+ * Steps 2-4 (chunk size, threads mapping, offsets, fill) run as HIP kernels
+ * on `stream`.  Step 1 (grouping) runs on the host from row_ptr_host when it
+ * is given, and otherwise on the device from row_ptr alone: with
+ * next(s) = the end of the group that opens at row s (a binary search on
+ * row_ptr), the groups are the path 0 -> next(0) -> ... -> n_rows, found by
+ * binary lifting (jump tables next^(2^k), then each group's start from the
+ * bits of its index).  Either way the result equals, byte for byte, the
  * sequential conversion the paper describes.
- *   row_ptr_host  host int32[n_rows+1]  (same content as row_ptr)
+ *   row_ptr_host  host int32[n_rows+1] (same content as row_ptr), or NULL
  *   row_ptr       device int32[n_rows+1]
  *   col           device int32[nnz], 0 <= col < n_cols
  *   val           device double[nnz]
  *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, dtype,
  *                     n_groups, n_slots and n_heavy as returned by
- *                     argcsr_plan, and the device buffers of those sizes
+ *                     argcsr_plan (or argcsr_plan_device), and the device
+ *                     buffers of those sizes
  *                     (heavy_groups may be NULL);
  *                 out: nnz, heavy_chunk, and the buffers filled.
  * Reduced dtypes round each value to nearest-even directly from FP64.

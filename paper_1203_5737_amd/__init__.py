@@ -50,7 +50,8 @@ def _stream(stream) -> ctypes.c_void_p:
 @dataclass
 class DeviceCsr:
     """A CSR matrix (Sec. 2) resident on the device, with a host copy of the
-    row offsets (conversion step 1 runs on the host)."""
+    row offsets (used when conversion step 1 runs on the host; the device
+    grouping path needs only the device arrays)."""
     n_rows: int
     n_cols: int
     row_ptr_host: np.ndarray     # int32 [n_rows+1]
@@ -115,11 +116,28 @@ def plan(row_ptr_host, block_dim: int, desired_chunk_size: int):
     return g.value, s.value, h.value
 
 
+def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, stream=None):
+    """(n_groups, n_slots, n_heavy) from a device row_ptr (argcsr_plan_device)."""
+    if row_ptr.dtype != torch.int32 or not row_ptr.is_contiguous() or not row_ptr.is_cuda:
+        raise ValueError("row_ptr must be a contiguous int32 device tensor")
+    g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    check(lib().argcsr_plan_device(int(row_ptr.numel() - 1), _ptr(row_ptr), int(block_dim),
+                                   int(desired_chunk_size), ctypes.byref(g), ctypes.byref(s),
+                                   ctypes.byref(h), _stream(stream)), "argcsr_plan_device")
+    return g.value, s.value, h.value
+
+
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
-            dtype: int = F64, stream=None, schedule: bool = True) -> ArgCsrMatrix:
+            dtype: int = F64, stream=None, schedule: bool = True,
+            device_grouping: bool = False) -> ArgCsrMatrix:
     """CSR -> ARG-CSR on the GPU (argcsr_convert); allocates the result.
-    `schedule` also builds the heavy-group launch schedule."""
-    G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size)
+    `schedule` also builds the heavy-group launch schedule.  With
+    `device_grouping` step 1 runs on the device and the host copy of
+    row_ptr is not used (argcsr_plan_device, row_ptr_host = NULL)."""
+    if device_grouping:
+        G, S, H = plan_device(A.row_ptr, block_dim, desired_chunk_size, stream)
+    else:
+        G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size)
     dev = A.row_ptr.device
     out = ArgCsrMatrix(
         A.n_rows, A.n_cols, int(block_dim), int(desired_chunk_size), int(dtype), G, A.nnz, S,
@@ -132,8 +150,8 @@ def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
     d = out.desc()
     if schedule and H == 0:
         d.heavy_groups = None
-    check(lib().argcsr_convert(A.n_rows, A.n_cols,
-                               A.row_ptr_host.ctypes.data_as(ctypes.c_void_p),
+    rp_host = None if device_grouping else A.row_ptr_host.ctypes.data_as(ctypes.c_void_p)
+    check(lib().argcsr_convert(A.n_rows, A.n_cols, rp_host,
                                _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), ctypes.byref(d),
                                _stream(stream)), "argcsr_convert")
     out.nnz = int(d.nnz)

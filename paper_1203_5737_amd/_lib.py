@@ -88,6 +88,8 @@ SIGNATURES = {
     "argcsr_version": (ctypes.c_int, []),
     "argcsr_plan": (ctypes.c_int, [i32, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
                                    ctypes.POINTER(i32)]),
+    "argcsr_plan_device": (ctypes.c_int, [i32, vp, i32, i32, ctypes.POINTER(i32),
+                                          ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),
     "argcsr_csr_spmv": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, vp, vp, vp]),

@@ -20,6 +20,7 @@ SOURCES = [
     "library.cpp",
     "plan.cpp",
     "convert.hip",
+    "group.hip",
     "spmv.hip",
     "csr_spmv.hip",
     "batch.hip",

@@ -1,5 +1,5 @@
-// Shared host-side helpers of libargcsr: status/error reporting, HIP call
-// checking, per-device workspace, and wave-level device primitives.
+// Shared helpers of libargcsr: status/error reporting, HIP call checking,
+// and wave-level device primitives.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,14 +23,6 @@ void clear_error();
       return ::argcsr::fail(ARGCSR_EHIP, "%s failed: %s (%s:%d)", #call,       \
                             hipGetErrorString(e_), __FILE__, __LINE__);        \
   } while (0)
-
-// Grow-only device workspace owned by the library, one per device.  Used by
-// conversion (validation flag, scan partials); never by argcsr_spmv.
-struct Workspace {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-int device_workspace(size_t bytes, void** out);
 
 // XCD-aware block remap: hardware dispatches consecutive workgroups round-robin
 // over the 8 XCDs; give every XCD a contiguous range of logical blocks so that

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "group.hpp"
 #include "plan.hpp"
 #include "schedule.hpp"
 #include "values.hpp"
@@ -36,6 +37,8 @@ struct Status {                       // device-side results read back by the ho
   long long total_slots;
   long long total_heavy;
 };
+
+__global__ void clear_status_kernel(Status* st) { *st = Status{}; }
 
 __global__ __launch_bounds__(256) void validate_columns_kernel(
     const int32_t* __restrict__ col, int64_t nnz, int32_t n_cols, Status* st) {
@@ -282,14 +285,32 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   if (out->desired_chunk_size < 1) return fail(ARGCSR_EINVAL, "desired_chunk_size < 1");
   if (out->dtype < ARGCSR_F64 || out->dtype > ARGCSR_F16)
     return fail(ARGCSR_EINVAL, "unknown dtype %d", out->dtype);
-  int rc = check_row_ptr(n_rows, row_ptr_host);
-  if (rc) return rc;
-  const int64_t nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
-
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // step 1: on the host from row_ptr_host, or on the device (group.hip)
   std::vector<argcsr_group_info> host_groups;
-  rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, &host_groups);
-  if (rc) return rc;
-  const int32_t G = (int32_t)host_groups.size();
+  DeviceGrouping device_groups;
+  int64_t nnz = 0;
+  int32_t G = 0;
+  int rc = ARGCSR_OK;
+  if (row_ptr_host) {
+    rc = check_row_ptr(n_rows, row_ptr_host);
+    if (rc) return rc;
+    nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
+    rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, &host_groups);
+    if (rc) return rc;
+    G = (int32_t)host_groups.size();
+  } else {
+    if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
+    rc = device_groups.build(n_rows, row_ptr, T, out->desired_chunk_size, s);
+    if (rc) return rc;
+    G = device_groups.n_groups;
+    if (n_rows > 0) {
+      int32_t last = 0;
+      ARGCSR_HIP(hipMemcpyAsync(&last, row_ptr + n_rows, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      ARGCSR_HIP(hipStreamSynchronize(s));
+      nnz = last;
+    }
+  }
   if (G != out->n_groups)
     return fail(ARGCSR_EINVAL, "out->n_groups = %d but the matrix has %d groups", out->n_groups, G);
   out->nnz = nnz;
@@ -303,21 +324,25 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
       (nnz > 0 && (!col || !val)))
     return fail(ARGCSR_EINVAL, "NULL device buffer");
 
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
-  void* ws = nullptr;
-  rc = device_workspace(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), &ws);
+  StreamScratch ws;
+  rc = ws.alloc(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), s);
   if (rc) return rc;
-  Status* st = static_cast<Status*>(ws);
+  Status* st = static_cast<Status*>(ws.ptr);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
   int64_t* heavy_tiles = tile_sums + n_tiles;
   // uses the caller's slot count; it is checked against the device total
   // before anything is written to the caller's heavy_groups buffer
   const int32_t heavy_chunk = out->heavy_chunk;
 
-  ARGCSR_HIP(hipMemsetAsync(st, 0, sizeof(Status), s));
-  ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
-                            sizeof(argcsr_group_info) * size_t(G), hipMemcpyHostToDevice, s));
+  clear_status_kernel<<<1, 1, 0, s>>>(st);
+  if (row_ptr_host) {
+    ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
+                              sizeof(argcsr_group_info) * size_t(G), hipMemcpyHostToDevice, s));
+  } else {
+    rc = device_groups.write(out->groups);
+    if (rc) return rc;
+  }
   if (nnz > 0) {
     const int64_t want = (nnz + 255) / 256;
     const int blocks = (int)(want < 8192 ? want : 8192);
@@ -361,5 +386,62 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   }
   ARGCSR_HIP(hipGetLastError());
   ARGCSR_HIP(hipStreamSynchronize(s));
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
+                                  int32_t desired_chunk_size, int32_t* n_groups,
+                                  int64_t* n_slots, int32_t* n_heavy, void* stream) {
+  using namespace argcsr;
+  clear_error();
+  if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
+  if (n_rows < 0) return fail(ARGCSR_EINVAL, "n_rows < 0");
+  if (block_dim < 1 || block_dim > kMaxBlockDim || desired_chunk_size < 1)
+    return fail(ARGCSR_EINVAL, "block_dim must be in [1, %d] and desired_chunk_size >= 1",
+                kMaxBlockDim);
+  if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DeviceGrouping dg;
+  int rc = dg.build(n_rows, row_ptr, block_dim, desired_chunk_size, s);
+  if (rc) return rc;
+  const int32_t G = dg.n_groups;
+  *n_groups = G;
+  *n_slots = 0;
+  if (n_heavy) *n_heavy = 0;
+  if (G == 0) return ARGCSR_OK;
+  // steps 2-3 into scratch: the chunk sizes give the slot count and the
+  // heavy-group count exactly as argcsr_plan computes them on the host
+  const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
+  const size_t groups_bytes = sizeof(argcsr_group_info) * size_t(G);
+  const size_t tm_bytes = (sizeof(int32_t) * size_t(n_rows) + 15) / 16 * 16;
+  StreamScratch ws;
+  rc = ws.alloc(groups_bytes + tm_bytes + sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), s);
+  if (rc) return rc;
+  auto* groups = static_cast<argcsr_group_info*>(ws.ptr);
+  auto* tm = reinterpret_cast<int32_t*>(static_cast<char*>(ws.ptr) + groups_bytes);
+  auto* st = reinterpret_cast<Status*>(static_cast<char*>(ws.ptr) + groups_bytes + tm_bytes);
+  int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
+  int64_t* heavy_tiles = tile_sums + n_tiles;
+  clear_status_kernel<<<1, 1, 0, s>>>(st);
+  rc = dg.write(groups);
+  if (rc) return rc;
+  const int wave_blocks = (G + kWaves - 1) / kWaves;
+  chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, groups, G, block_dim, tm);
+  offsets_reduce_kernel<<<n_tiles, kScanBlock, 0, s>>>(groups, G, block_dim, tile_sums);
+  tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(tile_sums, n_tiles, &st->total_slots);
+  ARGCSR_HIP(hipGetLastError());
+  Status host_st{};
+  ARGCSR_HIP(hipMemcpyAsync(&host_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  ARGCSR_HIP(hipStreamSynchronize(s));
+  const int64_t S = host_st.total_slots;
+  const int32_t heavy_chunk = heavy_chunk_for(block_dim, S, G);
+  heavy_count_kernel<<<n_tiles, kScanBlock, 0, s>>>(groups, G, heavy_chunk, heavy_tiles);
+  tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(heavy_tiles, n_tiles, &st->total_heavy);
+  ARGCSR_HIP(hipGetLastError());
+  ARGCSR_HIP(hipMemcpyAsync(&host_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
+  ARGCSR_HIP(hipStreamSynchronize(s));
+  *n_slots = S;
+  if (n_heavy) *n_heavy = int32_t(host_st.total_heavy);
+  if (S > INT32_MAX) return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", (long long)S);
   return ARGCSR_OK;
 }

@@ -32,10 +32,13 @@ def announce(msg):
     print(f"\n[gpu] {msg}", flush=True)
 
 
-def compare_conversion(ac, A, T, D, dtype):
-    announce(f"convert n={A.n_rows} nnz={A.nnz} T={T} D={D} dtype={dtype}")
+def compare_conversion(ac, A, T, D, dtype, device_grouping=False):
+    announce(f"convert n={A.n_rows} nnz={A.nnz} T={T} D={D} dtype={dtype} "
+             f"device_grouping={device_grouping}")
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
-    M = ac.convert(dev, T, D, dtype)
+    if device_grouping:
+        assert ac.plan_device(dev.row_ptr, T, D) == ac.plan(A.rp, T, D)
+    M = ac.convert(dev, T, D, dtype, device_grouping=device_grouping)
     ref = oracle.convert(A.rp, A.col, A.val, T, D, dtype)
     assert M.n_groups == ref.n_groups and M.n_slots == ref.n_slots
     assert np.array_equal(M.groups.cpu().numpy(), ref.groups)
@@ -125,6 +128,75 @@ def test_convert_rejects_bad_input(ac):
     dev = ac.to_device_csr(A.rp, col, A.val, A.n_cols, DEV)
     with pytest.raises(ac.ArgCsrError):
         ac.convert(dev, 64, 1)
+
+
+# ---------------------------------------------------------------------------
+# conversion step 1 on the device (binary lifting): identical groups
+# ---------------------------------------------------------------------------
+
+def csr_from_lengths(L, n_cols, seed):
+    rng = np.random.default_rng(seed)
+    return synth.random_csr(np.asarray(L, dtype=np.int64), n_cols, rng, rng)
+
+
+def test_device_grouping_fig3_and_laplace(ac):
+    for T in (1, 2, 3, 5, 12, 100):
+        for D in (1, 2, 3):
+            compare_conversion(ac, fig3(), T, D, oracle.F64, device_grouping=True)
+    A, _ = synth.workload_laplace64()
+    for T, D in [(64, 1), (64, 5), (128, 1), (100, 2), (1024, 1)]:
+        compare_conversion(ac, A, T, D, oracle.F64, device_grouping=True)
+
+
+@pytest.mark.parametrize("T,D", [(64, 1), (128, 2), (256, 1), (7, 3), (1000, 1)])
+def test_device_grouping_powerlaw(ac, T, D):
+    A, _ = powerlaw_sample(300_000, seed=31)
+    compare_conversion(ac, A, T, D, oracle.F64, device_grouping=True)
+
+
+def test_device_grouping_edge_cases(ac):
+    """Empty rows only (groups of T rows), every row over the budget (one
+    row per group), alternating empty and long rows, one row, and sizes
+    around powers of two (the number of jump levels)."""
+    cases = [
+        ([0], 5, 64, 1), ([300], 400, 64, 1), ([0] * 5000, 10, 64, 1),
+        ([200] * 3000, 300, 64, 1), ([0, 500] * 800, 600, 64, 2),
+        ([1] * 1023, 50, 1, 1), ([3] * 4097, 50, 64, 1),
+    ]
+    rng = np.random.default_rng(40)
+    for n in (255, 256, 257, 1023, 1024, 1025, 65536, 65537):
+        cases.append((rng.integers(0, 9, n), 100, int(rng.choice([1, 16, 64, 256])),
+                      int(rng.integers(1, 4))))
+    for i, (L, n_cols, T, D) in enumerate(cases):
+        compare_conversion(ac, csr_from_lengths(L, n_cols, 41 + i), T, D, oracle.F64,
+                           device_grouping=True)
+
+
+def test_device_grouping_random(ac):
+    rng = np.random.default_rng(42)
+    for i in range(30):
+        n = int(rng.integers(1, 3000))
+        L = rng.integers(0, int(rng.choice([3, 30, 300])), n)
+        L[rng.integers(0, n, 3)] = rng.integers(0, 4000, 3)
+        T = int(rng.choice([1, 3, 64, 128, 256, 1000]))
+        D = int(rng.integers(1, 6))
+        A = csr_from_lengths(L, 5000, 100 + i)
+        dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+        assert ac.plan_device(dev.row_ptr, T, D) == ac.plan(A.rp, T, D), (i, T, D)
+        M = ac.convert(dev, T, D, device_grouping=True)
+        ref = oracle.convert(A.rp, A.col, A.val, T, D)
+        assert np.array_equal(M.groups.cpu().numpy(), ref.groups), (i, T, D)
+        assert np.array_equal(M.threads_mapping.cpu().numpy(), ref.tm)
+        assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
+
+
+def test_device_grouping_rejects_bad_row_ptr(ac):
+    for rp in ([1, 2, 3], [0, 3, 2, 4], [0, 2, 1]):
+        rpd = torch.tensor(rp, dtype=torch.int32, device=DEV)
+        with pytest.raises(ac.ArgCsrError) as e:
+            ac.plan_device(rpd, 64, 1)
+        assert e.value.code == ac._lib.EINVAL
+    assert ac.plan_device(torch.zeros(1, dtype=torch.int32, device=DEV), 64, 1) == (0, 0, 0)
 
 
 # ---------------------------------------------------------------------------
@@ -286,6 +358,12 @@ def test_full_powerlaw_f64(ac, powerlaw_full, T, D):
     A, x = powerlaw_full
     dev, M, ref = compare_conversion(ac, A, T, D, oracle.F64)
     check_f64(A, x, gpu_spmv(ac, M, x))
+
+
+def test_full_device_grouping(ac, powerlaw_full, stencil_full):
+    compare_conversion(ac, powerlaw_full[0], 64, 1, oracle.F64, device_grouping=True)
+    compare_conversion(ac, stencil_full[0], 128, 27, oracle.F32, device_grouping=True)
+    torch.cuda.empty_cache()
 
 
 def test_full_powerlaw_f32(ac, powerlaw_full):
