@@ -57,6 +57,8 @@ def _bind(L):
         "ora_chunk_size": (i32, [i32, vp, i32, vp]),
         "ora_argcsr_sizes": (ctypes.c_int, [i32, vp, i32, i32, vp, vp]),
         "ora_argcsr_convert": (ctypes.c_int, [i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]),
+        "ora_rgcsr_sizes": (ctypes.c_int, [i32, vp, i32, vp, vp]),
+        "ora_rgcsr_convert": (ctypes.c_int, [i32, vp, vp, vp, i32, i32, vp, vp, vp, vp]),
         "ora_argcsr_spmv": (None, [i32, vp, vp, vp, vp, i32, vp, vp]),
         "ora_argcsr_to_csr": (i64, [i32, i32, vp, vp, vp, vp, i32, vp, vp, vp]),
         "ora_round_bf16": (u16, [f64]),
@@ -159,6 +161,34 @@ def convert(rp, col, val, block_dim: int, desired_chunk_size: int, dtype: int = 
     if rc != 0:
         raise ValueError(f"ora_argcsr_convert failed: {rc}")
     return ArgCsr(n, block_dim, desired_chunk_size, dtype, groups, tm, columns, values)
+
+
+def rg_sizes(rp, block_dim: int):
+    """(rc, groups, slots) of the row-grouped CSR storage (reading R9)."""
+    rp = _c(rp, np.int32)
+    g, s = ctypes.c_int32(0), ctypes.c_int64(0)
+    rc = lib().ora_rgcsr_sizes(rp.shape[0] - 1, _p(rp), block_dim, ctypes.byref(g),
+                               ctypes.byref(s))
+    return rc, g.value, s.value
+
+
+def rg_convert(rp, col, val, block_dim: int, dtype: int = F64) -> ArgCsr:
+    """CSR -> row-grouped CSR (reading R9) in the ARG-CSR arrays
+    (desired_chunk_size is reported as 0: it plays no part)."""
+    rp, col, val = _c(rp, np.int32), _c(col, np.int32), _c(val, np.float64)
+    n = rp.shape[0] - 1
+    rc, G, S = rg_sizes(rp, block_dim)
+    if rc != 0:
+        raise OverflowError(f"ora_rgcsr_sizes failed: {rc}")
+    groups = np.empty((G, 4), dtype=np.int32)
+    tm = np.empty(n, dtype=np.int32)
+    columns = np.empty(S, dtype=np.int32)
+    values = np.empty(S, dtype=_NP_STORAGE[dtype])
+    rc = lib().ora_rgcsr_convert(n, _p(rp), _p(col), _p(val), block_dim, dtype, _p(groups),
+                                 _p(tm), _p(columns), _p(values))
+    if rc != 0:
+        raise ValueError(f"ora_rgcsr_convert failed: {rc}")
+    return ArgCsr(n, block_dim, 0, dtype, groups, tm, columns, values)
 
 
 def values_as_f64(a: ArgCsr) -> np.ndarray:

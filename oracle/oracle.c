@@ -319,6 +319,65 @@ int ora_argcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Row-grouped CSR (reading R9): slice g holds rows g*T .. g*T+T-1; its      */
+/* width w is its longest row (at least 1); element e of the row in slice    */
+/* position l is stored at offset + e*T + l, everything else is padding.     */
+/* ------------------------------------------------------------------------ */
+
+int ora_rgcsr_sizes(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                    int32_t* n_groups, int64_t* n_slots)
+{
+    if (n_rows < 0 || block_dim < 1) return ORA_EINVAL;
+    int64_t S = 0;
+    int32_t G = 0;
+    for (int64_t first = 0; first < n_rows; first += block_dim, G++) {
+        int64_t w = 1;
+        for (int64_t r = first; r < n_rows && r < first + block_dim; r++)
+            if ((int64_t)rp[r + 1] - rp[r] > w) w = (int64_t)rp[r + 1] - rp[r];
+        S += w * block_dim;
+    }
+    *n_groups = G;
+    *n_slots = S;
+    return S > INT32_MAX ? ORA_EOVERFLOW : ORA_OK;
+}
+
+int ora_rgcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
+                      const double* val, int32_t block_dim, int32_t dtype,
+                      int32_t* groups, int32_t* tm, int32_t* columns,
+                      void* values)
+{
+    if (dtype < ORA_F64 || dtype > ORA_F16 || block_dim < 1) return ORA_EINVAL;
+    int64_t offset = 0;
+    int32_t g = 0;
+    for (int64_t first = 0; first < n_rows; first += block_dim, g++) {
+        const int64_t rows = (n_rows - first < block_dim) ? n_rows - first : block_dim;
+        int64_t w = 1;
+        for (int64_t l = 0; l < rows; l++)
+            if ((int64_t)rp[first + l + 1] - rp[first + l] > w)
+                w = (int64_t)rp[first + l + 1] - rp[first + l];
+        if (offset + w * block_dim > INT32_MAX) return ORA_EOVERFLOW;
+        groups[4 * g + 0] = (int32_t)first;
+        groups[4 * g + 1] = (int32_t)rows;
+        groups[4 * g + 2] = (int32_t)offset;
+        groups[4 * g + 3] = (int32_t)w;
+        for (int64_t s = 0; s < w * block_dim; s++) {
+            columns[offset + s] = -1;
+            store_value(values, dtype, offset + s, 0.0);
+        }
+        for (int64_t l = 0; l < rows; l++) {
+            const int64_t r = first + l;
+            tm[r] = (int32_t)(l + 1);
+            for (int64_t e = 0; e < (int64_t)rp[r + 1] - rp[r]; e++) {
+                columns[offset + e * block_dim + l] = col[rp[r] + e];
+                store_value(values, dtype, offset + e * block_dim + l, val[rp[r] + e]);
+            }
+        }
+        offset += w * block_dim;
+    }
+    return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* SpMV in ARG-CSR order (Sec. 4, Listing 2): chunk k of group g sums        */
 /* values*x over its slots offset + j*blockDim + k, j < chunkSize, stopping   */
 /* at the first column -1; row l of the group then sums the partial sums of   */

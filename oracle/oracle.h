@@ -35,6 +35,11 @@
  *   R7  reduced-precision storage rounds the FP64 value to nearest, ties to
  *       even, directly from FP64.
  *   R8  all indices are int32; a slot count above INT32_MAX is an error.
+ *   R9  Row-grouped CSR (the Sliced-ELLPACK-style storage Sec. 3 builds on,
+ *       compared against in Sec. 5): slices of blockDim consecutive rows,
+ *       one chunk per row, chunk size = the slice's longest row, but at
+ *       least 1 (as R6); stored in the same arrays as ARG-CSR, with
+ *       threadsMapping[row] = its position in the slice + 1.
  */
 #ifndef ARGCSR_ORACLE_H
 #define ARGCSR_ORACLE_H
@@ -90,6 +95,15 @@ int ora_argcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
                        int32_t desired_chunk_size, int32_t dtype,
                        int32_t* groups, int32_t* tm, int32_t* columns,
                        void* values);
+
+/* Row-grouped CSR (reading R9) in the same arrays: sizes, and the full
+ * conversion with the buffer conventions of ora_argcsr_convert. */
+int ora_rgcsr_sizes(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                    int32_t* n_groups, int64_t* n_slots);
+int ora_rgcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
+                      const double* val, int32_t block_dim, int32_t dtype,
+                      int32_t* groups, int32_t* tm, int32_t* columns,
+                      void* values);
 
 /* SpMV in ARG-CSR order, FP64 (Listing 2 semantics executed
  * sequentially): per group, chunk partial sums stopping at column -1, then

@@ -39,6 +39,12 @@ MUTANTS = {
     "rounding_ties_away": ("frac > 0.5 ||", "frac >= 0.5 ||"),
     "rounding_no_subnormal_quantum": ("(ue < emin ? emin : ue) - man_bits", "ue - man_bits"),
     "f32_truncates": ("((float*)values)[slot] = (float)v;", "((float*)values)[slot] = nextafterf((float)v, 0.0f);"),
+    "rg_width_may_be_zero": ("        const int64_t rows = (n_rows - first < block_dim) ? n_rows - first : block_dim;\n        int64_t w = 1;",
+                             "        const int64_t rows = (n_rows - first < block_dim) ? n_rows - first : block_dim;\n        int64_t w = 0;"),
+    "rg_layout_row_major": ("columns[offset + e * block_dim + l] = col[rp[r] + e];\n                store_value(values, dtype, offset + e * block_dim + l,",
+                            "columns[offset + l * w + e] = col[rp[r] + e];\n                store_value(values, dtype, offset + l * w + e,"),
+    "rg_mapping_exclusive": ("tm[r] = (int32_t)(l + 1);", "tm[r] = (int32_t)l;"),
+    "rg_slices_offset_by_one": ("groups[4 * g + 0] = (int32_t)first;", "groups[4 * g + 0] = (int32_t)first + (g > 0);"),
 }
 
 BATTERY = [
@@ -54,6 +60,11 @@ BATTERY = [
     pins.test_f16_rounding_matches_numpy,
     pins.test_bf16_rounding_is_nearest_even,
     pins.test_invariants_powerlaw_sample,
+    pins.test_rgcsr_fig3_one_thread_per_row,
+    pins.test_rgcsr_uniform_rows_closed_form,
+    pins.test_rgcsr_equals_argcsr_with_unbounded_budget,
+    pins.test_rgcsr_partial_last_slice_keeps_one_chunk_per_row,
+    pins.test_rgcsr_roundtrip_and_spmv_is_csr_order,
 ]
 
 

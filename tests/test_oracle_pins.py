@@ -492,3 +492,97 @@ def test_cg_true_residual(ora):
         M = sp.csr_matrix((A.val, A.col, A.rp), shape=(A.n_rows, A.n_cols))
         true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
         assert true <= 1e-10 and abs(true - rel) <= 1e-12 and it > 0
+
+
+# ---------------------------------------------------------------------------
+# Row-grouped CSR (reading R9): the Sliced-ELLPACK-style storage the paper
+# builds ARG-CSR from (Sec. 3) and compares it with (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def test_rgcsr_fig3_one_thread_per_row(ora):
+    """Sec. 3: with one thread per row the Fig. 3 matrix needs chunk size 8
+    and 49 artificial zeros (golden file); block_dim = 8 maps exactly one
+    thread to each row."""
+    paper = json.load(open(os.path.join(GOLDEN, "fig3_example.json")))["stated_by_paper"]
+    rp, col, val = fig3_matrix()
+    a = ora.rg_convert(rp, col, val, paper["rows"])
+    one = paper["one_thread_per_row"]
+    assert a.groups.tolist() == [[0, 8, 0, one["chunk_size"]]]
+    assert int((a.columns == -1).sum()) == one["artificial_zeros"]
+    assert a.tm.tolist() == list(range(1, 9))
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(T=st.sampled_from([1, 3, 8, 64]), k=st.integers(0, 9), n_blocks=st.integers(1, 5),
+       tail=st.integers(0, 7))
+def test_rgcsr_uniform_rows_closed_form(ora, T, k, n_blocks, tail):
+    """Uniform row length k: element e of row r sits at
+    floor(r/T)*max(k,1)*T + e*T + (r mod T) (ELLPACK per slice of T rows)."""
+    n = n_blocks * T + min(tail, T - 1)
+    rp = (np.arange(n + 1) * k).astype(np.int32)
+    col = np.tile(np.arange(k), n).astype(np.int32)
+    val = np.arange(n * k, dtype=np.float64) + 1.0        # value = 1 + CSR position
+    a = ora.rg_convert(rp, col, val, T)
+    w = max(k, 1)
+    assert a.n_groups == -(-n // T) and a.n_slots == a.n_groups * w * T
+    for r in range(n):
+        for e in range(k):
+            s = (r // T) * w * T + e * T + (r % T)
+            assert a.columns[s] == e and a.values[s] == 1.0 + r * k + e
+    assert int((a.columns >= 0).sum()) == n * k
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(lengths=st.lists(st.integers(0, 40), min_size=1, max_size=90),
+       T=st.sampled_from([1, 2, 5, 16, 30]))
+def test_rgcsr_equals_argcsr_with_unbounded_budget(ora, lengths, T):
+    """When every slice is full, row-grouped CSR is what ARG-CSR's own
+    steps give once the nonzero budget cannot bind (desired_chunk_size at
+    least the longest row): groups of T rows, chunk size = the longest row
+    (the greedy distribution leaves no thread free to split a row), one
+    chunk per row.  Two independent code paths of the oracle."""
+    n = len(lengths) - len(lengths) % T
+    if n == 0:
+        return
+    rp = np.concatenate([[0], np.cumsum(lengths[:n])]).astype(np.int32)
+    col = np.zeros(rp[-1], dtype=np.int32)
+    val = np.arange(rp[-1], dtype=np.float64)
+    rg = ora.rg_convert(rp, col, val, T)
+    ar = ora.convert(rp, col, val, T, max(1, max(lengths[:n])))
+    for f in ("groups", "tm", "columns", "values"):
+        assert np.array_equal(getattr(rg, f), getattr(ar, f)), f
+
+
+def test_rgcsr_partial_last_slice_keeps_one_chunk_per_row(ora):
+    """n = T + 1 with a long last row: the second slice holds that row alone
+    with chunk size = its length (ARG-CSR would spread it over the slice's
+    free threads), and an all-empty slice has chunk size 1 (R9)."""
+    T = 4
+    rp, col, val = csr_from_rows([[(0, 1.0)]] * T + [[(j, 2.0) for j in range(10)]], 10)
+    a = ora.rg_convert(rp, col, val, T)
+    assert a.groups.tolist() == [[0, 4, 0, 1], [4, 1, 4, 10]]
+    assert a.tm.tolist() == [1, 2, 3, 4, 1]
+    assert ora.convert(rp, col, val, T, 100).groups[1, 3] == 3     # ARG: ceil(10 / 4)
+    e = ora.rg_convert(np.zeros(6, dtype=np.int32), np.zeros(0, dtype=np.int32),
+                       np.zeros(0), 4)
+    assert e.groups.tolist() == [[0, 4, 0, 1], [4, 1, 4, 1]] and (e.columns == -1).all()
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(lengths=st.lists(st.integers(0, 25), min_size=0, max_size=70),
+       T=st.sampled_from([1, 4, 7, 64]), seed=st.integers(0, 2**31 - 1))
+def test_rgcsr_roundtrip_and_spmv_is_csr_order(ora, lengths, T, seed):
+    """Decoding the storage gives back the CSR matrix, and since each row is
+    one chunk summed left to right, the SpMV is bitwise the sequential CSR
+    sum (Sec. 2)."""
+    rng = np.random.default_rng(seed)
+    n = len(lengths)
+    A = synth.random_csr(np.asarray(lengths, dtype=np.int64), 30, rng, rng)
+    a = ora.rg_convert(A.rp, A.col, A.val, T)
+    rp2, col2, val2 = ora.argcsr_to_csr(a, A.nnz)
+    assert np.array_equal(rp2, A.rp) and np.array_equal(col2, A.col)
+    assert np.array_equal(val2, A.val)
+    x = rng.uniform(-1, 1, 30)
+    y = ora.argcsr_spmv(a, x)
+    yc = ora.csr_spmv(A.rp, A.col, A.val, x)
+    assert np.array_equal(y.view(np.uint64), yc.view(np.uint64)) or n == 0

@@ -49,6 +49,15 @@ int main(void) {
     if (ora_argcsr_to_csr(n, G, groups, tm, cols, v64, T, rp2, col2, val2) != nnz) return 4;
     if (n > 0 && memcmp(rp, rp2, sizeof(int) * (n + 1)) != 0) return 5;
     ora_round_array(nnz, val, 2, vals);
+    {   /* row-grouped CSR in the same arrays, decoded back */
+      int RG; int64_t RS;
+      if (ora_rgcsr_sizes(n, rp, T, &RG, &RS) != ORA_OK) return 7;
+      int *rgroups = malloc(sizeof(int) * 4 * (RG + 1)), *rcols = malloc(sizeof(int) * (RS + 1));
+      double *rvals = malloc(sizeof(double) * (RS + 1));
+      if (ora_rgcsr_convert(n, rp, col, val, T, 0, rgroups, tm, rcols, rvals) != ORA_OK) return 8;
+      if (ora_argcsr_to_csr(n, RG, rgroups, tm, rcols, rvals, T, rp2, col2, val2) != nnz) return 9;
+      free(rgroups); free(rcols); free(rvals);
+    }
     free(rp); free(col); free(val); free(x); free(groups); free(tm); free(cols); free(vals);
     free(v64); free(y1); free(y2); free(val2); free(rp2); free(col2);
   }
