@@ -190,8 +190,8 @@ def run_batch(args, torch, ac):
     for A, x in mats:
         d = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")
         r = ac.autotune(d, dtype, n_finalists=3)
-        tunes.append((r["block_dim"], r["desired_chunk_size"], r["from_cache"]))
-        Ms.append(ac.convert(d, r["block_dim"], r["desired_chunk_size"], dtype))
+        tunes.append((r["block_dim"], r["desired_chunk_size"], r["from_cache"], r["format"]))
+        Ms.append(ac.convert(d, r["block_dim"], r["desired_chunk_size"], dtype, fmt=r["format"]))
         devs.append(d)
         xs.append(torch.from_numpy(x).to("cuda", vdt))
         ys.append(torch.empty(A.n_rows, dtype=vdt, device="cuda"))
@@ -220,8 +220,9 @@ def run_batch(args, torch, ac):
         "spmv": stats(ms) | {"gflops": 2 * nnz / mean_s / 1e9, "useful_bytes": B,
                              "wall_ms_per_step": wall * 1e3 / args.steps} | batch.info(),
         "setup_s": setup_s,
-        "tuned": {f"T{T}/D{D}": sum(1 for t in tunes if t[:2] == (T, D))
-                  for T, D in sorted({t[:2] for t in tunes})},
+        "tuned": {(f"T{T}/RG" if fm else f"T{T}/D{D}"): sum(1 for t in tunes
+                                                          if (t[0], t[1], t[3]) == (T, D, fm))
+                  for T, D, fm in sorted({(t[0], t[1], t[3]) for t in tunes})},
         "kernel_hash": kernel_source_hash(),
     }
     if not args.no_extras:
@@ -436,6 +437,14 @@ def main():
         out["speedup_vs_csr"] = gbps / csr_gbps
         if dtype == 0 and args.workload == "powerlaw":
             out["f32"] = f32_variant(A, x, dev, timer, torch, ac, args.steps)
+        # the second storage format (row-grouped CSR, one chunk per row) at the same T
+        Mrg = ac.convert(dev, T, 0, dtype, fmt=ac.FORMAT_RG)
+        f = lambda: ac.spmv(Mrg, xd, yd)
+        timer.run(f, 3)
+        t, _ = timer.run(f, args.steps)
+        out["row_grouped"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9, "block_dim": T,
+                                         "padding_ratio": Mrg.n_slots / max(A.nnz, 1)}
+        del Mrg
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, x, useful_bytes(A, 0))   # the oracle is FP64

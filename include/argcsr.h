@@ -51,6 +51,23 @@ typedef enum {
   ARGCSR_F16 = 3
 } argcsr_dtype;
 
+/* Storage formats, both held in the arrays of argcsr_matrix and computed by
+ * the same SpMV kernels:
+ *   ARGCSR_FORMAT_ARG  Adaptive Row-grouped CSR (Sec. 3): groups bounded by
+ *                      block_dim rows and desired_chunk_size*block_dim
+ *                      nonzeros, long rows spread over free chunks.
+ *   ARGCSR_FORMAT_RG   Row-grouped CSR, the Sliced-ELLPACK-style storage the
+ *                      paper starts from and compares with (Sec. 3, Sec. 5):
+ *                      groups of block_dim consecutive rows, one chunk per
+ *                      row, chunk size = the group's longest row (at least
+ *                      1); desired_chunk_size plays no part.  The paper
+ *                      finds it faster than ARG-CSR on finite-difference
+ *                      matrices (Sec. 5). */
+typedef enum {
+  ARGCSR_FORMAT_ARG = 0,
+  ARGCSR_FORMAT_RG = 1
+} argcsr_format;
+
 /* One group of consecutive rows (Sec. 3, Listing 1): rows
  * first_row .. first_row+size-1; its chunk_size*block_dim slots start at
  * `offset` in values/columns, element j of chunk k at offset + j*block_dim + k. */
@@ -92,6 +109,8 @@ typedef struct {
   int32_t n_heavy;             /* set by argcsr_plan / argcsr_convert */
   int32_t heavy_chunk;         /* set by argcsr_convert */
   int32_t* heavy_groups;
+  int32_t format;              /* argcsr_format (0 = ARG-CSR) */
+  int32_t reserved;            /* 0 */
 } argcsr_matrix;
 
 /* Message describing the calling thread's most recent failure ("" if none). */
@@ -110,15 +129,16 @@ int argcsr_version(void);
  *   n_rows            >= 0
  *   row_ptr_host      host int32[n_rows+1], CSR row offsets (Sec. 2)
  *   block_dim         1..1024 (the SpMV entry points accept 64, 128, 256)
- *   desired_chunk_size >= 1
+ *   desired_chunk_size >= 1 (ignored for ARGCSR_FORMAT_RG)
+ *   format            argcsr_format
  *   n_groups, n_slots out: group count and slot count (sum c_g*block_dim)
  *   n_heavy           out (may be NULL): length of the heavy_groups schedule
  * Errors: EINVAL (bad sizes, row_ptr not starting at 0 or decreasing),
  * EOVERFLOW (slot count > INT32_MAX).  Allocates only host memory.
  */
 int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
-                int32_t desired_chunk_size, int32_t* n_groups, int64_t* n_slots,
-                int32_t* n_heavy);
+                int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
+                int64_t* n_slots, int32_t* n_heavy);
 
 /*
  * argcsr_plan_device -- the sizes argcsr_plan computes (same grouping rule,
@@ -132,8 +152,8 @@ int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
  * row_ptr not starting at 0 or decreasing), EOVERFLOW, ENOMEM, EHIP.
  */
 int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
-                       int32_t desired_chunk_size, int32_t* n_groups, int64_t* n_slots,
-                       int32_t* n_heavy, void* stream);
+                       int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
+                       int64_t* n_slots, int32_t* n_heavy, void* stream);
 
 /*
  * argcsr_convert -- CSR -> ARG-CSR on the GPU (Sec. 3, all four steps).
@@ -149,7 +169,7 @@ int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim
  *   row_ptr       device int32[n_rows+1]
  *   col           device int32[nnz], 0 <= col < n_cols
  *   val           device double[nnz]
- *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, dtype,
+ *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, format, dtype,
  *                     n_groups, n_slots and n_heavy as returned by
  *                     argcsr_plan (or argcsr_plan_device), and the device
  *                     buffers of those sizes
@@ -235,22 +255,26 @@ int argcsr_batch_destroy(argcsr_batch* b);
 
 typedef struct {
   int32_t block_dim;           /* chosen T */
-  int32_t desired_chunk_size;  /* chosen D */
+  int32_t desired_chunk_size;  /* chosen D (0 for ARGCSR_FORMAT_RG) */
   double model_us;             /* cost-model estimate of one SpMV */
   double measured_us;          /* mean of timed SpMVs (warm caches); < 0 if not timed */
   int32_t from_cache;          /* 1 if the choice came from the process cache */
-  int32_t n_candidates;        /* (T, D) pairs planned */
+  int32_t n_candidates;        /* candidates planned */
   int32_t n_timed;             /* candidates converted and timed */
+  int32_t format;              /* chosen argcsr_format */
 } argcsr_tune_result;
 
 /*
- * argcsr_autotune -- picks (block_dim, desired_chunk_size) for a matrix.
- * The paper makes desiredChunkSize the key, matrix-dependent parameter and
- * block size 128 its best on its GPU (Sec. 5).  Every pair in {64,128,256} x
- * {1,2,4,8,16,32,64} is sized with argcsr_plan, ranked by a cost model
- * (padded bytes, group count, long groups), and the best n_finalists are
- * converted and timed on `stream`.  The choice is cached for the process
- * under a signature of the row-length distribution.
+ * argcsr_autotune -- picks the storage format and its parameters for a
+ * matrix.  The paper makes desiredChunkSize the key, matrix-dependent
+ * parameter, block size 128 its best on its GPU, and advises trying more
+ * than one format, row-grouped CSR winning on finite-difference matrices
+ * (Sec. 5).  Every ARG-CSR pair in {64,128,256} x {1,2,4,8,16,32,64} and
+ * row-grouped CSR at {64,128,256} (24 candidates) is sized with
+ * argcsr_plan, ranked by a cost model (padded bytes, group count, long
+ * groups), and the best n_finalists are converted and timed on `stream`.
+ * The choice is cached for the process under a signature of the row-length
+ * distribution.
  *   arguments as for argcsr_convert; dtype is the value storage type
  *   n_finalists  candidates to time (0: model only)
  * Synchronous; allocates and frees temporary device memory.

@@ -18,7 +18,8 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import (BF16, F16, F32, F64, ArgCsrError, MatrixDesc, TuneResult, check, lib)
+from ._lib import (BF16, F16, F32, F64, FORMAT_ARG, FORMAT_RG, ArgCsrError, MatrixDesc,
+                   TuneResult, check, lib)
 
 __all__ = ["F64", "F32", "BF16", "F16", "ArgCsrError", "ArgCsrMatrix", "DeviceCsr",
            "plan", "convert", "spmv", "csr_spmv", "to_device_csr", "storage_dtype",
@@ -91,13 +92,14 @@ class ArgCsrMatrix:
     heavy_groups: Optional[torch.Tensor] = None   # int32 [n_heavy] launch schedule
     n_heavy: int = 0
     heavy_chunk: int = 0
+    format: int = FORMAT_ARG                      # FORMAT_ARG or FORMAT_RG
 
     def desc(self) -> MatrixDesc:
         return MatrixDesc(self.n_rows, self.n_cols, self.block_dim, self.desired_chunk_size,
                           self.dtype, self.n_groups, self.nnz, self.n_slots,
                           _ptr(self.groups), _ptr(self.threads_mapping), _ptr(self.columns),
                           _ptr(self.values), self.n_heavy, self.heavy_chunk,
-                          _ptr(self.heavy_groups))
+                          _ptr(self.heavy_groups), self.format, 0)
 
     def nbytes(self) -> int:
         ts = [self.groups, self.threads_mapping, self.columns, self.values]
@@ -106,38 +108,43 @@ class ArgCsrMatrix:
         return sum(t.numel() * t.element_size() for t in ts)
 
 
-def plan(row_ptr_host, block_dim: int, desired_chunk_size: int):
+def plan(row_ptr_host, block_dim: int, desired_chunk_size: int, fmt: int = FORMAT_ARG):
     """(n_groups, n_slots, n_heavy) of the converted matrix (host only)."""
     rp = np.ascontiguousarray(np.asarray(row_ptr_host, dtype=np.int32))
     g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
     check(lib().argcsr_plan(int(rp.shape[0] - 1), rp.ctypes.data_as(ctypes.c_void_p),
-                            int(block_dim), int(desired_chunk_size), ctypes.byref(g),
+                            int(block_dim), int(desired_chunk_size), int(fmt), ctypes.byref(g),
                             ctypes.byref(s), ctypes.byref(h)), "argcsr_plan")
     return g.value, s.value, h.value
 
 
-def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, stream=None):
+def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, stream=None,
+                fmt: int = FORMAT_ARG):
     """(n_groups, n_slots, n_heavy) from a device row_ptr (argcsr_plan_device)."""
     if row_ptr.dtype != torch.int32 or not row_ptr.is_contiguous() or not row_ptr.is_cuda:
         raise ValueError("row_ptr must be a contiguous int32 device tensor")
     g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
     check(lib().argcsr_plan_device(int(row_ptr.numel() - 1), _ptr(row_ptr), int(block_dim),
-                                   int(desired_chunk_size), ctypes.byref(g), ctypes.byref(s),
-                                   ctypes.byref(h), _stream(stream)), "argcsr_plan_device")
+                                   int(desired_chunk_size), int(fmt), ctypes.byref(g),
+                                   ctypes.byref(s), ctypes.byref(h), _stream(stream)),
+          "argcsr_plan_device")
     return g.value, s.value, h.value
 
 
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
             dtype: int = F64, stream=None, schedule: bool = True,
-            device_grouping: bool = False) -> ArgCsrMatrix:
-    """CSR -> ARG-CSR on the GPU (argcsr_convert); allocates the result.
-    `schedule` also builds the heavy-group launch schedule.  With
-    `device_grouping` step 1 runs on the device and the host copy of
-    row_ptr is not used (argcsr_plan_device, row_ptr_host = NULL)."""
+            device_grouping: bool = False, fmt: int = FORMAT_ARG) -> ArgCsrMatrix:
+    """CSR -> ARG-CSR (or, with fmt=FORMAT_RG, row-grouped CSR) on the GPU
+    (argcsr_convert); allocates the result.  `schedule` also builds the
+    heavy-group launch schedule.  With `device_grouping` step 1 runs on the
+    device and the host copy of row_ptr is not used (argcsr_plan_device,
+    row_ptr_host = NULL)."""
+    if fmt == FORMAT_RG:
+        desired_chunk_size = 0
     if device_grouping:
-        G, S, H = plan_device(A.row_ptr, block_dim, desired_chunk_size, stream)
+        G, S, H = plan_device(A.row_ptr, block_dim, desired_chunk_size, stream, fmt)
     else:
-        G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size)
+        G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size, fmt)
     dev = A.row_ptr.device
     out = ArgCsrMatrix(
         A.n_rows, A.n_cols, int(block_dim), int(desired_chunk_size), int(dtype), G, A.nnz, S,
@@ -146,7 +153,7 @@ def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
         torch.empty(S, dtype=torch.int32, device=dev),
         torch.empty(S, dtype=_STORAGE[dtype], device=dev),
         torch.empty(H, dtype=torch.int32, device=dev) if schedule else None,
-        H if schedule else 0)
+        H if schedule else 0, 0, int(fmt))
     d = out.desc()
     if schedule and H == 0:
         d.heavy_groups = None

@@ -16,6 +16,7 @@ OK, EINVAL, EOVERFLOW, ENOMEM, EHIP, EBUDGET, EBUSY, ENOTFOUND, EUNSUPPORTED, EN
 PENDING = 1
 REQ_ADMIT, REQ_SPMV, REQ_CG, REQ_EVICT = 0, 1, 2, 3
 F64, F32, BF16, F16 = 0, 1, 2, 3
+FORMAT_ARG, FORMAT_RG = 0, 1          # argcsr_format
 
 _NAMES = {OK: "OK", EINVAL: "EINVAL", EOVERFLOW: "EOVERFLOW", ENOMEM: "ENOMEM", EHIP: "EHIP",
           EBUDGET: "EBUDGET", EBUSY: "EBUSY", ENOTFOUND: "ENOTFOUND", EUNSUPPORTED: "EUNSUPPORTED",
@@ -41,14 +42,15 @@ class MatrixDesc(ctypes.Structure):
                 ("groups", ctypes.c_void_p), ("threads_mapping", ctypes.c_void_p),
                 ("columns", ctypes.c_void_p), ("values", ctypes.c_void_p),
                 ("n_heavy", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
-                ("heavy_groups", ctypes.c_void_p)]
+                ("heavy_groups", ctypes.c_void_p),
+                ("format", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("block_dim", ctypes.c_int32), ("desired_chunk_size", ctypes.c_int32),
                 ("model_us", ctypes.c_double), ("measured_us", ctypes.c_double),
                 ("from_cache", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
-                ("n_timed", ctypes.c_int32)]
+                ("n_timed", ctypes.c_int32), ("format", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -86,9 +88,9 @@ pi32 = ctypes.POINTER(i32)
 SIGNATURES = {
     "argcsr_last_error": (ctypes.c_char_p, []),
     "argcsr_version": (ctypes.c_int, []),
-    "argcsr_plan": (ctypes.c_int, [i32, vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
-                                   ctypes.POINTER(i32)]),
-    "argcsr_plan_device": (ctypes.c_int, [i32, vp, i32, i32, ctypes.POINTER(i32),
+    "argcsr_plan": (ctypes.c_int, [i32, vp, i32, i32, i32, ctypes.POINTER(i32),
+                                   ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+    "argcsr_plan_device": (ctypes.c_int, [i32, vp, i32, i32, i32, ctypes.POINTER(i32),
                                           ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),

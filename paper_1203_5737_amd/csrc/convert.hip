@@ -3,7 +3,8 @@
 // Step 1 (grouping) is a sequential scan and runs on the host (plan.cpp).
 // The kernels here run steps 2-4, every group independently:
 //   chunks_kernel   step 2: chunk size c_g = min{c >= 1 : sum_r max(1,ceil(L_r/c)) <= T}
-//                   and t_r = max(1, ceil(L_r/c_g)) chunks per row;
+//                   (row-grouped CSR: c_g = max(1, longest row)) and
+//                   t_r = max(1, ceil(L_r/c_g)) chunks per row;
 //                   step 3: inclusive per-group prefix sum of t_r -> threadsMapping
 //   offsets kernels exclusive scan of c_g*T over the groups -> groupInfo.offset
 //   heavy kernels   the launch schedule: ascending indices of groups whose
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(256) void validate_columns_kernel(
 // sub-row l / 64.
 __global__ __launch_bounds__(kWaves * 64) void chunks_kernel(
     const int32_t* __restrict__ rp, argcsr_group_info* __restrict__ groups,
-    int32_t n_groups, int32_t T, int32_t* __restrict__ tm) {
+    int32_t n_groups, int32_t T, int32_t row_grouped, int32_t* __restrict__ tm) {
   const int lane = lane_id();
   const int g = blockIdx.x * kWaves + wave_uniform(int(threadIdx.x >> 6));
   if (g >= n_groups) return;
@@ -87,10 +88,12 @@ __global__ __launch_bounds__(kWaves * 64) void chunks_kernel(
     }
     return wave_sum_i64(need);
   };
-  // binary search on the non-increasing chunks_needed(c)
+  // binary search on the non-increasing chunks_needed(c); row-grouped CSR
+  // takes the upper end, one chunk per row
   uint32_t lo = uint32_t((total + T - 1) / T);
   lo = lo < 1u ? 1u : lo;
   uint32_t hi = longest < 1 ? 1u : uint32_t(longest);
+  if (row_grouped) lo = hi;
   while (lo < hi) {
     const uint32_t mid = lo + (hi - lo) / 2;
     if (chunks_needed(mid) <= T) hi = mid;
@@ -282,7 +285,10 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   const int32_t T = out->block_dim;
   if (T < 1 || T > kMaxBlockDim)
     return fail(ARGCSR_EUNSUPPORTED, "block_dim %d outside [1, %d]", T, kMaxBlockDim);
-  if (out->desired_chunk_size < 1) return fail(ARGCSR_EINVAL, "desired_chunk_size < 1");
+  if (out->format != ARGCSR_FORMAT_ARG && out->format != ARGCSR_FORMAT_RG)
+    return fail(ARGCSR_EINVAL, "unknown format %d", out->format);
+  if (out->format == ARGCSR_FORMAT_ARG && out->desired_chunk_size < 1)
+    return fail(ARGCSR_EINVAL, "desired_chunk_size < 1");
   if (out->dtype < ARGCSR_F64 || out->dtype > ARGCSR_F16)
     return fail(ARGCSR_EINVAL, "unknown dtype %d", out->dtype);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -296,12 +302,12 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
     rc = check_row_ptr(n_rows, row_ptr_host);
     if (rc) return rc;
     nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
-    rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, &host_groups);
+    rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, out->format, &host_groups);
     if (rc) return rc;
     G = (int32_t)host_groups.size();
   } else {
     if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
-    rc = device_groups.build(n_rows, row_ptr, T, out->desired_chunk_size, s);
+    rc = device_groups.build(n_rows, row_ptr, T, out->desired_chunk_size, out->format, s);
     if (rc) return rc;
     G = device_groups.n_groups;
     if (n_rows > 0) {
@@ -351,6 +357,7 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   }
   const int wave_blocks = (G + kWaves - 1) / kWaves;
   chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, out->groups, G, T,
+                                                   out->format == ARGCSR_FORMAT_RG ? 1 : 0,
                                                    out->threads_mapping);
   ARGCSR_HIP(hipGetLastError());
   offsets_reduce_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, T, tile_sums);
@@ -390,19 +397,22 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
 }
 
 extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
-                                  int32_t desired_chunk_size, int32_t* n_groups,
+                                  int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
                                   int64_t* n_slots, int32_t* n_heavy, void* stream) {
   using namespace argcsr;
   clear_error();
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
   if (n_rows < 0) return fail(ARGCSR_EINVAL, "n_rows < 0");
-  if (block_dim < 1 || block_dim > kMaxBlockDim || desired_chunk_size < 1)
+  if (format != ARGCSR_FORMAT_ARG && format != ARGCSR_FORMAT_RG)
+    return fail(ARGCSR_EINVAL, "unknown format %d", format);
+  if (block_dim < 1 || block_dim > kMaxBlockDim ||
+      (format == ARGCSR_FORMAT_ARG && desired_chunk_size < 1))
     return fail(ARGCSR_EINVAL, "block_dim must be in [1, %d] and desired_chunk_size >= 1",
                 kMaxBlockDim);
   if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   DeviceGrouping dg;
-  int rc = dg.build(n_rows, row_ptr, block_dim, desired_chunk_size, s);
+  int rc = dg.build(n_rows, row_ptr, block_dim, desired_chunk_size, format, s);
   if (rc) return rc;
   const int32_t G = dg.n_groups;
   *n_groups = G;
@@ -426,7 +436,8 @@ extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_
   rc = dg.write(groups);
   if (rc) return rc;
   const int wave_blocks = (G + kWaves - 1) / kWaves;
-  chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, groups, G, block_dim, tm);
+  chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, groups, G, block_dim,
+                                                   format == ARGCSR_FORMAT_RG ? 1 : 0, tm);
   offsets_reduce_kernel<<<n_tiles, kScanBlock, 0, s>>>(groups, G, block_dim, tile_sums);
   tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(tile_sums, n_tiles, &st->total_slots);
   ARGCSR_HIP(hipGetLastError());

@@ -114,13 +114,14 @@ int StreamScratch::alloc(size_t bytes, hipStream_t s) {
 }
 
 int DeviceGrouping::build(int32_t n, const int32_t* rp, int32_t block_dim, int32_t desired,
-                          hipStream_t s) {
+                          int32_t format, hipStream_t s) {
   release();
   stream = s;
   n_rows = n;
   n_groups = 0;
   if (n == 0) return ARGCSR_OK;
-  if (block_dim < 1 || block_dim > kMaxGroupDim || desired < 1)
+  const bool row_grouped = format == ARGCSR_FORMAT_RG;
+  if (block_dim < 1 || block_dim > kMaxGroupDim || (!row_grouped && desired < 1))
     return fail(ARGCSR_EINVAL, "block_dim must be in [1, %d] and desired_chunk_size >= 1",
                 kMaxGroupDim);
   levels_n = 1;
@@ -135,7 +136,7 @@ int DeviceGrouping::build(int32_t n, const int32_t* rp, int32_t block_dim, int32
   fill_i32_kernel<<<1, 64, 0, s>>>(flags, 2, 0);
   const int64_t blocks = (int64_t(n) + 1 + kGroupBlock - 1) / kGroupBlock;
   next_kernel<<<dim3(uint32_t(blocks)), kGroupBlock, 0, s>>>(
-      n, rp, block_dim, int64_t(desired) * block_dim, levels, flags);
+      n, rp, block_dim, row_grouped ? INT64_MAX / 2 : int64_t(desired) * block_dim, levels, flags);
   for (int32_t k = 0; k + 1 < levels_n; ++k)
     jump_kernel<<<dim3(uint32_t(blocks)), kGroupBlock, 0, s>>>(n, levels + k * stride,
                                                                levels + (k + 1) * stride);

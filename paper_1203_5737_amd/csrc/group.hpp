@@ -24,7 +24,9 @@ struct DeviceGrouping {
   int32_t* levels = nullptr;
   hipStream_t stream = nullptr;
 
-  int build(int32_t n, const int32_t* row_ptr, int32_t block_dim, int32_t desired, hipStream_t s);
+  // format ARGCSR_FORMAT_RG: groups of block_dim rows (no nonzero budget)
+  int build(int32_t n, const int32_t* row_ptr, int32_t block_dim, int32_t desired,
+            int32_t format, hipStream_t s);
   int write(argcsr_group_info* groups) const;
   void release();
   ~DeviceGrouping() { release(); }

@@ -26,9 +26,10 @@ int check_row_ptr(int32_t n_rows, const int32_t* rp) {
 }
 
 int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
-               int32_t desired, std::vector<argcsr_group_info>* groups) {
+               int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups) {
   groups->clear();
-  const int64_t budget = int64_t(desired) * int64_t(block_dim);
+  const int64_t budget = format == ARGCSR_FORMAT_RG ? INT64_MAX / 2
+                                                   : int64_t(desired) * int64_t(block_dim);
   int32_t start = 0;
   while (start < n_rows) {
     // extend the group from `start` as far as both limits allow (at least one row)
@@ -40,6 +41,12 @@ int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
     start = end;
   }
   return ARGCSR_OK;
+}
+
+int32_t longest_row(const int32_t* rp, int32_t first, int32_t size) {
+  int32_t longest = 1;
+  for (int32_t l = 0; l < size; ++l) longest = std::max(longest, rp[first + l + 1] - rp[first + l]);
+  return longest;
 }
 
 int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
@@ -82,18 +89,21 @@ int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
 }  // namespace argcsr
 
 extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
-                           int32_t block_dim, int32_t desired_chunk_size,
+                           int32_t block_dim, int32_t desired_chunk_size, int32_t format,
                            int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy) {
   using namespace argcsr;
   clear_error();
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
-  if (block_dim < 1 || block_dim > kMaxGroupRows || desired_chunk_size < 1)
+  if (format != ARGCSR_FORMAT_ARG && format != ARGCSR_FORMAT_RG)
+    return fail(ARGCSR_EINVAL, "unknown format %d", format);
+  const bool row_grouped = format == ARGCSR_FORMAT_RG;
+  if (block_dim < 1 || block_dim > kMaxGroupRows || (!row_grouped && desired_chunk_size < 1))
     return fail(ARGCSR_EINVAL, "block_dim must be in [1, %d] and desired_chunk_size >= 1",
                 kMaxGroupRows);
   int rc = check_row_ptr(n_rows, row_ptr_host);
   if (rc) return rc;
   std::vector<argcsr_group_info> groups;
-  rc = group_rows(n_rows, row_ptr_host, block_dim, desired_chunk_size, &groups);
+  rc = group_rows(n_rows, row_ptr_host, block_dim, desired_chunk_size, format, &groups);
   if (rc) return rc;
   // step 2 is independent per group: split large matrices over host threads
   std::vector<int32_t> chunk(groups.size());
@@ -102,7 +112,9 @@ extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
   const unsigned n_threads = G >= 16384 ? hw : 1;
   auto work = [&](unsigned t) {
     for (size_t g = t * G / n_threads; g < (t + 1) * G / n_threads; ++g)
-      chunk[g] = min_chunk_size(row_ptr_host, groups[g].first_row, groups[g].size, block_dim);
+      chunk[g] = row_grouped ? longest_row(row_ptr_host, groups[g].first_row, groups[g].size)
+                             : min_chunk_size(row_ptr_host, groups[g].first_row, groups[g].size,
+                                              block_dim);
   };
   std::vector<std::thread> pool;
   for (unsigned t = 1; t < n_threads; ++t) pool.emplace_back(work, t);

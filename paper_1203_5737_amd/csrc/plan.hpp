@@ -16,12 +16,16 @@ int check_row_ptr(int32_t n_rows, const int32_t* rp);
 // group holds at most block_dim rows and at most desired*block_dim nonzeros;
 // a row that would break either limit opens the next group.  Fills
 // first_row/size of every group (offset and chunk_size left 0).
+// Row-grouped CSR (format ARGCSR_FORMAT_RG): groups of block_dim rows.
 int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
-               int32_t desired, std::vector<argcsr_group_info>* groups);
+               int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups);
 
 // Step 2 sizing: the smallest chunk size c >= 1 for which the rows of the
 // group need at most block_dim chunks, sum max(1, ceil(L_r / c)).
 int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
                        int32_t block_dim);
+
+// Row-grouped CSR: one chunk per row, chunk size max(1, longest row).
+int32_t longest_row(const int32_t* rp, int32_t first, int32_t size);
 
 }  // namespace argcsr

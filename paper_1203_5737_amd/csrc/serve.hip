@@ -213,7 +213,8 @@ int admit(argcsr_server* s, Request* r) {
   A.block_dim = T;
   A.desired_chunk_size = D;
   A.dtype = ARGCSR_F64;
-  rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, &A.n_groups, &A.n_slots, &A.n_heavy);
+  rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, ARGCSR_FORMAT_ARG, &A.n_groups, &A.n_slots,
+                   &A.n_heavy);
   if (rc) return rc;
   std::vector<size_t> sizes;
   auto grab = [&](size_t bytes) -> void* {

@@ -1,9 +1,12 @@
-// Autotuner for the conversion parameters (block_dim T, desired_chunk_size D).
+// Autotuner for the storage format and its parameters (block_dim T,
+// desired_chunk_size D; row-grouped CSR at each T).
 //
 // The paper finds D decisive and matrix dependent: larger D for regular
-// matrices, D = 1 as the robust default (Sec. 5).  Here every (T, D) in
-// {64,128,256} x {1,2,4,...,64} is planned on the host (steps 1-2 give the
-// group count, slot count and heavy-group count exactly), ranked by a cost
+// matrices, D = 1 as the robust default, and row-grouped CSR ahead on
+// finite-difference matrices (Sec. 5).  Here every (T, D) in
+// {64,128,256} x {1,2,4,...,64} and row-grouped CSR at each T is planned on
+// the host (steps 1-2 give the group count, slot count and heavy-group
+// count exactly), ranked by a cost
 // model, and the best `n_finalists` are converted and timed on the device.
 // Choices are cached per process under a signature of the row-length
 // distribution, so matrices of the same shape are tuned once.
@@ -36,7 +39,7 @@ constexpr double kUsPerGroup = 4.0e-4;
 constexpr double kUsPerHeavy = 2.0e-3;
 
 struct Candidate {
-  int32_t T, D, G, heavy;
+  int32_t T, D, format, G, heavy;
   int64_t S;
   double model_us;
   double measured_us;
@@ -88,6 +91,7 @@ int time_candidate(int32_t n_rows, int32_t n_cols, const int32_t* rp_host, const
   m.n_cols = n_cols;
   m.block_dim = c->T;
   m.desired_chunk_size = c->D;
+  m.format = c->format;
   m.dtype = dtype;
   m.n_groups = c->G;
   m.n_slots = c->S;
@@ -146,15 +150,17 @@ extern "C" int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* ro
   }
   const int sv = value_bytes(dtype), sx = dtype == ARGCSR_F64 ? 8 : 4;
   std::vector<Candidate> cands;
+  auto add = [&](int32_t T, int32_t D, int32_t format) {
+    int32_t G = 0, H = 0;
+    int64_t S = 0;
+    if (argcsr_plan(n_rows, row_ptr_host, T, D, format, &G, &S, &H) != ARGCSR_OK) return;
+    const double bytes = double(S) * (sv + 4) + 16.0 * G + double(n_rows) * (4 + sx);
+    cands.push_back(Candidate{T, D, format, G, H, S,
+                              bytes / kStreamBytesPerUs + kUsPerGroup * G + kUsPerHeavy * H, -1.0});
+  };
   for (int32_t T : kBlockDims) {
-    for (int32_t D : kDesired) {
-      int32_t G = 0, H = 0;
-      int64_t S = 0;
-      if (argcsr_plan(n_rows, row_ptr_host, T, D, &G, &S, &H) != ARGCSR_OK) continue;
-      const double bytes = double(S) * (sv + 4) + 16.0 * G + double(n_rows) * (4 + sx);
-      cands.push_back(Candidate{T, D, G, H, S,
-                                bytes / kStreamBytesPerUs + kUsPerGroup * G + kUsPerHeavy * H, -1.0});
-    }
+    for (int32_t D : kDesired) add(T, D, ARGCSR_FORMAT_ARG);
+    add(T, 0, ARGCSR_FORMAT_RG);
   }
   clear_error();
   if (cands.empty()) return fail(ARGCSR_EOVERFLOW, "no (block_dim, desired_chunk_size) fits int32");
@@ -184,7 +190,8 @@ extern "C" int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* ro
       if (cands[i].measured_us < cands[best].measured_us) best = i;
   }
   const Candidate& c = cands[best];
-  *out = argcsr_tune_result{c.T, c.D, c.model_us, c.measured_us, 0, int32_t(cands.size()), n_time};
+  *out = argcsr_tune_result{c.T,       c.D,   c.model_us,  c.measured_us, 0, int32_t(cands.size()),
+                            n_time, c.format};
   std::lock_guard<std::mutex> lock(g_cache_mutex);
   g_cache[key] = *out;
   return ARGCSR_OK;

@@ -42,9 +42,9 @@ def convert_all(ac, mats, dtype, seed):
     out = []
     for A, x in mats:
         T = int(rng.choice([64, 128, 256]))
-        D = int(rng.choice([1, 2, 4]))
+        D = int(rng.choice([1, 2, 4, 0]))           # 0: row-grouped CSR
         dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
-        M = ac.convert(dev, T, D, dtype)
+        M = ac.convert(dev, T, D, dtype, fmt=ac.FORMAT_ARG if D else ac.FORMAT_RG)
         xd = torch.from_numpy(x).to(DEV, ac.vector_dtype(dtype))
         out.append((A, x, M, xd))
     return out
@@ -115,9 +115,11 @@ def test_autotune_times_finalists(ac):
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
     r = ac.autotune(dev, ac.F64, n_finalists=3)
     assert r["n_timed"] == 3 and r["measured_us"] > 0 and r["from_cache"] == 0
-    assert r["block_dim"] in (64, 128, 256) and r["desired_chunk_size"] >= 1
+    assert r["block_dim"] in (64, 128, 256) and r["n_candidates"] == 24
+    assert r["format"] in (ac.FORMAT_ARG, ac.FORMAT_RG)
+    assert r["desired_chunk_size"] >= 1 or r["format"] == ac.FORMAT_RG
     r2 = ac.autotune(dev, ac.F64, n_finalists=3)
     assert r2["from_cache"] == 1 and r2["block_dim"] == r["block_dim"]
-    M = ac.convert(dev, r["block_dim"], r["desired_chunk_size"])
+    M = ac.convert(dev, r["block_dim"], r["desired_chunk_size"], fmt=r["format"])
     y = ac.spmv(M, torch.from_numpy(x).to(DEV)).cpu().numpy()
     check_f64(A, x, y)

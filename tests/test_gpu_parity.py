@@ -32,14 +32,17 @@ def announce(msg):
     print(f"\n[gpu] {msg}", flush=True)
 
 
-def compare_conversion(ac, A, T, D, dtype, device_grouping=False):
+def compare_conversion(ac, A, T, D, dtype, device_grouping=False, fmt=0):
     announce(f"convert n={A.n_rows} nnz={A.nnz} T={T} D={D} dtype={dtype} "
-             f"device_grouping={device_grouping}")
+             f"device_grouping={device_grouping} format={fmt}")
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
     if device_grouping:
-        assert ac.plan_device(dev.row_ptr, T, D) == ac.plan(A.rp, T, D)
-    M = ac.convert(dev, T, D, dtype, device_grouping=device_grouping)
-    ref = oracle.convert(A.rp, A.col, A.val, T, D, dtype)
+        assert ac.plan_device(dev.row_ptr, T, D, fmt=fmt) == ac.plan(A.rp, T, D, fmt)
+    M = ac.convert(dev, T, D, dtype, device_grouping=device_grouping, fmt=fmt)
+    if fmt == ac.FORMAT_RG:
+        ref = oracle.rg_convert(A.rp, A.col, A.val, T, dtype)
+    else:
+        ref = oracle.convert(A.rp, A.col, A.val, T, D, dtype)
     assert M.n_groups == ref.n_groups and M.n_slots == ref.n_slots
     assert np.array_equal(M.groups.cpu().numpy(), ref.groups)
     assert np.array_equal(M.threads_mapping.cpu().numpy(), ref.tm)
@@ -197,6 +200,35 @@ def test_device_grouping_rejects_bad_row_ptr(ac):
             ac.plan_device(rpd, 64, 1)
         assert e.value.code == ac._lib.EINVAL
     assert ac.plan_device(torch.zeros(1, dtype=torch.int32, device=DEV), 64, 1) == (0, 0, 0)
+
+
+# ---------------------------------------------------------------------------
+# row-grouped CSR (second storage format, same kernels)
+# ---------------------------------------------------------------------------
+
+def test_row_grouped_conversion_bit_exact(ac):
+    compare_conversion(ac, fig3(), 8, 0, oracle.F64, fmt=ac.FORMAT_RG)
+    A, _ = synth.workload_laplace64()
+    for T in (64, 100, 256):
+        compare_conversion(ac, A, T, 0, oracle.F64, fmt=ac.FORMAT_RG)
+    Ap, _ = powerlaw_sample(100_000, seed=33)
+    for T, dtype, dev_group in [(64, oracle.F64, False), (128, oracle.F32, True),
+                                (256, oracle.BF16, False), (64, oracle.F16, True)]:
+        compare_conversion(ac, Ap, T, 0, dtype, device_grouping=dev_group, fmt=ac.FORMAT_RG)
+    for i, (L, T) in enumerate([([0] * 300, 64), ([5] * 129 + [2000], 64), ([3, 0, 700] * 50, 7)]):
+        compare_conversion(ac, csr_from_lengths(L, 2500, 60 + i), T, 0, oracle.F64,
+                           device_grouping=bool(i % 2), fmt=ac.FORMAT_RG)
+
+
+def test_row_grouped_spmv(ac):
+    A, x = powerlaw_sample(60_000, seed=34)
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    for T in (64, 128, 256):
+        M = ac.convert(dev, T, 0, fmt=ac.FORMAT_RG)
+        assert M.format == ac.FORMAT_RG
+        check_f64(A, x, gpu_spmv(ac, M, x))
+        M32 = ac.convert(dev, T, 0, ac.F32, fmt=ac.FORMAT_RG)
+        check_reduced(A, x, gpu_spmv(ac, M32, x.astype(np.float32)), oracle.F32)
 
 
 # ---------------------------------------------------------------------------
@@ -363,6 +395,14 @@ def test_full_powerlaw_f64(ac, powerlaw_full, T, D):
 def test_full_device_grouping(ac, powerlaw_full, stencil_full):
     compare_conversion(ac, powerlaw_full[0], 64, 1, oracle.F64, device_grouping=True)
     compare_conversion(ac, stencil_full[0], 128, 27, oracle.F32, device_grouping=True)
+    torch.cuda.empty_cache()
+
+
+def test_full_stencil_row_grouped(ac, stencil_full):
+    A, x = stencil_full
+    dev, M, ref = compare_conversion(ac, A, 128, 0, oracle.F64, fmt=ac.FORMAT_RG)
+    check_f64(A, x, gpu_spmv(ac, M, x))
+    del M, ref
     torch.cuda.empty_cache()
 
 

@@ -71,10 +71,10 @@ def test_missing_library_fails_loudly(monkeypatch):
         _lib.lib()
 
 
-def plan(L, rp, T, D):
+def plan(L, rp, T, D, fmt=0):
     rp = np.ascontiguousarray(rp, dtype=np.int32)
     g, s = ctypes.c_int32(0), ctypes.c_int64(0)
-    rc = L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D,
+    rc = L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D, fmt,
                        ctypes.byref(g), ctypes.byref(s), None)
     return rc, g.value, s.value
 
@@ -97,11 +97,22 @@ def test_plan_matches_oracle_random(L, ora, lengths, T, D):
     assert plan(L, rp, T, D) == ora.sizes(rp, T, D)
 
 
+@settings(max_examples=150, deadline=None)
+@given(lengths=st.lists(st.integers(0, 300), min_size=0, max_size=200),
+       T=st.integers(1, 300))
+def test_plan_row_grouped_matches_oracle(L, ora, lengths, T):
+    """Row-grouped CSR sizes (groups of T rows, chunk = longest row >= 1)."""
+    rp = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    assert plan(L, rp, T, 0, 1) == ora.rg_sizes(rp, T)
+
+
 def test_plan_errors(L):
     from paper_1203_5737_amd import _lib
     good = np.array([0, 2, 3], dtype=np.int32)
     assert plan(L, good, 0, 1)[0] == _lib.EINVAL
     assert plan(L, good, 64, 0)[0] == _lib.EINVAL
+    assert plan(L, good, 64, 1, 2)[0] == _lib.EINVAL          # unknown format
+    assert plan(L, good, 64, 0, 1)[0] == _lib.OK              # D plays no part for RgCSR
     assert plan(L, np.array([1, 2, 3], dtype=np.int32), 64, 1)[0] == _lib.EINVAL
     assert plan(L, np.array([0, 3, 2], dtype=np.int32), 64, 1)[0] == _lib.EINVAL
     assert b"decreases" in L.argcsr_last_error()
@@ -145,7 +156,7 @@ def test_plan_heavy_count_matches_oracle_groups(L, ora):
     for A, T, D in [(Ap, 64, 1), (Ap, 128, 2), (Ap, 256, 1), (A2, 256, 27), (A2, 64, 1)]:
         rp = np.ascontiguousarray(A.rp, dtype=np.int32)
         g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
-        assert L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D,
+        assert L.argcsr_plan(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.c_void_p), T, D, 0,
                              ctypes.byref(g), ctypes.byref(s), ctypes.byref(h)) == 0
         ref = ora.convert(A.rp, A.col, A.val, T, D)
         hc = heavy_chunk_for(T, ref.n_slots, ref.n_groups)
@@ -164,14 +175,15 @@ def test_autotune_model_ranking_on_host(L, ora):
         sv, sx = (8, 8) if dt == ac.F64 else (4, 4)
         best = None
         for T in (64, 128, 256):
-            for D in (1, 2, 4, 8, 16, 32, 64):
-                rc, G, S = ora.sizes(A.rp, T, D)
-                ref = ora.convert(A.rp, A.col, A.val, T, D)
+            for D in (1, 2, 4, 8, 16, 32, 64, 0):          # 0: row-grouped CSR at this T
+                ref = (ora.convert(A.rp, A.col, A.val, T, D) if D
+                       else ora.rg_convert(A.rp, A.col, A.val, T))
+                G, S = ref.n_groups, ref.n_slots
                 H = int((ref.groups[:, 3] > heavy_chunk_for(T, S, G)).sum())
                 model = (S * (sv + 4) + 16 * G + A.n_rows * (4 + sx)) / 5e6 + 4e-4 * G + 2e-3 * H
                 if best is None or model < best[0]:
-                    best = (model, T, D)
-        assert (r["block_dim"], r["desired_chunk_size"]) == best[1:]
+                    best = (model, T, D, 0 if D else 1)
+        assert (r["block_dim"], r["desired_chunk_size"], r["format"]) == best[1:]
         assert abs(r["model_us"] - best[0]) < 1e-9 * max(1.0, best[0])
-        assert r["n_candidates"] == 21 and r["n_timed"] == 0 and r["from_cache"] == 0
+        assert r["n_candidates"] == 24 and r["n_timed"] == 0 and r["from_cache"] == 0
         assert ac.autotune(d, dt, n_finalists=0)["from_cache"] == 1
