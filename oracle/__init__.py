@@ -57,6 +57,10 @@ def _bind(L):
         "ora_chunk_size": (i32, [i32, vp, i32, vp]),
         "ora_argcsr_sizes": (ctypes.c_int, [i32, vp, i32, i32, vp, vp]),
         "ora_argcsr_convert": (ctypes.c_int, [i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]),
+        "ora_group_rows_regions": (ctypes.c_int, [i32, vp, i32, i32, vp, vp, vp, vp]),
+        "ora_argcsr_sizes_regions": (ctypes.c_int, [i32, vp, i32, i32, vp, vp, vp]),
+        "ora_argcsr_convert_regions": (ctypes.c_int, [i32, vp, vp, vp, i32, i32, vp, i32, vp, vp,
+                                                      vp, vp]),
         "ora_rgcsr_sizes": (ctypes.c_int, [i32, vp, i32, vp, vp]),
         "ora_rgcsr_convert": (ctypes.c_int, [i32, vp, vp, vp, i32, i32, vp, vp, vp, vp]),
         "ora_argcsr_spmv": (None, [i32, vp, vp, vp, vp, i32, vp, vp]),
@@ -161,6 +165,36 @@ def convert(rp, col, val, block_dim: int, desired_chunk_size: int, dtype: int = 
     if rc != 0:
         raise ValueError(f"ora_argcsr_convert failed: {rc}")
     return ArgCsr(n, block_dim, desired_chunk_size, dtype, groups, tm, columns, values)
+
+
+def sizes_regions(rp, block_dim: int, region_rows: int, desired):
+    """(rc, groups, slots) with desired[w] for rows [w*region_rows, ...) (reading R10)."""
+    rp, d = _c(rp, np.int32), _c(desired, np.int32)
+    g, s = ctypes.c_int32(0), ctypes.c_int64(0)
+    rc = lib().ora_argcsr_sizes_regions(rp.shape[0] - 1, _p(rp), block_dim, region_rows, _p(d),
+                                        ctypes.byref(g), ctypes.byref(s))
+    return rc, g.value, s.value
+
+
+def convert_regions(rp, col, val, block_dim: int, region_rows: int, desired,
+                    dtype: int = F64) -> ArgCsr:
+    """CSR -> ARG-CSR with a desiredChunkSize per region of rows (reading R10);
+    desired_chunk_size is reported as 0."""
+    rp, col, val, d = _c(rp, np.int32), _c(col, np.int32), _c(val, np.float64), _c(desired, np.int32)
+    n = rp.shape[0] - 1
+    rc, G, S = sizes_regions(rp, block_dim, region_rows, d)
+    if rc != 0:
+        raise ValueError(f"ora_argcsr_sizes_regions failed: {rc}")
+    groups = np.empty((G, 4), dtype=np.int32)
+    tm = np.empty(n, dtype=np.int32)
+    columns = np.empty(S, dtype=np.int32)
+    values = np.empty(S, dtype=_NP_STORAGE[dtype])
+    rc = lib().ora_argcsr_convert_regions(n, _p(rp), _p(col), _p(val), block_dim, region_rows,
+                                          _p(d), dtype, _p(groups), _p(tm), _p(columns),
+                                          _p(values))
+    if rc != 0:
+        raise ValueError(f"ora_argcsr_convert_regions failed: {rc}")
+    return ArgCsr(n, block_dim, 0, dtype, groups, tm, columns, values)
 
 
 def rg_sizes(rp, block_dim: int):

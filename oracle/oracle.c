@@ -68,13 +68,18 @@ int ora_csr_check(int32_t n_rows, int32_t n_cols, int64_t nnz,
 /* the next group).                                                           */
 /* ------------------------------------------------------------------------ */
 
-int ora_group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
-                   int32_t desired_chunk_size, int32_t* first_row,
-                   int32_t* size, int32_t* n_groups)
+/* Step 1 with a desiredChunkSize per region of region_rows consecutive rows
+ * (reading R10): the group that opens at row s may hold at most
+ * desired[s / region_rows] * blockDim nonzeros.  One region covering every
+ * row is the paper's rule with a single desiredChunkSize. */
+static int group_rows_regions(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                              int32_t region_rows, const int32_t* desired,
+                              int32_t* first_row, int32_t* size, int32_t* n_groups)
 {
-    if (n_rows < 0 || block_dim < 1 || desired_chunk_size < 1)
-        return ORA_EINVAL;
-    const int64_t limit = (int64_t)desired_chunk_size * (int64_t)block_dim;
+    if (n_rows < 0 || block_dim < 1 || region_rows < 1) return ORA_EINVAL;
+    for (int64_t w = 0; w * region_rows < n_rows; w++)
+        if (desired[w] < 1) return ORA_EINVAL;
+    int64_t limit = 0;
     int32_t g = 0;
     int32_t open_first = 0, open_size = 0;
     int64_t open_count = 0;
@@ -89,6 +94,8 @@ int ora_group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
             open_size = 0;
             open_count = 0;
         }
+        if (open_size == 0)                  /* row r opens a group */
+            limit = (int64_t)desired[r / region_rows] * (int64_t)block_dim;
         open_size += 1;
         open_count += L;
     }
@@ -99,6 +106,22 @@ int ora_group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
     }
     *n_groups = g;
     return ORA_OK;
+}
+
+int ora_group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                   int32_t desired_chunk_size, int32_t* first_row,
+                   int32_t* size, int32_t* n_groups)
+{
+    return group_rows_regions(n_rows, rp, block_dim, INT32_MAX, &desired_chunk_size,
+                              first_row, size, n_groups);
+}
+
+int ora_group_rows_regions(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                           int32_t region_rows, const int32_t* desired,
+                           int32_t* first_row, int32_t* size, int32_t* n_groups)
+{
+    return group_rows_regions(n_rows, rp, block_dim, region_rows, desired, first_row,
+                              size, n_groups);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -140,12 +163,20 @@ int ora_argcsr_sizes(int32_t n_rows, const int32_t* rp, int32_t block_dim,
                      int32_t desired_chunk_size, int32_t* n_groups,
                      int64_t* n_slots)
 {
+    return ora_argcsr_sizes_regions(n_rows, rp, block_dim, INT32_MAX, &desired_chunk_size,
+                                    n_groups, n_slots);
+}
+
+int ora_argcsr_sizes_regions(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                             int32_t region_rows, const int32_t* desired,
+                             int32_t* n_groups, int64_t* n_slots)
+{
     int32_t* first = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_rows + 1));
     int32_t* size = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_rows + 1));
     int64_t* L = (int64_t*)malloc(sizeof(int64_t) * (size_t)(block_dim + 1));
     int32_t* t = (int32_t*)malloc(sizeof(int32_t) * (size_t)(block_dim + 1));
-    int rc = ora_group_rows(n_rows, rp, block_dim, desired_chunk_size, first,
-                            size, n_groups);
+    int rc = group_rows_regions(n_rows, rp, block_dim, region_rows, desired, first,
+                                size, n_groups);
     int64_t S = 0;
     for (int32_t g = 0; rc == ORA_OK && g < *n_groups; g++) {
         for (int32_t l = 0; l < size[g]; l++)
@@ -268,14 +299,24 @@ int ora_argcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
                        int32_t* groups, int32_t* tm, int32_t* columns,
                        void* values)
 {
+    return ora_argcsr_convert_regions(n_rows, rp, col, val, block_dim, INT32_MAX,
+                                      &desired_chunk_size, dtype, groups, tm, columns,
+                                      values);
+}
+
+int ora_argcsr_convert_regions(int32_t n_rows, const int32_t* rp, const int32_t* col,
+                               const double* val, int32_t block_dim, int32_t region_rows,
+                               const int32_t* desired, int32_t dtype, int32_t* groups,
+                               int32_t* tm, int32_t* columns, void* values)
+{
     if (dtype < ORA_F64 || dtype > ORA_F16) return ORA_EINVAL;
     int32_t* first = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_rows + 1));
     int32_t* size = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_rows + 1));
     int64_t* L = (int64_t*)malloc(sizeof(int64_t) * (size_t)(block_dim + 1));
     int32_t* t = (int32_t*)malloc(sizeof(int32_t) * (size_t)(block_dim + 1));
     int32_t G = 0;
-    int rc = ora_group_rows(n_rows, rp, block_dim, desired_chunk_size, first,
-                            size, &G);
+    int rc = group_rows_regions(n_rows, rp, block_dim, region_rows, desired, first,
+                                size, &G);
     int64_t offset = 0;
     for (int32_t g = 0; rc == ORA_OK && g < G; g++) {
         /* step 2 */

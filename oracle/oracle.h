@@ -35,6 +35,10 @@
  *   R7  reduced-precision storage rounds the FP64 value to nearest, ties to
  *       even, directly from FP64.
  *   R8  all indices are int32; a slot count above INT32_MAX is an error.
+ *   R10 a desiredChunkSize per region of consecutive rows (the Sec. 5 rule
+ *       -- the more regular the rows, the larger desiredChunkSize -- applied
+ *       locally): the group that opens at row s uses the value of the region
+ *       holding s for its nonzero limit.
  *   R9  Row-grouped CSR (the Sliced-ELLPACK-style storage Sec. 3 builds on,
  *       compared against in Sec. 5): slices of blockDim consecutive rows,
  *       one chunk per row, chunk size = the slice's longest row, but at
@@ -75,6 +79,12 @@ int ora_group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
                    int32_t desired_chunk_size, int32_t* first_row,
                    int32_t* size, int32_t* n_groups);
 
+/* Step 1 with desired[w] for rows [w*region_rows, (w+1)*region_rows)
+ * (reading R10); desired has ceil(n_rows / region_rows) entries, all >= 1. */
+int ora_group_rows_regions(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                           int32_t region_rows, const int32_t* desired,
+                           int32_t* first_row, int32_t* size, int32_t* n_groups);
+
 /* Conversion step 2 for one group of `size` rows with lengths L[0..size):
  * the paper's greedy thread distribution.  Returns the chunk size c_g and
  * writes t[l] = max(1, ceil(L[l]/c_g)) (reading R2).  block_dim >= size. */
@@ -85,6 +95,16 @@ int32_t ora_chunk_size(int32_t size, const int64_t* L, int32_t block_dim,
 int ora_argcsr_sizes(int32_t n_rows, const int32_t* rp, int32_t block_dim,
                      int32_t desired_chunk_size, int32_t* n_groups,
                      int64_t* n_slots);
+
+/* ora_argcsr_sizes / ora_argcsr_convert with a desiredChunkSize per region
+ * of rows (reading R10). */
+int ora_argcsr_sizes_regions(int32_t n_rows, const int32_t* rp, int32_t block_dim,
+                             int32_t region_rows, const int32_t* desired,
+                             int32_t* n_groups, int64_t* n_slots);
+int ora_argcsr_convert_regions(int32_t n_rows, const int32_t* rp, const int32_t* col,
+                               const double* val, int32_t block_dim, int32_t region_rows,
+                               const int32_t* desired, int32_t dtype, int32_t* groups,
+                               int32_t* tm, int32_t* columns, void* values);
 
 /* Full conversion CSR -> ARG-CSR (steps 1-4).  Output buffers are sized by
  * ora_argcsr_sizes: groups[4*G] = {firstRow,size,offset,chunkSize} per group

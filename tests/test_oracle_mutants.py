@@ -39,6 +39,8 @@ MUTANTS = {
     "rounding_ties_away": ("frac > 0.5 ||", "frac >= 0.5 ||"),
     "rounding_no_subnormal_quantum": ("(ue < emin ? emin : ue) - man_bits", "ue - man_bits"),
     "f32_truncates": ("((float*)values)[slot] = (float)v;", "((float*)values)[slot] = nextafterf((float)v, 0.0f);"),
+    "regions_limit_of_current_row": ("        if (open_size == 0)                  /* row r opens a group */",
+                                     "        if (1)                  /* row r opens a group */"),
     "rg_width_may_be_zero": ("        const int64_t rows = (n_rows - first < block_dim) ? n_rows - first : block_dim;\n        int64_t w = 1;",
                              "        const int64_t rows = (n_rows - first < block_dim) ? n_rows - first : block_dim;\n        int64_t w = 0;"),
     "rg_layout_row_major": ("columns[offset + e * block_dim + l] = col[rp[r] + e];\n                store_value(values, dtype, offset + e * block_dim + l,",
@@ -60,6 +62,8 @@ BATTERY = [
     pins.test_f16_rounding_matches_numpy,
     pins.test_bf16_rounding_is_nearest_even,
     pins.test_invariants_powerlaw_sample,
+    pins.test_regions_hand_worked_example,
+    pins.test_regions_groups_are_greedy_maximal,
     pins.test_rgcsr_fig3_one_thread_per_row,
     pins.test_rgcsr_uniform_rows_closed_form,
     pins.test_rgcsr_equals_argcsr_with_unbounded_budget,

@@ -586,3 +586,47 @@ def test_rgcsr_roundtrip_and_spmv_is_csr_order(ora, lengths, T, seed):
     y = ora.argcsr_spmv(a, x)
     yc = ora.csr_spmv(A.rp, A.col, A.val, x)
     assert np.array_equal(y.view(np.uint64), yc.view(np.uint64)) or n == 0
+
+
+# ---------------------------------------------------------------------------
+# desiredChunkSize per region of rows (reading R10: the region of a group's
+# first row sets its nonzero limit)
+# ---------------------------------------------------------------------------
+
+def test_regions_hand_worked_example(ora):
+    """T = 4, regions of 4 rows with D = 2 then 1 (limits 8 and 4 nonzeros),
+    row lengths 3,3,3,3 | 2,2,2,2 | 1,1.  By hand: rows 0-1 (6; row 2 would
+    make 9 > 8); rows 2-4 (8: the group opened in region 0 keeps its limit
+    while it runs into region 1); rows 5-6 (4); rows 7-9 (4)."""
+    L = [3, 3, 3, 3, 2, 2, 2, 2, 1, 1]
+    rp = np.concatenate([[0], np.cumsum(L)]).astype(np.int32)
+    col = np.zeros(rp[-1], dtype=np.int32)
+    a = ora.convert_regions(rp, col, np.ones(rp[-1]), 4, 4, [2, 1, 1])
+    assert a.groups[:, :2].tolist() == [[0, 2], [2, 3], [5, 2], [7, 3]]
+
+
+@settings(max_examples=80, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(lengths=st.lists(st.integers(0, 60), min_size=0, max_size=120),
+       T=st.sampled_from([1, 2, 5, 16, 64]), region_rows=st.integers(1, 40),
+       seed=st.integers(0, 2**31 - 1))
+def test_regions_groups_are_greedy_maximal(ora, lengths, T, region_rows, seed):
+    """Brute-force statement of the rule: the groups partition the rows in
+    order; a group opened at s holds at most T rows and at most D(s)*T
+    nonzeros unless it is the single row s; and it cannot take one more row
+    without breaking one of those limits."""
+    rng = np.random.default_rng(seed)
+    n = len(lengths)
+    D = rng.integers(1, 5, max(1, -(-n // region_rows)))
+    rp = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    a = ora.convert_regions(rp.astype(np.int32), np.zeros(rp[-1], dtype=np.int32),
+                            np.ones(rp[-1]), T, region_rows, D)
+    nxt = 0
+    for first, size, _, _ in a.groups.tolist():
+        assert first == nxt and size >= 1
+        limit = int(D[first // region_rows]) * T
+        e = first + size
+        assert size <= T and (rp[e] - rp[first] <= limit or size == 1)
+        if e < n:
+            assert size + 1 > T or rp[e + 1] - rp[first] > limit
+        nxt = e
+    assert nxt == n
