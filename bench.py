@@ -39,7 +39,9 @@ KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_
                   "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp",
                   "paper_1203_5737_amd/csrc/schedule.hpp"]
 # (block_dim, desired_chunk_size) per workload unless given on the command line
-DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (128, 27), "laplace64": (64, 1)}
+DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (128, 27), "laplace64": (64, 1),
+                  "mixed": (64, 1)}
+DEFAULT_REGION_ROWS = {"mixed": 4096}
 
 
 def kernel_source_hash() -> str:
@@ -61,6 +63,10 @@ def load_workload(name: str):
     elif name == "laplace64":
         A, x = synth.workload_laplace64()
         desc = "2D 5-point Laplacian 64x64"
+    elif name == "mixed":
+        A, x = synth.workload_mixed(64)
+        desc = ("mixed regularity: 27-point stencil 64^3 rows, then 64^3 power-law rows "
+                "(Zipf(2.0), clip 1e4), n=524288")
     else:
         raise SystemExit(f"unknown workload {name}")
     return A, x, desc
@@ -331,6 +337,8 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=list(DTYPES))
     ap.add_argument("--block-dim", type=int, default=None)
     ap.add_argument("--desired-chunk-size", type=int, default=None)
+    ap.add_argument("--region-rows", type=int, default=None,
+                    help="desiredChunkSize per region of this many rows (0: one D)")
     ap.add_argument("--warm", action="store_true", help="no cache flush between steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the CSR and warm timings")
@@ -368,19 +376,24 @@ def main():
     A, x, desc = load_workload(args.workload)
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")
     torch.cuda.synchronize()
+    region_rows = (args.region_rows if args.region_rows is not None
+                   else DEFAULT_REGION_ROWS.get(args.workload, 0))
+    regions = ac.choose_region_desired(A.rp, region_rows) if region_rows else None
+    conv = lambda **kw: ac.convert(dev, T, D, dtype, region_rows=region_rows,
+                                   region_desired=regions, **kw)
 
     # conversion (timed separately, host grouping included)
     t0 = time.perf_counter()
-    M = ac.convert(dev, T, D, dtype)
+    M = conv()
     convert_ms = (time.perf_counter() - t0) * 1e3
     t0 = time.perf_counter()
-    M = ac.convert(dev, T, D, dtype)
+    M = conv()
     convert_ms = min(convert_ms, (time.perf_counter() - t0) * 1e3)
     # the same with conversion step 1 on the device (no host row_ptr pass)
     convert_device_ms = float("inf")
     for _ in range(2):
         t0 = time.perf_counter()
-        Md = ac.convert(dev, T, D, dtype, device_grouping=True)
+        Md = conv(device_grouping=True)
         convert_device_ms = min(convert_device_ms, (time.perf_counter() - t0) * 1e3)
         del Md
 
@@ -403,7 +416,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": desc, "n_rows": A.n_rows, "nnz": A.nnz, "block_dim": T,
-                   "desired_chunk_size": D, "value_dtype": args.dtype,
+                   "desired_chunk_size": D if regions is None else "per region",
+                   "region_rows": region_rows or None, "value_dtype": args.dtype,
                    "timing": "warm" if args.warm else "cold (1 GiB flush before each step, untimed)"},
         "roofline": {"bound": "hbm", "achieved": round(gbps, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
@@ -437,6 +451,19 @@ def main():
         out["speedup_vs_csr"] = gbps / csr_gbps
         if dtype == 0 and args.workload == "powerlaw":
             out["f32"] = f32_variant(A, x, dev, timer, torch, ac, args.steps)
+        if regions is not None:
+            # the same matrix with one desiredChunkSize for every row
+            out["uniform_desired"] = {}
+            for Du in sorted({1, int(regions.max())}):
+                Mu = ac.convert(dev, T, Du, dtype)
+                f = lambda: ac.spmv(Mu, xd, yd)
+                timer.run(f, 3)
+                t, _ = timer.run(f, args.steps)
+                out["uniform_desired"][f"D{Du}"] = stats(t) | {
+                    "gbps": B / (t.mean() * 1e-3) / 1e9, "padding_ratio": Mu.n_slots / A.nnz}
+                del Mu
+            out["region_desired_histogram"] = {
+                int(k): int(v) for k, v in zip(*np.unique(regions, return_counts=True))}
         # the second storage format (row-grouped CSR, one chunk per row) at the same T
         Mrg = ac.convert(dev, T, 0, dtype, fmt=ac.FORMAT_RG)
         f = lambda: ac.spmv(Mrg, xd, yd)

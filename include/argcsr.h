@@ -110,7 +110,13 @@ typedef struct {
   int32_t heavy_chunk;         /* set by argcsr_convert */
   int32_t* heavy_groups;
   int32_t format;              /* argcsr_format (0 = ARG-CSR) */
-  int32_t reserved;            /* 0 */
+  /* conversion input, ARG-CSR only: a desiredChunkSize per region of
+   * region_rows consecutive rows (host int32[ceil(n_rows/region_rows)],
+   * each >= 1), the region of a group's first row setting the group's
+   * nonzero limit; NULL = desired_chunk_size for every row.  Read by
+   * argcsr_convert only. */
+  int32_t region_rows;
+  const int32_t* region_desired;
 } argcsr_matrix;
 
 /* Message describing the calling thread's most recent failure ("" if none). */
@@ -141,6 +147,33 @@ int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
                 int64_t* n_slots, int32_t* n_heavy);
 
 /*
+ * argcsr_plan_regions -- argcsr_plan for ARG-CSR with a desiredChunkSize per
+ * region of rows: rows [w*region_rows, (w+1)*region_rows) use
+ * region_desired[w]; the group that opens at row s takes the value of the
+ * region holding s for its nonzero limit (the Sec. 5 rule -- the more
+ * regular the rows, the larger desiredChunkSize -- applied locally).
+ *   region_rows     >= 1
+ *   region_desired  host int32[ceil(n_rows / region_rows)], each >= 1
+ *   other arguments as for argcsr_plan
+ * Errors: as argcsr_plan; EINVAL for a bad region table.
+ */
+int argcsr_plan_regions(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
+                        int32_t region_rows, const int32_t* region_desired,
+                        int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy);
+
+/*
+ * argcsr_choose_region_desired -- fills region_desired (host
+ * int32[ceil(n_rows / region_rows)]) by the Sec. 5 rule applied per region:
+ * a region whose rows are regular (longest row <= 2 x its mean row length)
+ * gets its longest row length, capped at max_desired, so that its groups
+ * take block_dim rows of one chunk each; every other region gets 1.
+ * Host only.  Errors: EINVAL.
+ */
+int argcsr_choose_region_desired(int32_t n_rows, const int32_t* row_ptr_host,
+                                 int32_t region_rows, int32_t max_desired,
+                                 int32_t* region_desired);
+
+/*
  * argcsr_plan_device -- the sizes argcsr_plan computes (same grouping rule,
  * same results), from a row_ptr that lives only in device memory: steps 1-2
  * of Sec. 3 run as HIP kernels on `stream` (step 1 by binary lifting over
@@ -169,7 +202,8 @@ int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim
  *   row_ptr       device int32[n_rows+1]
  *   col           device int32[nnz], 0 <= col < n_cols
  *   val           device double[nnz]
- *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, format, dtype,
+ *   out           in: n_rows, n_cols, block_dim, desired_chunk_size, format,
+ *                     region_rows and region_desired, dtype,
  *                     n_groups, n_slots and n_heavy as returned by
  *                     argcsr_plan (or argcsr_plan_device), and the device
  *                     buffers of those sizes

@@ -99,7 +99,7 @@ class ArgCsrMatrix:
                           self.dtype, self.n_groups, self.nnz, self.n_slots,
                           _ptr(self.groups), _ptr(self.threads_mapping), _ptr(self.columns),
                           _ptr(self.values), self.n_heavy, self.heavy_chunk,
-                          _ptr(self.heavy_groups), self.format, 0)
+                          _ptr(self.heavy_groups), self.format, 0, None)
 
     def nbytes(self) -> int:
         ts = [self.groups, self.threads_mapping, self.columns, self.values]
@@ -118,6 +118,32 @@ def plan(row_ptr_host, block_dim: int, desired_chunk_size: int, fmt: int = FORMA
     return g.value, s.value, h.value
 
 
+def plan_regions(row_ptr_host, block_dim: int, region_rows: int, region_desired):
+    """(n_groups, n_slots, n_heavy) with a desiredChunkSize per region of rows
+    (argcsr_plan_regions)."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr_host, dtype=np.int32))
+    d = np.ascontiguousarray(np.asarray(region_desired, dtype=np.int32))
+    g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    check(lib().argcsr_plan_regions(int(rp.shape[0] - 1), rp.ctypes.data_as(ctypes.c_void_p),
+                                    int(block_dim), int(region_rows),
+                                    d.ctypes.data_as(ctypes.c_void_p), ctypes.byref(g),
+                                    ctypes.byref(s), ctypes.byref(h)), "argcsr_plan_regions")
+    return g.value, s.value, h.value
+
+
+def choose_region_desired(row_ptr_host, region_rows: int, max_desired: int = 64) -> np.ndarray:
+    """desiredChunkSize per region of rows by the local regularity rule
+    (argcsr_choose_region_desired)."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr_host, dtype=np.int32))
+    n = int(rp.shape[0] - 1)
+    out = np.zeros(max(1, -(-n // int(region_rows))), dtype=np.int32)
+    check(lib().argcsr_choose_region_desired(n, rp.ctypes.data_as(ctypes.c_void_p),
+                                             int(region_rows), int(max_desired),
+                                             out.ctypes.data_as(ctypes.c_void_p)),
+          "argcsr_choose_region_desired")
+    return out[: -(-n // int(region_rows))] if n else out[:0]
+
+
 def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, stream=None,
                 fmt: int = FORMAT_ARG):
     """(n_groups, n_slots, n_heavy) from a device row_ptr (argcsr_plan_device)."""
@@ -133,15 +159,23 @@ def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, 
 
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
             dtype: int = F64, stream=None, schedule: bool = True,
-            device_grouping: bool = False, fmt: int = FORMAT_ARG) -> ArgCsrMatrix:
+            device_grouping: bool = False, fmt: int = FORMAT_ARG, region_rows: int = 0,
+            region_desired=None) -> ArgCsrMatrix:
     """CSR -> ARG-CSR (or, with fmt=FORMAT_RG, row-grouped CSR) on the GPU
     (argcsr_convert); allocates the result.  `schedule` also builds the
     heavy-group launch schedule.  With `device_grouping` step 1 runs on the
     device and the host copy of row_ptr is not used (argcsr_plan_device,
-    row_ptr_host = NULL)."""
+    row_ptr_host = NULL).  `region_desired` (with `region_rows`) gives
+    ARG-CSR a desiredChunkSize per region of rows (argcsr_plan_regions; the
+    sizes are planned on the host)."""
     if fmt == FORMAT_RG:
         desired_chunk_size = 0
-    if device_grouping:
+    regions = None
+    if region_desired is not None:
+        regions = np.ascontiguousarray(np.asarray(region_desired, dtype=np.int32))
+        desired_chunk_size = 0
+        G, S, H = plan_regions(A.row_ptr_host, block_dim, region_rows, regions)
+    elif device_grouping:
         G, S, H = plan_device(A.row_ptr, block_dim, desired_chunk_size, stream, fmt)
     else:
         G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size, fmt)
@@ -157,6 +191,9 @@ def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
     d = out.desc()
     if schedule and H == 0:
         d.heavy_groups = None
+    if regions is not None:
+        d.region_rows = int(region_rows)
+        d.region_desired = regions.ctypes.data_as(ctypes.c_void_p)
     rp_host = None if device_grouping else A.row_ptr_host.ctypes.data_as(ctypes.c_void_p)
     check(lib().argcsr_convert(A.n_rows, A.n_cols, rp_host,
                                _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), ctypes.byref(d),

@@ -43,7 +43,8 @@ class MatrixDesc(ctypes.Structure):
                 ("columns", ctypes.c_void_p), ("values", ctypes.c_void_p),
                 ("n_heavy", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
                 ("heavy_groups", ctypes.c_void_p),
-                ("format", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("format", ctypes.c_int32), ("region_rows", ctypes.c_int32),
+                ("region_desired", ctypes.c_void_p)]
 
 
 class TuneResult(ctypes.Structure):
@@ -90,6 +91,9 @@ SIGNATURES = {
     "argcsr_version": (ctypes.c_int, []),
     "argcsr_plan": (ctypes.c_int, [i32, vp, i32, i32, i32, ctypes.POINTER(i32),
                                    ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+    "argcsr_plan_regions": (ctypes.c_int, [i32, vp, i32, i32, vp, ctypes.POINTER(i32),
+                                           ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+    "argcsr_choose_region_desired": (ctypes.c_int, [i32, vp, i32, i32, vp]),
     "argcsr_plan_device": (ctypes.c_int, [i32, vp, i32, i32, i32, ctypes.POINTER(i32),
                                           ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),

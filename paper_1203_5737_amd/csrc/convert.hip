@@ -287,7 +287,7 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
     return fail(ARGCSR_EUNSUPPORTED, "block_dim %d outside [1, %d]", T, kMaxBlockDim);
   if (out->format != ARGCSR_FORMAT_ARG && out->format != ARGCSR_FORMAT_RG)
     return fail(ARGCSR_EINVAL, "unknown format %d", out->format);
-  if (out->format == ARGCSR_FORMAT_ARG && out->desired_chunk_size < 1)
+  if (out->format == ARGCSR_FORMAT_ARG && out->desired_chunk_size < 1 && !out->region_desired)
     return fail(ARGCSR_EINVAL, "desired_chunk_size < 1");
   if (out->dtype < ARGCSR_F64 || out->dtype > ARGCSR_F16)
     return fail(ARGCSR_EINVAL, "unknown dtype %d", out->dtype);
@@ -298,16 +298,21 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   int64_t nnz = 0;
   int32_t G = 0;
   int rc = ARGCSR_OK;
+  const int32_t* regions = out->format == ARGCSR_FORMAT_ARG ? out->region_desired : nullptr;
+  rc = check_regions(n_rows, out->region_rows, regions);
+  if (rc) return rc;
   if (row_ptr_host) {
     rc = check_row_ptr(n_rows, row_ptr_host);
     if (rc) return rc;
     nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
-    rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, out->format, &host_groups);
+    rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, out->format, &host_groups,
+                    out->region_rows, regions);
     if (rc) return rc;
     G = (int32_t)host_groups.size();
   } else {
     if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
-    rc = device_groups.build(n_rows, row_ptr, T, out->desired_chunk_size, out->format, s);
+    rc = device_groups.build(n_rows, row_ptr, T, out->desired_chunk_size, out->format, s,
+                             out->region_rows, regions);
     if (rc) return rc;
     G = device_groups.n_groups;
     if (n_rows > 0) {

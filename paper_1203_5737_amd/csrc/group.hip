@@ -37,6 +37,7 @@ __global__ void fill_i32_kernel(int32_t* __restrict__ p, int32_t n, int32_t v) {
 // rows any of their groups can reach.
 __global__ __launch_bounds__(kGroupBlock) void next_kernel(
     int32_t n, const int32_t* __restrict__ rp, int32_t block_dim, int64_t budget,
+    int32_t region_rows, const int32_t* __restrict__ region_desired,
     int32_t* __restrict__ j0, int32_t* __restrict__ bad) {
   __shared__ int32_t srp[kGroupBlock + kMaxGroupDim + 1];
   const int64_t base = int64_t(blockIdx.x) * kGroupBlock;
@@ -55,6 +56,8 @@ __global__ __launch_bounds__(kGroupBlock) void next_kernel(
     j0[r] = int32_t(r + 1);       // keeps every pointer moving forward
     return;
   }
+  // a per-region desiredChunkSize: the region of the group's first row r
+  if (region_desired) budget = int64_t(region_desired[r / region_rows]) * block_dim;
   const int64_t limit = int64_t(srp[l]) + budget;
   const int32_t hi = int32_t(min(int64_t(n) - base, int64_t(l) + block_dim));  // local index
   // largest e in [l+1, hi] with srp[e] <= limit, or l+1 if none
@@ -114,29 +117,37 @@ int StreamScratch::alloc(size_t bytes, hipStream_t s) {
 }
 
 int DeviceGrouping::build(int32_t n, const int32_t* rp, int32_t block_dim, int32_t desired,
-                          int32_t format, hipStream_t s) {
+                          int32_t format, hipStream_t s, int32_t region_rows,
+                          const int32_t* region_desired) {
   release();
   stream = s;
   n_rows = n;
   n_groups = 0;
   if (n == 0) return ARGCSR_OK;
   const bool row_grouped = format == ARGCSR_FORMAT_RG;
-  if (block_dim < 1 || block_dim > kMaxGroupDim || (!row_grouped && desired < 1))
+  if (block_dim < 1 || block_dim > kMaxGroupDim ||
+      (!row_grouped && !region_desired && desired < 1) || (region_desired && region_rows < 1))
     return fail(ARGCSR_EINVAL, "block_dim must be in [1, %d] and desired_chunk_size >= 1",
                 kMaxGroupDim);
   levels_n = 1;
   while ((int64_t(1) << levels_n) <= n) ++levels_n;   // 2^levels_n > n >= any jump count
   stride = int64_t(n) + 1;
-  const size_t bytes = sizeof(int32_t) * (size_t(levels_n) * size_t(stride) + 2);
+  const int64_t n_regions = region_desired ? (int64_t(n) + region_rows - 1) / region_rows : 0;
+  const size_t bytes = sizeof(int32_t) * (size_t(levels_n) * size_t(stride) + 2 + size_t(n_regions));
   if (hipMallocAsync(reinterpret_cast<void**>(&levels), bytes, s) != hipSuccess) {
     levels = nullptr;
     return fail(ARGCSR_ENOMEM, "grouping tables of %zu bytes could not be allocated", bytes);
   }
   int32_t* flags = levels + size_t(levels_n) * size_t(stride);   // [0] bad row_ptr, [1] count
+  int32_t* d_regions = n_regions ? flags + 2 : nullptr;
   fill_i32_kernel<<<1, 64, 0, s>>>(flags, 2, 0);
+  if (d_regions)
+    ARGCSR_HIP(hipMemcpyAsync(d_regions, region_desired, sizeof(int32_t) * size_t(n_regions),
+                              hipMemcpyHostToDevice, s));
   const int64_t blocks = (int64_t(n) + 1 + kGroupBlock - 1) / kGroupBlock;
   next_kernel<<<dim3(uint32_t(blocks)), kGroupBlock, 0, s>>>(
-      n, rp, block_dim, row_grouped ? INT64_MAX / 2 : int64_t(desired) * block_dim, levels, flags);
+      n, rp, block_dim, row_grouped ? INT64_MAX / 2 : int64_t(desired) * block_dim,
+      row_grouped ? 1 : region_rows, row_grouped ? nullptr : d_regions, levels, flags);
   for (int32_t k = 0; k + 1 < levels_n; ++k)
     jump_kernel<<<dim3(uint32_t(blocks)), kGroupBlock, 0, s>>>(n, levels + k * stride,
                                                                levels + (k + 1) * stride);

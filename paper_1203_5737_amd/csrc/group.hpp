@@ -24,9 +24,12 @@ struct DeviceGrouping {
   int32_t* levels = nullptr;
   hipStream_t stream = nullptr;
 
-  // format ARGCSR_FORMAT_RG: groups of block_dim rows (no nonzero budget)
+  // format ARGCSR_FORMAT_RG: groups of block_dim rows (no nonzero budget);
+  // region_desired (host, checked by the caller): a desiredChunkSize per
+  // region of region_rows rows, taken from the region of a group's first row
   int build(int32_t n, const int32_t* row_ptr, int32_t block_dim, int32_t desired,
-            int32_t format, hipStream_t s);
+            int32_t format, hipStream_t s, int32_t region_rows = 0,
+            const int32_t* region_desired = nullptr);
   int write(argcsr_group_info* groups) const;
   void release();
   ~DeviceGrouping() { release(); }

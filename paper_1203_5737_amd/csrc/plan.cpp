@@ -25,14 +25,25 @@ int check_row_ptr(int32_t n_rows, const int32_t* rp) {
   return ARGCSR_OK;
 }
 
+int check_regions(int32_t n_rows, int32_t region_rows, const int32_t* region_desired) {
+  if (!region_desired) return ARGCSR_OK;
+  if (region_rows < 1) return fail(ARGCSR_EINVAL, "region_rows must be >= 1");
+  for (int64_t w = 0; w * region_rows < n_rows; ++w)
+    if (region_desired[w] < 1)
+      return fail(ARGCSR_EINVAL, "region_desired[%lld] = %d < 1", (long long)w, region_desired[w]);
+  return ARGCSR_OK;
+}
+
 int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
-               int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups) {
+               int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups,
+               int32_t region_rows, const int32_t* region_desired) {
   groups->clear();
-  const int64_t budget = format == ARGCSR_FORMAT_RG ? INT64_MAX / 2
-                                                   : int64_t(desired) * int64_t(block_dim);
+  const bool rg = format == ARGCSR_FORMAT_RG;
   int32_t start = 0;
   while (start < n_rows) {
     // extend the group from `start` as far as both limits allow (at least one row)
+    const int32_t d = region_desired ? region_desired[start / region_rows] : desired;
+    const int64_t budget = rg ? INT64_MAX / 2 : int64_t(d) * int64_t(block_dim);
     int32_t end = start + 1;
     const int32_t row_cap = (int32_t)std::min<int64_t>(n_rows, int64_t(start) + block_dim);
     const int64_t base = rp[start];
@@ -88,11 +99,13 @@ int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
 
 }  // namespace argcsr
 
-extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
-                           int32_t block_dim, int32_t desired_chunk_size, int32_t format,
-                           int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy) {
-  using namespace argcsr;
-  clear_error();
+namespace argcsr {
+namespace {
+
+int plan_impl(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
+              int32_t desired_chunk_size, int32_t format, int32_t region_rows,
+              const int32_t* region_desired, int32_t* n_groups, int64_t* n_slots,
+              int32_t* n_heavy) {
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
   if (format != ARGCSR_FORMAT_ARG && format != ARGCSR_FORMAT_RG)
     return fail(ARGCSR_EINVAL, "unknown format %d", format);
@@ -102,8 +115,11 @@ extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
                 kMaxGroupRows);
   int rc = check_row_ptr(n_rows, row_ptr_host);
   if (rc) return rc;
+  rc = check_regions(n_rows, region_rows, region_desired);
+  if (rc) return rc;
   std::vector<argcsr_group_info> groups;
-  rc = group_rows(n_rows, row_ptr_host, block_dim, desired_chunk_size, format, &groups);
+  rc = group_rows(n_rows, row_ptr_host, block_dim, desired_chunk_size, format, &groups,
+                  region_rows, region_desired);
   if (rc) return rc;
   // step 2 is independent per group: split large matrices over host threads
   std::vector<int32_t> chunk(groups.size());
@@ -130,5 +146,53 @@ extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
   if (n_heavy) *n_heavy = heavy;
   if (slots > INT32_MAX)
     return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", (long long)slots);
+  return ARGCSR_OK;
+}
+
+}  // namespace
+}  // namespace argcsr
+
+extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,
+                           int32_t block_dim, int32_t desired_chunk_size, int32_t format,
+                           int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy) {
+  argcsr::clear_error();
+  return argcsr::plan_impl(n_rows, row_ptr_host, block_dim, desired_chunk_size, format, 0,
+                           nullptr, n_groups, n_slots, n_heavy);
+}
+
+extern "C" int argcsr_plan_regions(int32_t n_rows, const int32_t* row_ptr_host,
+                                   int32_t block_dim, int32_t region_rows,
+                                   const int32_t* region_desired, int32_t* n_groups,
+                                   int64_t* n_slots, int32_t* n_heavy) {
+  using namespace argcsr;
+  clear_error();
+  if (!region_desired) return fail(ARGCSR_EINVAL, "region_desired is NULL");
+  return plan_impl(n_rows, row_ptr_host, block_dim, 1, ARGCSR_FORMAT_ARG, region_rows,
+                   region_desired, n_groups, n_slots, n_heavy);
+}
+
+// The Sec. 5 rule applied per region: a region whose rows are regular (its
+// longest row at most twice its mean length) gets desiredChunkSize = its
+// longest row, capped at max_desired, so that its groups take block_dim rows
+// with one chunk each; any other region gets 1, the robust setting.
+extern "C" int argcsr_choose_region_desired(int32_t n_rows, const int32_t* row_ptr_host,
+                                            int32_t region_rows, int32_t max_desired,
+                                            int32_t* region_desired) {
+  using namespace argcsr;
+  clear_error();
+  if (region_rows < 1 || max_desired < 1 || (n_rows > 0 && !region_desired))
+    return fail(ARGCSR_EINVAL, "region_rows and max_desired must be >= 1");
+  int rc = check_row_ptr(n_rows, row_ptr_host);
+  if (rc) return rc;
+  for (int64_t first = 0; first < n_rows; first += region_rows) {
+    const int64_t end = std::min<int64_t>(n_rows, first + region_rows);
+    int64_t longest = 0;
+    for (int64_t r = first; r < end; ++r)
+      longest = std::max<int64_t>(longest, int64_t(row_ptr_host[r + 1]) - row_ptr_host[r]);
+    const int64_t nnz = int64_t(row_ptr_host[end]) - row_ptr_host[first];
+    const bool regular = longest > 0 && longest * (end - first) <= 2 * nnz;
+    region_desired[first / region_rows] =
+        regular ? int32_t(std::min<int64_t>(longest, max_desired)) : 1;
+  }
   return ARGCSR_OK;
 }

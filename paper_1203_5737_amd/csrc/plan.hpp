@@ -17,8 +17,15 @@ int check_row_ptr(int32_t n_rows, const int32_t* rp);
 // a row that would break either limit opens the next group.  Fills
 // first_row/size of every group (offset and chunk_size left 0).
 // Row-grouped CSR (format ARGCSR_FORMAT_RG): groups of block_dim rows.
+// With region_desired (host, ceil(n_rows / region_rows) entries >= 1) the
+// group that opens at row s takes region_desired[s / region_rows] instead
+// of `desired`.
 int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
-               int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups);
+               int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups,
+               int32_t region_rows = 0, const int32_t* region_desired = nullptr);
+
+// Checks a region table: region_rows >= 1 and every entry >= 1.
+int check_regions(int32_t n_rows, int32_t region_rows, const int32_t* region_desired);
 
 // Step 2 sizing: the smallest chunk size c >= 1 for which the rows of the
 // group need at most block_dim chunks, sum max(1, ceil(L_r / c)).

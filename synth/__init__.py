@@ -261,6 +261,25 @@ def workload_stencil27(n: int = 128):
     return A, uniform_vector(A.n_cols, xr)
 
 
+def workload_mixed(side: int = 64):
+    """Rows of two kinds in one square matrix of n = 2*side^3 rows: the first
+    side^3 rows are a 27-point stencil on a side^3 grid (regular rows, columns
+    in the first half), the rest power-law rows (clip(Zipf(2.0), 1, 10^4),
+    distinct uniform columns over all n) -- a matrix whose regularity
+    changes between regions of rows; x U[-1,1]."""
+    s, v, xr = streams(6)
+    St = stencil27_weighted(side, v)
+    m = St.n_rows
+    n = 2 * m
+    L = np.clip(s.zipf(2.0, m), 1, 10_000).astype(np.int64)
+    P = random_csr(L, n, s, v)
+    rp = np.concatenate([St.rp, St.rp[-1] + P.rp[1:]]).astype(np.int32)
+    col = np.concatenate([St.col, P.col]).astype(np.int32)
+    val = np.concatenate([St.val, P.val])
+    A = Csr(n, n, rp, col, val)
+    return A, uniform_vector(n, xr)
+
+
 def batch_member(k: int, n_lo: float = 1e3, n_hi: float = 2e5):
     """Matrix k of the mixed batch: n log-uniform in [n_lo, n_hi]; even k has
     U{5..50} nonzeros per row, odd k clip(Zipf(2.2), 1, min(5000, n))."""

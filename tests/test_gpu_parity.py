@@ -232,6 +232,44 @@ def test_row_grouped_spmv(ac):
 
 
 # ---------------------------------------------------------------------------
+# desiredChunkSize per region of rows (reading R10)
+# ---------------------------------------------------------------------------
+
+def compare_regions(ac, A, T, region_rows, D, dtype=0, device_grouping=False):
+    announce(f"regions n={A.n_rows} T={T} region_rows={region_rows} device={device_grouping}")
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    M = ac.convert(dev, T, 0, dtype, region_rows=region_rows, region_desired=D,
+                   device_grouping=device_grouping)
+    ref = oracle.convert_regions(A.rp, A.col, A.val, T, region_rows, D, dtype)
+    assert np.array_equal(M.groups.cpu().numpy(), ref.groups)
+    assert np.array_equal(M.threads_mapping.cpu().numpy(), ref.tm)
+    assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
+    gv = M.values.cpu()
+    gbits = gv.view(torch.int64 if dtype == 0 else torch.int32 if dtype == 1 else torch.int16)
+    rbits = ref.values.view(np.int64 if dtype == 0 else np.int32 if dtype == 1 else np.int16)
+    assert np.array_equal(gbits.numpy(), rbits)
+    return dev, M
+
+
+def test_regions_conversion_and_spmv(ac):
+    A, x = synth.workload_mixed(16)
+    D = ac.choose_region_desired(A.rp, 512)
+    assert D.min() == 1 and D.max() == 27
+    for T, dev_group, dtype in [(64, False, 0), (128, True, 0), (256, False, 1), (64, True, 2)]:
+        dev, M = compare_regions(ac, A, T, 512, D, dtype, dev_group)
+        if dtype == 0:
+            check_f64(A, x, gpu_spmv(ac, M, x))
+    rng = np.random.default_rng(50)
+    for i in range(6):
+        L = rng.integers(0, int(rng.choice([4, 40])), int(rng.integers(100, 3000)))
+        A2 = csr_from_lengths(L, 5000, 200 + i)
+        region_rows = int(rng.integers(1, 700))
+        D2 = rng.integers(1, 9, -(-A2.n_rows // region_rows)).astype(np.int32)
+        compare_regions(ac, A2, int(rng.choice([1, 64, 100, 256])), region_rows, D2,
+                        device_grouping=bool(i % 2))
+
+
+# ---------------------------------------------------------------------------
 # SpMV
 # ---------------------------------------------------------------------------
 

@@ -106,6 +106,35 @@ def test_plan_row_grouped_matches_oracle(L, ora, lengths, T):
     assert plan(L, rp, T, 0, 1) == ora.rg_sizes(rp, T)
 
 
+@settings(max_examples=120, deadline=None)
+@given(lengths=st.lists(st.integers(0, 120), min_size=0, max_size=200),
+       T=st.sampled_from([1, 7, 64, 128]), region_rows=st.integers(1, 60),
+       seed=st.integers(0, 2**31 - 1))
+def test_plan_regions_matches_oracle(L, ora, lengths, T, region_rows, seed):
+    import paper_1203_5737_amd as ac
+    rng = np.random.default_rng(seed)
+    rp = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    D = rng.integers(1, 9, max(1, -(-len(lengths) // region_rows))).astype(np.int32)
+    rc, G, S = ora.sizes_regions(rp, T, region_rows, D)
+    assert rc == 0
+    assert ac.plan_regions(rp, T, region_rows, D)[:2] == (G, S)
+
+
+def test_choose_region_desired_rule(L):
+    """Regular regions (longest row <= 2 x mean) get their longest row,
+    capped; irregular or empty regions get 1."""
+    import paper_1203_5737_amd as ac
+    lengths = [4, 5, 6, 5] + [1, 1, 1, 40] + [0, 0, 0, 0] + [27] * 4 + [100] * 2
+    rp = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    assert ac.choose_region_desired(rp, 4, 64).tolist() == [6, 1, 1, 27, 64]
+    assert ac.choose_region_desired(rp, 4, 16).tolist() == [6, 1, 1, 16, 16]
+    assert ac.choose_region_desired(np.zeros(1, dtype=np.int32), 4).tolist() == []
+    with pytest.raises(ac.ArgCsrError):
+        ac.plan_regions(rp, 64, 4, [1, 1, 0, 1, 1])              # an entry < 1
+    with pytest.raises(ac.ArgCsrError):
+        ac.plan_regions(rp, 64, 0, [1])                          # region_rows < 1
+
+
 def test_plan_errors(L):
     from paper_1203_5737_amd import _lib
     good = np.array([0, 2, 3], dtype=np.int32)
