@@ -341,6 +341,10 @@ typedef struct {
   double cg_inner_tol;         /* residual reduction of one FP32-matrix inner cycle */
   int32_t cg_max_inner;        /* inner iterations per refinement cycle */
   int32_t cg_max_iter;         /* inner iterations per solve; then ARGCSR_ENOCONV */
+  int64_t staging_bytes;       /* pinned host staging for request inputs and results,
+                                  filled and drained by a copy thread so the scheduler
+                                  never waits on host copies: 0 = 256 MiB, < 0 = none
+                                  (then copies go straight to/from the caller's memory) */
 } argcsr_server_config;
 
 typedef enum {

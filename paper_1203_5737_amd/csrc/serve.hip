@@ -21,9 +21,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -42,6 +44,8 @@
 
 namespace argcsr {
 namespace {
+
+constexpr size_t kDefaultStaging = size_t(256) << 20;   // pinned staging when the config says 0
 
 int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -77,6 +81,40 @@ class Arena {
   RangeAllocator ranges_;
 };
 
+// Pinned host memory for request inputs and results, carved up like the
+// device arena.  Thread-safe: the scheduler allocates, the copy helper
+// releases.
+class PinnedArena {
+ public:
+  int init(size_t bytes) {
+    if (bytes == 0) return ARGCSR_OK;
+    if (hipHostMalloc(&base_, bytes, hipHostMallocDefault) != hipSuccess) {
+      base_ = nullptr;
+      return fail(ARGCSR_ENOMEM, "pinned staging of %zu bytes could not be allocated", bytes);
+    }
+    ranges_.reset(bytes);
+    return ARGCSR_OK;
+  }
+  ~PinnedArena() {
+    if (base_) (void)hipHostFree(base_);
+  }
+  void* alloc(size_t bytes) {
+    std::lock_guard<std::mutex> lock(mu_);
+    if (!base_) return nullptr;
+    const size_t off = ranges_.alloc(bytes);
+    return off == RangeAllocator::kNone ? nullptr : static_cast<char*>(base_) + off;
+  }
+  void release(void* p) {
+    std::lock_guard<std::mutex> lock(mu_);
+    if (p) ranges_.release(size_t(static_cast<char*>(p) - static_cast<char*>(base_)));
+  }
+
+ private:
+  void* base_ = nullptr;
+  RangeAllocator ranges_;
+  std::mutex mu_;
+};
+
 struct Resident {
   int64_t id = 0;
   argcsr_matrix m64{};        // FP64 values
@@ -104,6 +142,20 @@ struct Request {
   float* p32 = nullptr;
   float* q32 = nullptr;
   Resident* mat = nullptr;
+  // pinned staging of the input (set by the copy helper when filled) and of
+  // the result
+  void* stage = nullptr;
+  std::atomic<int> staged{0};
+};
+
+// Work of the copy helper thread: fill a request's pinned input from the
+// caller's buffer, or, once `done` has fired, copy its pinned result into
+// the caller's buffer and publish it.
+struct CopyJob {
+  Request* r = nullptr;
+  void* stage = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;    // result copies only
 };
 
 }  // namespace
@@ -134,6 +186,16 @@ struct argcsr_server {
   argcsr::CgScalars* d_scalars = nullptr;
   argcsr::CgScalars* h_scalars = nullptr;   // pinned
   argcsr::WorkQueues* d_queues = nullptr;
+  int32_t mspmv_grid[2] = {1, 1};           // persistent grid per dtype (FP32, FP64)
+  // pinned staging and its copy helper
+  argcsr::PinnedArena pinned;
+  std::thread helper;
+  std::mutex hmu;
+  std::condition_variable hcv;
+  std::deque<argcsr::CopyJob> jobs;          // guarded by hmu
+  bool helper_stop = false;                  // guarded by hmu
+  std::vector<argcsr::Request*> staging;     // scheduler: waiting for their input copy
+  std::vector<void*> stage_release;          // scheduler: free after the next step's sync
 };
 
 namespace argcsr {
@@ -289,8 +351,91 @@ void release_request(argcsr_server* s, Request* r) {
   r->slot = -1;
 }
 
+struct Span {
+  void* dev;
+  size_t bytes;
+};
+
+// The device vector a request's input goes to, and the one its result
+// comes from (request vectors and matrix must be set).
+Span input_of(const Request* r) {
+  const argcsr_matrix& A = r->mat->m64;
+  if (r->q.kind == ARGCSR_REQ_SPMV) return Span{r->x32, sizeof(float) * size_t(A.n_cols)};
+  return Span{r->v64[0], sizeof(double) * size_t(A.n_rows)};
+}
+
+Span output_of(const Request* r) {
+  const argcsr_matrix& A = r->mat->m64;
+  if (r->q.kind == ARGCSR_REQ_SPMV) return Span{r->y32, sizeof(float) * size_t(A.n_rows)};
+  return Span{r->v64[1], sizeof(double) * size_t(A.n_rows)};
+}
+
+// Hands a finished request's result to the caller with `status`: an
+// asynchronous copy into pinned staging that the copy helper completes and
+// publishes, or, without staging space, a synchronous copy and publish here.
+// Frees the request's device vectors either way (in stream order, so the
+// copy still reads them).
+void finish(argcsr_server* s, Request* r, int status) {
+  const Span out = output_of(r);
+  r->res.status = status;
+  void* st = s->pinned.alloc(out.bytes);
+  hipEvent_t ev = nullptr;
+  if (st && hipMemcpyAsync(st, out.dev, out.bytes, hipMemcpyDeviceToHost, s->stream) == hipSuccess &&
+      hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+      hipEventRecord(ev, s->stream) == hipSuccess) {
+    release_request(s, r);
+    std::lock_guard<std::mutex> lock(s->hmu);
+    s->jobs.push_back(CopyJob{r, st, out.bytes, ev});
+    s->hcv.notify_one();
+    return;
+  }
+  if (ev) (void)hipEventDestroy(ev);
+  if (st) {
+    (void)hipStreamSynchronize(s->stream);     // the copy may have been queued
+    s->pinned.release(st);
+  }
+  if (hipMemcpy(r->q.out, out.dev, out.bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    r->res.status = fail(ARGCSR_EHIP, "result copy failed");
+  release_request(s, r);
+  publish(s, r);
+  delete r;
+}
+
+// The copy helper thread: host-side copies between callers' buffers and the
+// pinned staging, so that the scheduler never waits on them.
+void copy_helper(argcsr_server* s) {
+  (void)hipSetDevice(s->cfg.device);
+  for (;;) {
+    CopyJob j;
+    {
+      std::unique_lock<std::mutex> lock(s->hmu);
+      s->hcv.wait(lock, [&] { return s->helper_stop || !s->jobs.empty(); });
+      if (s->jobs.empty()) return;
+      j = s->jobs.front();
+      s->jobs.pop_front();
+    }
+    if (j.done) {                              // a result: wait for its copy, hand it over
+      if (hipEventSynchronize(j.done) != hipSuccess)
+        j.r->res.status = ARGCSR_EHIP;
+      else
+        std::memcpy(j.r->q.out, j.stage, j.bytes);
+      (void)hipEventDestroy(j.done);
+      s->pinned.release(j.stage);
+      publish(s, j.r);
+      delete j.r;
+    } else {                                   // an input: fill the staging, wake the scheduler
+      std::memcpy(j.stage, j.r->q.in, j.bytes);
+      j.r->staged.store(1, std::memory_order_release);
+      std::lock_guard<std::mutex> lock(s->mu);
+      s->cv_work.notify_one();
+    }
+  }
+}
+
 // Moves a queued SPMV/CG request into a slot: allocates its vectors and
-// uploads its input.  Returns ARGCSR_EBUSY if memory is short right now.
+// starts its input copy (staged requests become active once the copy
+// helper has filled their staging).  Returns ARGCSR_EBUSY if memory is
+// short right now.
 int activate(argcsr_server* s, Request* r) {
   auto it = s->resident.find(r->q.matrix_id);
   if (it == s->resident.end())
@@ -312,8 +457,6 @@ int activate(argcsr_server* s, Request* r) {
       r->blocks.clear();
       return ARGCSR_EBUSY;
     }
-    ARGCSR_HIP(hipMemcpyAsync(r->x32, r->q.in, sizeof(float) * size_t(A.n_cols),
-                              hipMemcpyHostToDevice, s->stream));
   } else {
     if (A.n_rows != A.n_cols) return fail(ARGCSR_EINVAL, "CG needs a square matrix");
     const size_t n = size_t(std::max(A.n_rows, 1));
@@ -326,12 +469,22 @@ int activate(argcsr_server* s, Request* r) {
       r->blocks.clear();
       return ARGCSR_EBUSY;
     }
-    ARGCSR_HIP(hipMemcpyAsync(r->v64[0], r->q.in, sizeof(double) * size_t(A.n_rows),
-                              hipMemcpyHostToDevice, s->stream));
     ARGCSR_HIP(hipMemsetAsync(r->v64[1], 0, sizeof(double) * size_t(A.n_rows), s->stream));
     r->phase = kPhaseStart;
   }
   r->mat = m;
+  // the input: through pinned staging filled by the copy helper (the
+  // scheduler uploads it once staged), or, without staging space, straight
+  // from the caller's memory
+  const Span in = input_of(r);
+  r->stage = s->pinned.alloc(in.bytes);
+  if (r->stage) {
+    std::lock_guard<std::mutex> lock(s->hmu);
+    s->jobs.push_back(CopyJob{r, r->stage, in.bytes, nullptr});
+    s->hcv.notify_one();
+  } else {
+    ARGCSR_HIP(hipMemcpyAsync(in.dev, r->q.in, in.bytes, hipMemcpyHostToDevice, s->stream));
+  }
   m->last_use = now_ns();
   r->slot = s->free_slots.back();
   s->free_slots.pop_back();
@@ -373,17 +526,22 @@ int ensure_desc(argcsr_server* s, size_t bytes) {
   return ARGCSR_OK;
 }
 
+// Persistent grid of mspmv_kernel<DT>: the workgroups that fit, at most 8 per CU.
+template <int DT>
+int32_t mspmv_grid_cap(int device) {
+  int cus = 0, per_cu = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mspmv_kernel<DT>, kSpmvWaves * 64, 0);
+  return std::max(1, cus * std::max(1, std::min(per_cu, 8)));
+}
+
 template <int DT>
 void launch_mspmv(argcsr_server* s, const MatWork* d_w, int32_t n, int32_t groups, int32_t heavy,
                   WorkQueues* q) {
-  int dev = 0, cus = 0, per_cu = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mspmv_kernel<DT>, kSpmvWaves * 64, 0);
-  per_cu = std::max(1, std::min(per_cu, 8));
+  const int64_t cap = s->mspmv_grid[DT == ARGCSR_F64 ? 1 : 0];
   const int64_t work = int64_t(heavy) + (int64_t(groups) + kMspmvGrab * kSpmvWaves - 1) /
                                             (kMspmvGrab * kSpmvWaves);
-  const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(cus) * per_cu, work)));
+  const int grid = int(std::max<int64_t>(1, std::min<int64_t>(cap, work)));
   mspmv_kernel<DT><<<grid, kSpmvWaves * 64, 0, s->stream>>>(d_w, n, groups, heavy, q);
 }
 
@@ -456,15 +614,15 @@ int step(argcsr_server* s) {
   }
   ARGCSR_HIP(hipGetLastError());
   ARGCSR_HIP(hipStreamSynchronize(s->stream));
+  for (void* p : s->stage_release) s->pinned.release(p);   // their uploads have run
+  s->stage_release.clear();
 
   // retire / advance
   std::vector<Request*> keep;
   for (Request* r : s->active) {
     bool done = false;
+    int status = ARGCSR_OK;
     if (r->q.kind == ARGCSR_REQ_SPMV) {
-      rc = hipMemcpy(r->q.out, r->y32, sizeof(float) * size_t(r->mat->m64.n_rows),
-                     hipMemcpyDeviceToHost) == hipSuccess ? ARGCSR_OK : ARGCSR_EHIP;
-      r->res.status = rc;
       done = true;
     } else {
       const CgScalars& sc = s->h_scalars[r->slot];
@@ -480,10 +638,7 @@ int step(argcsr_server* s) {
         if (r->phase == kPhaseOuter) r->res.refinements++;
         r->res.relres = sc.bnorm2 > 0.0 ? std::sqrt(sc.rr / sc.bnorm2) : 0.0;
         if (r->res.relres <= s->cfg.cg_tol || r->res.iterations >= s->cfg.cg_max_iter) {
-          const bool conv = r->res.relres <= s->cfg.cg_tol;
-          rc = hipMemcpy(r->q.out, r->v64[1], sizeof(double) * size_t(r->mat->m64.n_rows),
-                         hipMemcpyDeviceToHost) == hipSuccess ? ARGCSR_OK : ARGCSR_EHIP;
-          r->res.status = rc != ARGCSR_OK ? rc : conv ? ARGCSR_OK : ARGCSR_ENOCONV;
+          status = r->res.relres <= s->cfg.cg_tol ? ARGCSR_OK : ARGCSR_ENOCONV;
           done = true;
         } else {
           r->phase = kPhaseInner;
@@ -492,13 +647,8 @@ int step(argcsr_server* s) {
         }
       }
     }
-    if (done) {
-      release_request(s, r);
-      publish(s, r);
-      delete r;
-    } else {
-      keep.push_back(r);
-    }
+    if (done) finish(s, r, status);
+    else keep.push_back(r);
   }
   s->active.swap(keep);
   std::lock_guard<std::mutex> lock(s->mu);
@@ -510,8 +660,14 @@ void scheduler(argcsr_server* s) {
   (void)hipSetDevice(s->cfg.device);
   for (;;) {
     {
+      auto staged_ready = [&] {
+        for (Request* r : s->staging)
+          if (r->staged.load(std::memory_order_acquire)) return true;
+        return false;
+      };
       std::unique_lock<std::mutex> lock(s->mu);
-      if (s->active.empty() && s->pending.empty() && s->incoming.empty() && !s->stop)
+      if (s->active.empty() && s->pending.empty() && s->incoming.empty() && !s->stop &&
+          !staged_ready())
         s->cv_work.wait_for(lock, std::chrono::milliseconds(2));
       if (s->stop && s->incoming.empty()) break;
       while (!s->incoming.empty()) {
@@ -558,12 +714,38 @@ void scheduler(argcsr_server* s) {
       }
       s->pending.pop_front();
       if (rc == ARGCSR_OK) {
-        s->active.push_back(r);
+        if (r->stage) s->staging.push_back(r);   // starts once its input is staged
+        else s->active.push_back(r);
       } else {
         release_request(s, r);
         publish(s, r);
         delete r;
       }
+    }
+    // staged inputs: upload (in stream order before the next step) and start
+    for (size_t i = 0; i < s->staging.size();) {
+      Request* r = s->staging[i];
+      if (!r->staged.load(std::memory_order_acquire)) {
+        ++i;
+        continue;
+      }
+      const Span in = input_of(r);
+      if (hipMemcpyAsync(in.dev, r->stage, in.bytes, hipMemcpyHostToDevice, s->stream) !=
+          hipSuccess) {
+        (void)hipStreamSynchronize(s->stream);
+        s->pinned.release(r->stage);
+        r->stage = nullptr;
+        r->res.status = fail(ARGCSR_EHIP, "input upload failed");
+        release_request(s, r);
+        publish(s, r);
+        delete r;
+      } else {
+        s->stage_release.push_back(r->stage);
+        r->stage = nullptr;
+        s->active.push_back(r);
+      }
+      s->staging[i] = s->staging.back();
+      s->staging.pop_back();
     }
     if (!s->active.empty()) {
       const int rc = step(s);
@@ -613,6 +795,8 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
   int rc = ARGCSR_OK;
   if (hipSetDevice(cfg->device) != hipSuccess) rc = fail(ARGCSR_EHIP, "hipSetDevice failed");
   if (!rc) rc = s->arena.init(size_t(cfg->budget_bytes));
+  if (!rc && cfg->staging_bytes >= 0)
+    rc = s->pinned.init(cfg->staging_bytes > 0 ? size_t(cfg->staging_bytes) : kDefaultStaging);
   if (!rc && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
     rc = fail(ARGCSR_EHIP, "hipStreamCreate failed");
   if (!rc && (hipMalloc(&s->d_scalars, sizeof(CgScalars) * size_t(cfg->max_active)) != hipSuccess ||
@@ -629,6 +813,9 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
     return rc;
   }
   for (int32_t k = cfg->max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
+  s->mspmv_grid[0] = mspmv_grid_cap<ARGCSR_F32>(cfg->device);
+  s->mspmv_grid[1] = mspmv_grid_cap<ARGCSR_F64>(cfg->device);
+  s->helper = std::thread(copy_helper, s);
   s->worker = std::thread(scheduler, s);
   *out = s;
   return ARGCSR_OK;
@@ -726,6 +913,20 @@ extern "C" int argcsr_server_destroy(argcsr_server* s) {
     s->cv_work.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  {
+    std::lock_guard<std::mutex> lock(s->hmu);   // the helper drains its queue, then exits
+    s->helper_stop = true;
+    s->hcv.notify_all();
+  }
+  if (s->helper.joinable()) s->helper.join();
+  for (Request* r : s->staging) {               // never started
+    s->pinned.release(r->stage);
+    r->res.status = ARGCSR_ENOTFOUND;
+    release_request(s, r);
+    publish(s, r);
+    delete r;
+  }
+  s->staging.clear();
   (void)hipStreamSynchronize(s->stream);
   (void)hipStreamDestroy(s->stream);
   if (s->d_desc) (void)hipFree(s->d_desc);

@@ -95,12 +95,29 @@ def test_serve_results_and_alone_vs_mix(srv_mod):
             assert r["relres"] <= 1e-10 and r["refinements"] >= 1 and r["iterations"] > 0
             assert true_relres(mats[m], out, inp) <= 1e-10
     print("[gpu] serve alone", flush=True)
-    with srv_mod.Server(budget_bytes=1 << 30, max_active=1) as srv:  # one request at a time
+    # one request at a time, and without pinned staging: inputs and results
+    # go straight between the caller's memory and the device
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=1, staging_bytes=-1) as srv:
         admit_all(srv, mats)
         alone_out, alone_res = run_requests(srv, mats, reqs)
     for a, b, ra, rb in zip(mix_out, alone_out, mix_res, alone_res):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
         assert ra["iterations"] == rb["iterations"]
+
+
+def test_serve_small_staging_falls_back(srv_mod):
+    """A staging arena too small for most requests: those bypass it, the
+    others go through it; results are the same as with ample staging."""
+    print("\n[gpu] serve small staging", flush=True)
+    mats = pool(4)
+    reqs = make_requests(mats, 16, 7)
+    outs = []
+    for staging in (0, 64 << 10):
+        with srv_mod.Server(budget_bytes=1 << 30, max_active=8, staging_bytes=staging) as srv:
+            admit_all(srv, mats)
+            outs.append(run_requests(srv, mats, reqs)[0])
+    for a, b in zip(*outs):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
 
 
 def test_serve_requests_join_while_others_run(srv_mod):
