@@ -389,6 +389,37 @@ def test_spmv_heavy_schedule_on_and_off(ac):
         check_f64(A, x, gpu_spmv(ac, M0, x))
 
 
+def test_concurrent_conversions_on_separate_streams(ac):
+    """Conversions from several host threads, each on its own stream, at
+    once: conversion scratch is stream-ordered per call, so every result is
+    the oracle's."""
+    import threading
+    mats = [powerlaw_sample(40_000 + 7_000 * i, seed=70 + i)[0] for i in range(4)]
+    refs = [oracle.convert(A.rp, A.col, A.val, 64, 1) for A in mats]
+    devs = [ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV) for A in mats]
+    errors = []
+
+    def work(i):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for rep in range(5):
+                    M = ac.convert(devs[i], 64, 1, stream=st, device_grouping=bool(rep % 2))
+                    st.synchronize()
+                    if not (np.array_equal(M.groups.cpu().numpy(), refs[i].groups) and
+                            np.array_equal(M.columns.cpu().numpy(), refs[i].columns)):
+                        errors.append((i, rep))
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append((i, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+
+
 def test_spmv_deterministic(ac):
     A, x = powerlaw_sample(100_000, seed=5)
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
