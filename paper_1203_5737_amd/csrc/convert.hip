@@ -246,18 +246,23 @@ __global__ __launch_bounds__(kWaves * 64) void fill_kernel(
     }
   }
   wave_lds_sync();
-  const uint32_t n = uint32_t(c) * uint32_t(T);           // <= INT32_MAX (checked)
-  for (uint32_t s = lane; s < n; s += 64) {
-    const int32_t j = int32_t(s / uint32_t(T));
-    const int32_t k = int32_t(s - uint32_t(j) * uint32_t(T));
-    const int64_t dst = int64_t(gi.offset) + s;
-    if (j < src_len[w][k]) {
-      const int32_t e = src_start[w][k] + j;
-      columns[dst] = col[e];
-      values[dst] = Val<DT>::from_f64(val[e]);
-    } else {
-      columns[dst] = -1;
-      values[dst] = S(0);
+  // 64 chunks at a time, all their steps: for each step the wave writes 64
+  // consecutive slots, and each lane reads its own chunk's consecutive CSR
+  // elements, so the rows being read stay in L1 across the steps
+  for (int32_t k = lane; k - lane < T; k += 64) {
+    const bool mine = k < T;
+    const int32_t start = mine ? src_start[w][k] : 0;
+    const int32_t len = mine ? src_len[w][k] : 0;
+    for (int32_t j = 0; j < c; ++j) {
+      if (!mine) continue;
+      const int64_t dst = int64_t(gi.offset) + int64_t(j) * T + k;
+      if (j < len) {
+        columns[dst] = col[start + j];
+        values[dst] = Val<DT>::from_f64(val[start + j]);
+      } else {
+        columns[dst] = -1;
+        values[dst] = S(0);
+      }
     }
   }
 }
