@@ -144,10 +144,10 @@ def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
 
 
 def f32_variant(A, x, dev, timer, torch, ac, steps):
-    """The same matrix with FP32 values, x and y (T=256, D=1), against plain
+    """The same matrix with FP32 values, x and y (T=128, D=1), against plain
     CSR in FP32, timed the same way."""
     B = useful_bytes(A, 1)
-    M = ac.convert(dev, 256, 1, 1)
+    M = ac.convert(dev, 128, 1, 1)
     xd = torch.from_numpy(x).to("cuda", torch.float32)
     yd = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
     f = lambda: ac.spmv(M, xd, yd)
@@ -161,7 +161,7 @@ def f32_variant(A, x, dev, timer, torch, ac, steps):
         c, _ = timer.run(g, max(10, steps // 5))
         if best is None or c.mean() < best[1].mean():
             best = (V, c)
-    return {"block_dim": 256, "desired_chunk_size": 1, "mean_ms": float(t.mean()),
+    return {"block_dim": 128, "desired_chunk_size": 1, "mean_ms": float(t.mean()),
             "gbps": B / (t.mean() * 1e-3) / 1e9, "csr_gbps": B / (best[1].mean() * 1e-3) / 1e9,
             "csr_lanes_per_row": best[0], "speedup_vs_csr": float(best[1].mean() / t.mean())}
 
