@@ -605,6 +605,19 @@ def test_regions_hand_worked_example(ora):
     assert a.groups[:, :2].tolist() == [[0, 2], [2, 3], [5, 2], [7, 3]]
 
 
+def test_regions_group_keeps_its_limit_after_crossing(ora):
+    """T = 4, regions of 4 rows with D = 2, 1, 1 (limits 8, 4, 4), row
+    lengths 3,3,3,3 | 1,1,1,1 | 1,1.  The group opened at row 2 keeps the
+    limit 8 of its first row's region after it runs into region 1, so it takes
+    rows 2-5 (3+3+1+1 = 8, four rows); a limit taken from the row just added
+    would close it after row 4.  Then rows 6-9 (4 nonzeros, four rows)."""
+    L = [3, 3, 3, 3, 1, 1, 1, 1, 1, 1]
+    rp = np.concatenate([[0], np.cumsum(L)]).astype(np.int32)
+    col = np.zeros(rp[-1], dtype=np.int32)
+    a = ora.convert_regions(rp, col, np.ones(rp[-1]), 4, 4, [2, 1, 1])
+    assert a.groups[:, :2].tolist() == [[0, 2], [2, 4], [6, 4]]
+
+
 @settings(max_examples=80, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
 @given(lengths=st.lists(st.integers(0, 60), min_size=0, max_size=120),
        T=st.sampled_from([1, 2, 5, 16, 64]), region_rows=st.integers(1, 40),
