@@ -12,7 +12,8 @@
 //   fill_kernel     step 4: every slot (j, k) of a group -- element j of chunk
 //                   k at offset + j*T + k -- is written exactly once: the
 //                   matching CSR element if chunk k's row has one there,
-//                   otherwise the artificial zero (0, -1).
+//                   otherwise the artificial zero (0, -1); the CSR elements
+//                   pass through LDS so that reads and writes are coalesced.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -31,6 +32,9 @@ constexpr int kMaxBlockDim = 1024;    // conversion accepts 1 <= T <= 1024
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 4;         // groups per thread in the offset scan
 constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kMinStage = 256;        // CSR elements one fill wave stages in LDS
+constexpr int kMaxStage = 2048;
+constexpr int kMaxFillWaves = 4;
 
 struct Status {                       // device-side results read back by the host
   int bad_column;
@@ -40,6 +44,23 @@ struct Status {                       // device-side results read back by the ho
 };
 
 __global__ void clear_status_kernel(Status* st) { *st = Status{}; }
+
+// LDS of one fill wave: chunk starts and lengths, then the staged columns and
+// values (the byte count keeps the next wave's region 8-byte aligned)
+template <typename S>
+__host__ __device__ inline size_t fill_lds_bytes(int32_t T, int32_t stage) {
+  const size_t b = sizeof(int32_t) * (2 * size_t(T) + size_t(stage)) + sizeof(S) * size_t(stage);
+  return (b + 7) & ~size_t(7);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int t = __shfl_xor(v, d, 64);
+    v = t < v ? t : v;
+  }
+  return v;
+}
 
 __global__ __launch_bounds__(256) void validate_columns_kernel(
     const int32_t* __restrict__ col, int64_t nnz, int32_t n_cols, Status* st) {
@@ -88,12 +109,19 @@ __global__ __launch_bounds__(kWaves * 64) void chunks_kernel(
     }
     return wave_sum_i64(need);
   };
-  // binary search on the non-increasing chunks_needed(c); row-grouped CSR
-  // takes the upper end, one chunk per row
+  // binary search on the non-increasing chunks_needed(c) between two bounds:
+  // no c below total/T fits, and c = longest (one chunk per row) always does;
+  // since max(1, ceil(L/c)) <= L/c + 1, every c >= total/(T - size) fits too.
+  // Row-grouped CSR, and a group of T rows, take one chunk per row.
   uint32_t lo = uint32_t((total + T - 1) / T);
   lo = lo < 1u ? 1u : lo;
   uint32_t hi = longest < 1 ? 1u : uint32_t(longest);
-  if (row_grouped) lo = hi;
+  if (row_grouped || size >= T) {
+    lo = hi;
+  } else {
+    const int64_t fit = (total + (T - size) - 1) / (T - size);
+    if (fit < int64_t(hi)) hi = fit < 1 ? 1u : uint32_t(fit);
+  }
   while (lo < hi) {
     const uint32_t mid = lo + (hi - lo) / 2;
     if (chunks_needed(mid) <= T) hi = mid;
@@ -211,25 +239,36 @@ __global__ __launch_bounds__(kScanBlock) void heavy_scatter_kernel(
 }
 
 // Step 4, one wave per group.  For every chunk k the wave first records in
-// LDS where its elements start in the CSR arrays and how many there are
-// (0 for free chunks), then writes all c*T slots in slot order.
+// LDS where its elements start in the CSR arrays and how many there are (0 for
+// free chunks).  It then takes the chunks 64 at a time.  The elements of 64
+// consecutive chunks form one contiguous CSR range (a row's chunks follow each
+// other, and so do the rows), so when that range fits the wave's stage of
+// `stage` elements the wave copies it into LDS with coalesced loads,
+// converting the values to their storage type, and then writes the block's
+// slots step by step, 64 consecutive slots per store, each lane taking its
+// chunk's element from LDS.  A block whose range is longer than the stage has
+// each lane read its own chunk's elements directly.
 template <int DT>
-__global__ __launch_bounds__(kWaves * 64) void fill_kernel(
+__global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const double* __restrict__ val, const argcsr_group_info* __restrict__ groups,
-    int32_t n_groups, int32_t T, const int32_t* __restrict__ tm,
+    int32_t n_groups, int32_t T, const int32_t* __restrict__ tm, int32_t stage,
     int32_t* __restrict__ columns, typename Val<DT>::storage* __restrict__ values) {
   using S = typename Val<DT>::storage;
-  __shared__ int32_t src_start[kWaves][kMaxBlockDim];
-  __shared__ int32_t src_len[kWaves][kMaxBlockDim];
+  extern __shared__ int32_t fill_lds[];   // per wave: [T] starts, [T] lengths, stage
   const int lane = lane_id();
   const int w = wave_uniform(int(threadIdx.x >> 6));
-  const int g = blockIdx.x * kWaves + w;
+  const size_t wave_bytes = fill_lds_bytes<S>(T, stage);
+  int32_t* src_start = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(fill_lds) + w * wave_bytes);
+  int32_t* src_len = src_start + T;
+  int32_t* stage_col = src_start + 2 * T;
+  S* stage_val = reinterpret_cast<S*>(stage_col + stage);
+  const int g = blockIdx.x * (blockDim.x >> 6) + w;
   if (g >= n_groups) return;
   const argcsr_group_info gi = groups[g];
   const int32_t c = gi.chunk_size;
 
-  for (int k = lane; k < T; k += 64) src_len[w][k] = 0;
+  for (int k = lane; k < T; k += 64) src_len[k] = 0;
   wave_lds_sync();
   for (int l = lane; l < gi.size; l += 64) {
     const int32_t r = gi.first_row + l;
@@ -240,39 +279,75 @@ __global__ __launch_bounds__(kWaves * 64) void fill_kernel(
     for (int32_t k = begin; k < end; ++k) {
       const int32_t q = k - begin;                    // chunk q of row r
       const int32_t first_elem = q * c;
-      src_start[w][k] = row_start + first_elem;
+      src_start[k] = row_start + first_elem;
       const int32_t left = L - first_elem;
-      src_len[w][k] = left < 0 ? 0 : (left < c ? left : c);
+      src_len[k] = left < 0 ? 0 : (left < c ? left : c);
     }
   }
   wave_lds_sync();
-  // 64 chunks at a time, all their steps: for each step the wave writes 64
-  // consecutive slots, and each lane reads its own chunk's consecutive CSR
-  // elements, so the rows being read stay in L1 across the steps
-  for (int32_t k = lane; k - lane < T; k += 64) {
+  for (int32_t k0 = 0; k0 < T; k0 += 64) {
+    const int32_t k = k0 + lane;
     const bool mine = k < T;
-    const int32_t start = mine ? src_start[w][k] : 0;
-    const int32_t len = mine ? src_len[w][k] : 0;
-    for (int32_t j = 0; j < c; ++j) {
-      if (!mine) continue;
-      const int64_t dst = int64_t(gi.offset) + int64_t(j) * T + k;
-      if (j < len) {
-        columns[dst] = col[start + j];
-        values[dst] = Val<DT>::from_f64(val[start + j]);
-      } else {
-        columns[dst] = -1;
-        values[dst] = S(0);
+    const int32_t start = mine ? src_start[k] : 0;
+    const int32_t len = mine ? src_len[k] : 0;
+    const int32_t lo = wave_min(len > 0 ? start : INT32_MAX);
+    const int32_t hi = wave_max(len > 0 ? start + len : 0);
+    const int32_t extent = hi > lo ? hi - lo : 0;
+    const int64_t dst0 = int64_t(gi.offset) + k;
+    if (extent <= stage) {
+#pragma unroll 8
+      for (int32_t p = lane; p < extent; p += 64) {
+        stage_col[p] = col[lo + p];
+        stage_val[p] = Val<DT>::from_f64(val[lo + p]);
+      }
+      wave_lds_sync();
+      const int32_t rel = start - lo;
+      for (int32_t j = 0; j < c; ++j) {
+        if (!mine) continue;
+        const int64_t dst = dst0 + int64_t(j) * T;
+        if (j < len) {
+          columns[dst] = stage_col[rel + j];
+          values[dst] = stage_val[rel + j];
+        } else {
+          columns[dst] = -1;
+          values[dst] = S(0);
+        }
+      }
+      wave_lds_sync();   // the next block overwrites the stage
+    } else {
+      for (int32_t j = 0; j < c; ++j) {
+        if (!mine) continue;
+        const int64_t dst = dst0 + int64_t(j) * T;
+        if (j < len) {
+          columns[dst] = col[start + j];
+          values[dst] = Val<DT>::from_f64(val[start + j]);
+        } else {
+          columns[dst] = -1;
+          values[dst] = S(0);
+        }
       }
     }
   }
 }
 
+// The stage holds the blocks of chunks up to twice the matrix's mean chunk
+// size (at least 4 and at most 32 elements per chunk); small stages leave room
+// for 4 waves per workgroup, which the many short groups of irregular
+// matrices need to hide their latency.
 template <int DT>
-void launch_fill(int blocks, hipStream_t s, const int32_t* rp, const int32_t* col,
+void launch_fill(int32_t n_groups, hipStream_t s, const int32_t* rp, const int32_t* col,
                  const double* val, const argcsr_matrix* out) {
-  fill_kernel<DT><<<blocks, kWaves * 64, 0, s>>>(
-      rp, col, val, out->groups, out->n_groups, out->block_dim, out->threads_mapping,
-      out->columns, static_cast<typename Val<DT>::storage*>(out->values));
+  using S = typename Val<DT>::storage;
+  const int64_t T = out->block_dim;
+  const int64_t mean_chunk = (out->n_slots + int64_t(n_groups) * T - 1) / (int64_t(n_groups) * T);
+  int32_t stage = kMinStage;
+  while (stage < kMaxStage && stage < 128 * mean_chunk) stage *= 2;
+  const int waves = stage <= 512 ? kMaxFillWaves : 1;
+  const size_t lds = fill_lds_bytes<S>(int32_t(T), stage) * size_t(waves);
+  const uint32_t blocks = uint32_t((int64_t(n_groups) + waves - 1) / waves);
+  fill_kernel<DT><<<dim3(blocks), 64 * waves, lds, s>>>(
+      rp, col, val, out->groups, out->n_groups, out->block_dim, out->threads_mapping, stage,
+      out->columns, static_cast<S*>(out->values));
 }
 
 }  // namespace
@@ -396,10 +471,10 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
                                                         out->heavy_groups);
 
   switch (out->dtype) {
-    case ARGCSR_F64: launch_fill<ARGCSR_F64>(wave_blocks, s, row_ptr, col, val, out); break;
-    case ARGCSR_F32: launch_fill<ARGCSR_F32>(wave_blocks, s, row_ptr, col, val, out); break;
-    case ARGCSR_BF16: launch_fill<ARGCSR_BF16>(wave_blocks, s, row_ptr, col, val, out); break;
-    default: launch_fill<ARGCSR_F16>(wave_blocks, s, row_ptr, col, val, out); break;
+    case ARGCSR_F64: launch_fill<ARGCSR_F64>(G, s, row_ptr, col, val, out); break;
+    case ARGCSR_F32: launch_fill<ARGCSR_F32>(G, s, row_ptr, col, val, out); break;
+    case ARGCSR_BF16: launch_fill<ARGCSR_BF16>(G, s, row_ptr, col, val, out); break;
+    default: launch_fill<ARGCSR_F16>(G, s, row_ptr, col, val, out); break;
   }
   ARGCSR_HIP(hipGetLastError());
   ARGCSR_HIP(hipStreamSynchronize(s));

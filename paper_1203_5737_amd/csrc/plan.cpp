@@ -69,9 +69,13 @@ int32_t min_chunk_size(const int32_t* rp, int32_t first, int32_t size,
   if (size == 1) return int32_t(longest > T ? (longest - 1) / T + 1 : 1);   // one row: ceil(L/T)
   const uint64_t total = uint64_t(rp[first + size]) - uint64_t(rp[first]);
   // chunks_needed is non-increasing in c; at c = longest every row needs one
-  // chunk (size <= block_dim), and no c below total/block_dim can fit.
+  // chunk (size <= block_dim), no c below total/block_dim can fit, and since
+  // max(1, ceil(L/c)) <= L/c + 1 every c >= total/(block_dim - size) fits.
+  // A group of block_dim rows has one chunk per row.
   uint32_t lo = uint32_t(std::max<uint64_t>(1, (total + T - 1) / T));
   uint32_t hi = std::max<uint32_t>(1, longest);
+  if (uint32_t(size) >= T) return int32_t(hi);
+  hi = uint32_t(std::min<uint64_t>(hi, std::max<uint64_t>(1, (total + (T - size) - 1) / (T - size))));
   if (lo >= hi) return int32_t(hi);
   // for c >= lo only rows longer than lo can need more than one chunk
   uint32_t longer[kMaxGroupRows];
