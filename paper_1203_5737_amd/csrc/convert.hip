@@ -16,6 +16,7 @@
 //                   pass through LDS so that reads and writes are coalesced.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -35,10 +36,12 @@ constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kMinStage = 256;        // CSR elements one fill wave stages in LDS
 constexpr int kMaxStage = 2048;
 constexpr int kMaxFillWaves = 4;
+constexpr int kLongSteps = 16;        // steps per LDS tile in fill_long_kernel
+constexpr int kLongGrid = 4096;       // one-wave workgroups of fill_long_kernel
 
 struct Status {                       // device-side results read back by the host
   int bad_column;
-  int pad;
+  int long_items;                     // entries of the fill's long-row work list
   long long total_slots;
   long long total_heavy;
 };
@@ -238,36 +241,12 @@ __global__ __launch_bounds__(kScanBlock) void heavy_scatter_kernel(
       heavy[pos++] = int32_t(base + i);
 }
 
-// Step 4, one wave per group.  For every chunk k the wave first records in
-// LDS where its elements start in the CSR arrays and how many there are (0 for
-// free chunks).  It then takes the chunks 64 at a time.  The elements of 64
-// consecutive chunks form one contiguous CSR range (a row's chunks follow each
-// other, and so do the rows), so when that range fits the wave's stage of
-// `stage` elements the wave copies it into LDS with coalesced loads,
-// converting the values to their storage type, and then writes the block's
-// slots step by step, 64 consecutive slots per store, each lane taking its
-// chunk's element from LDS.  A block whose range is longer than the stage has
-// each lane read its own chunk's elements directly.
-template <int DT>
-__global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
-    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-    const double* __restrict__ val, const argcsr_group_info* __restrict__ groups,
-    int32_t n_groups, int32_t T, const int32_t* __restrict__ tm, int32_t stage,
-    int32_t* __restrict__ columns, typename Val<DT>::storage* __restrict__ values) {
-  using S = typename Val<DT>::storage;
-  extern __shared__ int32_t fill_lds[];   // per wave: [T] starts, [T] lengths, stage
-  const int lane = lane_id();
-  const int w = wave_uniform(int(threadIdx.x >> 6));
-  const size_t wave_bytes = fill_lds_bytes<S>(T, stage);
-  int32_t* src_start = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(fill_lds) + w * wave_bytes);
-  int32_t* src_len = src_start + T;
-  int32_t* stage_col = src_start + 2 * T;
-  S* stage_val = reinterpret_cast<S*>(stage_col + stage);
-  const int g = blockIdx.x * (blockDim.x >> 6) + w;
-  if (g >= n_groups) return;
-  const argcsr_group_info gi = groups[g];
+// For every chunk k of the group: where its elements start in the CSR arrays
+// and how many there are (0 for free chunks), in the wave's LDS tables.
+__device__ inline void chunk_sources(const argcsr_group_info& gi, const int32_t* __restrict__ rp,
+                                     const int32_t* __restrict__ tm, int32_t T, int lane,
+                                     int32_t* src_start, int32_t* src_len) {
   const int32_t c = gi.chunk_size;
-
   for (int k = lane; k < T; k += 64) src_len[k] = 0;
   wave_lds_sync();
   for (int l = lane; l < gi.size; l += 64) {
@@ -285,14 +264,67 @@ __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
     }
   }
   wave_lds_sync();
+}
+
+// The CSR range [lo, lo + extent) that holds the elements of the wave's 64
+// chunks (start, len per lane); extent 0 when they have none.
+__device__ inline int32_t block_extent(int32_t start, int32_t len, int32_t* lo_out) {
+  const int32_t lo = wave_min(len > 0 ? start : INT32_MAX);
+  const int32_t hi = wave_max(len > 0 ? start + len : 0);
+  *lo_out = lo;
+  return hi > lo ? hi - lo : 0;
+}
+
+// Step 4, one wave per group.  For every chunk k the wave first records in
+// LDS where its elements start in the CSR arrays and how many there are (0 for
+// free chunks).  It then takes the chunks 64 at a time.  The elements of 64
+// consecutive chunks form one contiguous CSR range (a row's chunks follow each
+// other, and so do the rows), so when that range fits the wave's stage of
+// `stage` elements the wave copies it into LDS with coalesced loads,
+// converting the values to their storage type, and then writes the block's
+// slots step by step, 64 consecutive slots per store, each lane taking its
+// chunk's element from LDS.  Blocks whose range is longer than the stage are
+// left to fill_long_kernel: a group whose chunks are longer than stage/64
+// elements, the only kind that can have such blocks, appends one work item per
+// tile of kLongSteps steps to a list.
+template <int DT>
+__global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const argcsr_group_info* __restrict__ groups,
+    int32_t n_groups, int32_t T, const int32_t* __restrict__ tm, int32_t stage,
+    Status* __restrict__ st, int32_t* __restrict__ long_list,
+    int32_t* __restrict__ columns, typename Val<DT>::storage* __restrict__ values) {
+  using S = typename Val<DT>::storage;
+  extern __shared__ int32_t fill_lds[];   // per wave: [T] starts, [T] lengths, stage
+  const int lane = lane_id();
+  const int w = wave_uniform(int(threadIdx.x >> 6));
+  const size_t wave_bytes = fill_lds_bytes<S>(T, stage);
+  int32_t* src_start = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(fill_lds) + w * wave_bytes);
+  int32_t* src_len = src_start + T;
+  int32_t* stage_col = src_start + 2 * T;
+  S* stage_val = reinterpret_cast<S*>(stage_col + stage);
+  const int g = blockIdx.x * (blockDim.x >> 6) + w;
+  if (g >= n_groups) return;
+  const argcsr_group_info gi = groups[g];
+  const int32_t c = gi.chunk_size;
+  if (int64_t(c) * 64 > stage) {   // one work item per tile of kLongSteps steps
+    const int32_t n_items = (c + kLongSteps - 1) / kLongSteps;
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(&st->long_items, n_items);
+    base = __shfl(base, 0, 64);
+    for (int32_t t = lane; t < n_items; t += 64) {
+      long_list[2 * int64_t(base + t)] = g;
+      long_list[2 * int64_t(base + t) + 1] = t * kLongSteps;
+    }
+  }
+  chunk_sources(gi, rp, tm, T, lane, src_start, src_len);
   for (int32_t k0 = 0; k0 < T; k0 += 64) {
     const int32_t k = k0 + lane;
     const bool mine = k < T;
     const int32_t start = mine ? src_start[k] : 0;
     const int32_t len = mine ? src_len[k] : 0;
-    const int32_t lo = wave_min(len > 0 ? start : INT32_MAX);
-    const int32_t hi = wave_max(len > 0 ? start + len : 0);
-    const int32_t extent = hi > lo ? hi - lo : 0;
+    int32_t lo;
+    const int32_t extent = block_extent(start, len, &lo);
     const int64_t dst0 = int64_t(gi.offset) + k;
     if (extent <= stage) {
 #pragma unroll 8
@@ -314,18 +346,74 @@ __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
         }
       }
       wave_lds_sync();   // the next block overwrites the stage
-    } else {
-      for (int32_t j = 0; j < c; ++j) {
-        if (!mine) continue;
-        const int64_t dst = dst0 + int64_t(j) * T;
-        if (j < len) {
-          columns[dst] = col[start + j];
-          values[dst] = Val<DT>::from_f64(val[start + j]);
-        } else {
-          columns[dst] = -1;
-          values[dst] = S(0);
-        }
+    }
+  }
+}
+
+// Step 4 for the blocks fill_kernel leaves: those whose CSR range is longer
+// than the stage, from the list of (group, first step) work items (in any
+// order: every slot belongs to one block and one tile).  One-wave workgroups
+// stride over the list; an item moves kLongSteps steps of the group's long
+// blocks through LDS: each load instruction reads kLongSteps consecutive
+// elements of each of 64/kLongSteps chunks (a lane past its chunk's end reads
+// an element of the block and keeps the padding value, so the loads carry no
+// branch and are issued together), and each store writes one step of the 64
+// chunks, 64 consecutive slots.
+template <int DT>
+__global__ __launch_bounds__(64) void fill_long_kernel(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const argcsr_group_info* __restrict__ groups,
+    int32_t T, const int32_t* __restrict__ tm, int32_t stage, const Status* __restrict__ st,
+    const int32_t* __restrict__ long_list, int32_t* __restrict__ columns,
+    typename Val<DT>::storage* __restrict__ values) {
+  using S = typename Val<DT>::storage;
+  constexpr int kPer = 64 / kLongSteps;           // chunks per load instruction
+  __shared__ int32_t tile_col[kLongSteps][65];    // [step][chunk], padded rows
+  __shared__ S tile_val[kLongSteps][65];
+  extern __shared__ int32_t long_tables[];        // [T] starts, [T] lengths
+  int32_t* src_start = long_tables;
+  int32_t* src_len = long_tables + T;
+  const int lane = lane_id();
+  const int jj = lane % kLongSteps, kq = lane / kLongSteps;
+  const int32_t n_items = st->long_items;
+  for (int32_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const argcsr_group_info gi = groups[long_list[2 * int64_t(i)]];
+    const int32_t j0 = long_list[2 * int64_t(i) + 1];
+    const int32_t c = gi.chunk_size;
+    chunk_sources(gi, rp, tm, T, lane, src_start, src_len);
+    for (int32_t k0 = 0; k0 < T; k0 += 64) {
+      const int32_t k = k0 + lane;
+      int32_t lo;
+      if (block_extent(k < T ? src_start[k] : 0, k < T ? src_len[k] : 0, &lo) <= stage) continue;
+      int32_t cv[kLongSteps];
+      double v[kLongSteps];
+      bool ok[kLongSteps];
+#pragma unroll
+      for (int it = 0; it < kLongSteps; ++it) {
+        const int32_t kk = k0 + it * kPer + kq;
+        const int32_t kc = kk < T ? kk : T - 1;
+        const int32_t j = j0 + jj;
+        ok[it] = kk < T && j < src_len[kc];
+        const int32_t e = ok[it] ? src_start[kc] + j : lo;
+        cv[it] = col[e];
+        v[it] = val[e];
       }
+#pragma unroll
+      for (int it = 0; it < kLongSteps; ++it) {
+        const int32_t kl = it * kPer + kq;          // chunk within the block
+        tile_col[jj][kl] = ok[it] ? cv[it] : -1;
+        tile_val[jj][kl] = ok[it] ? Val<DT>::from_f64(v[it]) : S(0);
+      }
+      wave_lds_sync();
+      const int32_t steps = c - j0 < kLongSteps ? c - j0 : kLongSteps;
+      if (k < T)
+#pragma unroll 4
+        for (int32_t u = 0; u < steps; ++u) {
+          const int64_t dst = int64_t(gi.offset) + int64_t(j0 + u) * T + k;
+          columns[dst] = tile_col[u][lane];
+          values[dst] = tile_val[u][lane];
+        }
+      wave_lds_sync();   // the next block or item overwrites the tile and tables
     }
   }
 }
@@ -336,7 +424,7 @@ __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
 // matrices need to hide their latency.
 template <int DT>
 void launch_fill(int32_t n_groups, hipStream_t s, const int32_t* rp, const int32_t* col,
-                 const double* val, const argcsr_matrix* out) {
+                 const double* val, Status* st, int32_t* long_list, const argcsr_matrix* out) {
   using S = typename Val<DT>::storage;
   const int64_t T = out->block_dim;
   const int64_t mean_chunk = (out->n_slots + int64_t(n_groups) * T - 1) / (int64_t(n_groups) * T);
@@ -346,7 +434,11 @@ void launch_fill(int32_t n_groups, hipStream_t s, const int32_t* rp, const int32
   const size_t lds = fill_lds_bytes<S>(int32_t(T), stage) * size_t(waves);
   const uint32_t blocks = uint32_t((int64_t(n_groups) + waves - 1) / waves);
   fill_kernel<DT><<<dim3(blocks), 64 * waves, lds, s>>>(
-      rp, col, val, out->groups, out->n_groups, out->block_dim, out->threads_mapping, stage,
+      rp, col, val, out->groups, out->n_groups, out->block_dim, out->threads_mapping, stage, st,
+      long_list, out->columns, static_cast<S*>(out->values));
+  const int64_t long_blocks = std::min<int64_t>(n_groups, kLongGrid);
+  fill_long_kernel<DT><<<dim3(uint32_t(long_blocks)), 64, sizeof(int32_t) * 2 * size_t(T), s>>>(
+      rp, col, val, out->groups, out->block_dim, out->threads_mapping, stage, st, long_list,
       out->columns, static_cast<S*>(out->values));
 }
 
@@ -417,11 +509,16 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
 
   const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
   StreamScratch ws;
-  rc = ws.alloc(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), s);
+  const int64_t long_capacity = int64_t(G) + out->n_slots / (int64_t(kLongSteps) * T) + 1;
+  rc = ws.alloc(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles) +
+                2 * sizeof(int32_t) * size_t(long_capacity), s);
   if (rc) return rc;
   Status* st = static_cast<Status*>(ws.ptr);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
   int64_t* heavy_tiles = tile_sums + n_tiles;
+  // (group, first step) per tile of the fill's long blocks: at most one per
+  // group plus one per kLongSteps steps of all groups
+  int32_t* long_list = reinterpret_cast<int32_t*>(heavy_tiles + n_tiles);
   // uses the caller's slot count; it is checked against the device total
   // before anything is written to the caller's heavy_groups buffer
   const int32_t heavy_chunk = out->heavy_chunk;
@@ -471,10 +568,10 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
                                                         out->heavy_groups);
 
   switch (out->dtype) {
-    case ARGCSR_F64: launch_fill<ARGCSR_F64>(G, s, row_ptr, col, val, out); break;
-    case ARGCSR_F32: launch_fill<ARGCSR_F32>(G, s, row_ptr, col, val, out); break;
-    case ARGCSR_BF16: launch_fill<ARGCSR_BF16>(G, s, row_ptr, col, val, out); break;
-    default: launch_fill<ARGCSR_F16>(G, s, row_ptr, col, val, out); break;
+    case ARGCSR_F64: launch_fill<ARGCSR_F64>(G, s, row_ptr, col, val, st, long_list, out); break;
+    case ARGCSR_F32: launch_fill<ARGCSR_F32>(G, s, row_ptr, col, val, st, long_list, out); break;
+    case ARGCSR_BF16: launch_fill<ARGCSR_BF16>(G, s, row_ptr, col, val, st, long_list, out); break;
+    default: launch_fill<ARGCSR_F16>(G, s, row_ptr, col, val, st, long_list, out); break;
   }
   ARGCSR_HIP(hipGetLastError());
   ARGCSR_HIP(hipStreamSynchronize(s));

@@ -96,6 +96,28 @@ def test_convert_dtypes_bit_exact(ac, dtype):
         compare_conversion(ac, A, T, D, dtype)
 
 
+@pytest.mark.parametrize("dtype", [0, 1, 2, 3])
+def test_convert_long_rows_bit_exact(ac, dtype):
+    """Many short rows keep the mean chunk small, so rows of a few hundred to
+    tens of thousands of elements have chunks longer than the fill's LDS stage
+    and are filled by the long-row pass: single-row groups, several blocks of
+    64 chunks, step counts that are not a multiple of the tile, and long rows
+    at the start, middle and end of the matrix."""
+    rng = np.random.default_rng(17)
+    lengths = rng.integers(0, 6, 30_000)
+    for pos, L in [(0, 20_000), (5, 300), (777, 1025), (12_345, 4097), (20_000, 65_537),
+                   (29_999, 2_500)]:
+        lengths[pos] = L
+    rp = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    nnz = int(rp[-1])
+    n_cols = 70_000
+    col = np.concatenate([np.sort(rng.choice(n_cols, L, replace=False)) for L in lengths]).astype(np.int32)
+    val = rng.uniform(-1, 1, nnz)
+    A = synth.Csr(len(lengths), n_cols, rp, col, val)
+    for T, D in [(64, 1), (100, 1), (256, 2), (1000, 1)]:
+        compare_conversion(ac, A, T, D, dtype)
+
+
 @pytest.mark.parametrize("T,D", [(64, 1), (64, 2), (64, 4), (128, 1), (256, 1), (7, 3), (1000, 1)])
 def test_convert_powerlaw(ac, T, D):
     A, _ = powerlaw_sample(60_000, seed=2)
