@@ -65,14 +65,26 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
+// Every column index in [0, n_cols): 16-byte loads over the aligned body of
+// the array, single elements for the unaligned head and the tail.
 __global__ __launch_bounds__(256) void validate_columns_kernel(
     const int32_t* __restrict__ col, int64_t nnz, int32_t n_cols, Status* st) {
+  const uint32_t limit = uint32_t(n_cols);          // a negative index wraps above it
+  const int64_t head = min(nnz, int64_t((16 - (reinterpret_cast<uintptr_t>(col) & 15)) & 15) / 4);
+  const int64_t n4 = (nnz - head) / 4;
+  const int4* __restrict__ body = reinterpret_cast<const int4*>(col + head);
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   bool bad = false;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < nnz;
-       k += int64_t(gridDim.x) * blockDim.x) {
-    const int32_t c = col[k];
-    bad |= (c < 0) | (c >= n_cols);
+#pragma unroll 4
+  for (int64_t i = tid; i < n4; i += stride) {
+    const int4 v = body[i];
+    bad |= (uint32_t(v.x) >= limit) | (uint32_t(v.y) >= limit) | (uint32_t(v.z) >= limit) |
+           (uint32_t(v.w) >= limit);
   }
+  const int64_t tail = head + 4 * n4;               // head and tail: fewer than 7 elements
+  for (int64_t k = tid; k < head + (nnz - tail); k += stride)
+    bad |= uint32_t(col[k < head ? k : tail + (k - head)]) >= limit;
   if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&st->bad_column, 1);
 }
 
@@ -532,7 +544,7 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
     if (rc) return rc;
   }
   if (nnz > 0) {
-    const int64_t want = (nnz + 255) / 256;
+    const int64_t want = (nnz + 1023) / 1024;     // 4 elements per thread per pass
     const int blocks = (int)(want < 8192 ? want : 8192);
     validate_columns_kernel<<<blocks, 256, 0, s>>>(col, nnz, n_cols, st);
     ARGCSR_HIP(hipGetLastError());

@@ -155,6 +155,35 @@ def test_convert_rejects_bad_input(ac):
         ac.convert(dev, 64, 1)
 
 
+def test_convert_validates_every_column_position(ac):
+    """The column check reads 16-byte words over the aligned body of the
+    array and single elements around it: a bad index in the unaligned head,
+    the body or the tail is found, for every alignment of the array."""
+    rng = np.random.default_rng(23)
+    L = rng.integers(0, 9, 500)
+    A = csr_from_lengths(L, 300, 23)
+    nnz = A.nnz
+    for shift in range(4):
+        for pos in sorted({0, 1, 2, 3, 4, 5, nnz // 2, nnz - 5, nnz - 4, nnz - 3, nnz - 2, nnz - 1}):
+            for bad in (A.n_cols, -1, -(2 ** 31), 2 ** 31 - 1):
+                col = A.col.copy()
+                col[pos] = bad
+                padded = torch.zeros(nnz + 4, dtype=torch.int32, device=DEV)
+                padded[shift:shift + nnz] = torch.from_numpy(col).to(DEV)
+                dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+                dev.col = padded[shift:shift + nnz]       # a view 4*shift bytes past alignment
+                with pytest.raises(ac.ArgCsrError) as e:
+                    ac.convert(dev, 32, 2)
+                assert e.value.code == ac._lib.EINVAL, (shift, pos, bad)
+        padded = torch.zeros(nnz + 4, dtype=torch.int32, device=DEV)
+        padded[shift:shift + nnz] = torch.from_numpy(A.col).to(DEV)
+        dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+        dev.col = padded[shift:shift + nnz]
+        M = ac.convert(dev, 32, 2)                            # every index valid
+        ref = oracle.convert(A.rp, A.col, A.val, 32, 2)
+        assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
+
+
 # ---------------------------------------------------------------------------
 # conversion step 1 on the device (binary lifting): identical groups
 # ---------------------------------------------------------------------------
