@@ -116,6 +116,32 @@ def stats(ms):
             "p10_ms": float(np.percentile(ms, 10)), "p90_ms": float(np.percentile(ms, 90))}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_convert(A, T, D, region_rows, regions, budget_s: float = 6.0):
+    """CSR -> ARG-CSR by the oracle (single-threaded C, FP64 values): median
+    time of up to 3 conversions of the whole matrix within `budget_s`."""
+    import oracle
+    ts = []
+    while len(ts) < 3 and sum(ts) < budget_s / 2:
+        t0 = time.perf_counter()
+        if regions is not None:
+            oracle.convert_regions(A.rp, A.col, A.val, T, region_rows, regions)
+        else:
+            oracle.convert(A.rp, A.col, A.val, T, D)
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)) * 1e3, len(ts)
+
+
 def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
     """The FP64 CSR oracle on this host's cores (OpenMP row split; identical
     result to the sequential oracle), on a bounded number of full SpMVs."""
@@ -140,7 +166,7 @@ def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
             "sample": f"full matrix, {reps} SpMVs on {threads} threads (OpenMP row split) "
                       f"+ {st_reps} single-threaded",
             "ms_per_spmv": mt * 1e3, "single_thread_gbps": B_useful / st / 1e9,
-            "single_thread_ms": st * 1e3}
+            "single_thread_ms": st * 1e3, "cpu_model": cpu_model()}
 
 
 def f32_variant(A, x, dev, timer, torch, ac, steps):
@@ -475,6 +501,10 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, x, useful_bytes(A, 0))   # the oracle is FP64
+        conv_ms, conv_reps = cpu_convert(A, T, D, region_rows, regions)
+        out["cpu_baseline"]["convert_ms"] = conv_ms
+        out["cpu_baseline"]["convert_sample"] = (f"whole matrix, T={T} D={D}, single thread, "
+                                                 f"median of {conv_reps}")
     print(json.dumps(out))
 
 
