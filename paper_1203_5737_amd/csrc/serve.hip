@@ -134,6 +134,7 @@ struct Request {
   int32_t slot = -1;
   int32_t phase = kPhaseStart;
   int32_t inner_in_cycle = 0;
+  int32_t parity = 0;          // which CgScalars::rr holds |r|^2 before the next step
   double cycle_rr0 = 0.0;
   std::vector<void*> blocks;
   float* x32 = nullptr;
@@ -185,7 +186,6 @@ struct argcsr_server {
   void* h_desc = nullptr;      // pinned staging
   argcsr::CgScalars* d_scalars = nullptr;
   argcsr::CgScalars* h_scalars = nullptr;   // pinned
-  argcsr::WorkQueues* d_queues = nullptr;
   int32_t mspmv_grid[2] = {1, 1};           // persistent grid per dtype (FP32, FP64)
   // pinned staging and its copy helper
   argcsr::PinnedArena pinned;
@@ -471,6 +471,7 @@ int activate(argcsr_server* s, Request* r) {
     }
     ARGCSR_HIP(hipMemsetAsync(r->v64[1], 0, sizeof(double) * size_t(A.n_rows), s->stream));
     r->phase = kPhaseStart;
+    r->parity = 0;
   }
   r->mat = m;
   // the input: through pinned staging filled by the copy helper (the
@@ -558,21 +559,25 @@ int step(argcsr_server* s) {
   }
   int32_t tiles = 0;
   for (Request* r : cg) tiles += (r->mat->m64.n_rows + kTile - 1) / kTile;
-  // descriptor block: MatWork f32 | MatWork f64 | CgVec | tile table | partials
-  const size_t o_f64 = sizeof(MatWork) * f32.size();
+  // descriptor block: work queues (zeroed by the upload, so no reset
+  // kernel) | MatWork f32 | MatWork f64 | CgVec | tile table | two partials
+  const size_t o_w32 = sizeof(WorkQueues) * 2;
+  const size_t o_f64 = o_w32 + sizeof(MatWork) * f32.size();
   const size_t o_vec = o_f64 + sizeof(MatWork) * f64.size();
   const size_t o_tile = o_vec + sizeof(CgVec) * cg.size();
   const size_t o_part = (o_tile + sizeof(int32_t) * size_t(tiles) + 15) / 16 * 16;
-  const size_t total = o_part + sizeof(double) * size_t(std::max(tiles, 1));
+  const size_t o_part2 = o_part + sizeof(double) * size_t(std::max(tiles, 1));
+  const size_t total = o_part2 + sizeof(double) * size_t(std::max(tiles, 1));
   int rc = ensure_desc(s, total);
   if (rc) return rc;
   char* h = static_cast<char*>(s->h_desc);
   char* d = static_cast<char*>(s->d_desc);
+  std::memset(h, 0, o_w32);
   int32_t g32 = 0, h32 = 0, g64 = 0, h64 = 0;
   for (size_t i = 0; i < f32.size(); ++i) {
     Request* r = f32[i];
     const argcsr_matrix& A = r->mat->m64;
-    MatWork& w = reinterpret_cast<MatWork*>(h)[i];
+    MatWork& w = reinterpret_cast<MatWork*>(h + o_w32)[i];
     if (r->q.kind == ARGCSR_REQ_SPMV) fill_matwork(w, A, r->mat->values32, r->x32, r->y32, g32, h32);
     else fill_matwork(w, A, r->mat->values32, r->p32, r->q32, g32, h32);
   }
@@ -587,28 +592,27 @@ int step(argcsr_server* s) {
     Request* r = cg[i];
     CgVec& v = reinterpret_cast<CgVec*>(h + o_vec)[i];
     v = CgVec{r->v64[0], r->v64[1], r->v64[2], r->v64[3], r->v64[4], r->v64[5],
-              r->p32, r->q32, r->mat->m64.n_rows, r->phase, t, r->slot};
+              r->p32, r->q32, r->mat->m64.n_rows, r->phase, t, r->slot, r->parity};
     const int32_t nt = (r->mat->m64.n_rows + kTile - 1) / kTile;
     for (int32_t k = 0; k < nt; ++k) tile_req[t + k] = int32_t(i);
     t += nt;
   }
   ARGCSR_HIP(hipMemcpyAsync(d, h, o_part, hipMemcpyHostToDevice, s->stream));
-  const MatWork* d_w32 = reinterpret_cast<const MatWork*>(d);
+  WorkQueues* d_queues = reinterpret_cast<WorkQueues*>(d);
+  const MatWork* d_w32 = reinterpret_cast<const MatWork*>(d + o_w32);
   const MatWork* d_w64 = reinterpret_cast<const MatWork*>(d + o_f64);
   const CgVec* d_vec = reinterpret_cast<const CgVec*>(d + o_vec);
   const int32_t* d_tiles = reinterpret_cast<const int32_t*>(d + o_tile);
-  double* d_part = reinterpret_cast<double*>(d + o_part);
+  double* d_pq = reinterpret_cast<double*>(d + o_part);
+  double* d_rr = reinterpret_cast<double*>(d + o_part2);
   const int ncg = int(cg.size());
   if (!f64.empty()) cg_pre_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles);
-  reset_work_queues_kernel<<<1, 64, 0, s->stream>>>(s->d_queues, 2);
-  if (!f32.empty()) launch_mspmv<ARGCSR_F32>(s, d_w32, int32_t(f32.size()), g32, h32, s->d_queues);
-  if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64, s->d_queues + 1);
+  if (!f32.empty()) launch_mspmv<ARGCSR_F32>(s, d_w32, int32_t(f32.size()), g32, h32, d_queues);
+  if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64, d_queues + 1);
   if (ncg > 0) {
-    cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, d_part);
-    cg_alpha_kernel<<<ncg, kVecBlock, 0, s->stream>>>(d_vec, d_part, s->d_scalars);
-    cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_part);
-    cg_beta_kernel<<<ncg, kVecBlock, 0, s->stream>>>(d_vec, d_part, s->d_scalars);
-    cg_direction_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars);
+    cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, d_pq);
+    cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_pq, d_rr);
+    cg_direction_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_rr);
     ARGCSR_HIP(hipMemcpyAsync(s->h_scalars, s->d_scalars, sizeof(CgScalars) * size_t(s->cfg.max_active),
                               hipMemcpyDeviceToHost, s->stream));
   }
@@ -626,24 +630,26 @@ int step(argcsr_server* s) {
       done = true;
     } else {
       const CgScalars& sc = s->h_scalars[r->slot];
+      const double rr = sc.rr[1 - r->parity];    // written by this step
+      r->parity ^= 1;
       if (r->phase == kPhaseInner) {
         r->res.iterations++;
         r->inner_in_cycle++;
         const bool cycle_done = sc.pq <= 0.0 ||
-                                sc.rr <= s->cfg.cg_inner_tol * s->cfg.cg_inner_tol * r->cycle_rr0 ||
+                                rr <= s->cfg.cg_inner_tol * s->cfg.cg_inner_tol * r->cycle_rr0 ||
                                 r->inner_in_cycle >= s->cfg.cg_max_inner ||
                                 r->res.iterations >= s->cfg.cg_max_iter;
         if (cycle_done) r->phase = kPhaseOuter;
       } else {
         if (r->phase == kPhaseOuter) r->res.refinements++;
-        r->res.relres = sc.bnorm2 > 0.0 ? std::sqrt(sc.rr / sc.bnorm2) : 0.0;
+        r->res.relres = sc.bnorm2 > 0.0 ? std::sqrt(rr / sc.bnorm2) : 0.0;
         if (r->res.relres <= s->cfg.cg_tol || r->res.iterations >= s->cfg.cg_max_iter) {
           status = r->res.relres <= s->cfg.cg_tol ? ARGCSR_OK : ARGCSR_ENOCONV;
           done = true;
         } else {
           r->phase = kPhaseInner;
           r->inner_in_cycle = 0;
-          r->cycle_rr0 = sc.rr;
+          r->cycle_rr0 = rr;
         }
       }
     }
@@ -801,14 +807,12 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
     rc = fail(ARGCSR_EHIP, "hipStreamCreate failed");
   if (!rc && (hipMalloc(&s->d_scalars, sizeof(CgScalars) * size_t(cfg->max_active)) != hipSuccess ||
               hipHostMalloc(&s->h_scalars, sizeof(CgScalars) * size_t(cfg->max_active),
-                            hipHostMallocDefault) != hipSuccess ||
-              hipMalloc(&s->d_queues, sizeof(WorkQueues) * 2) != hipSuccess))
+                            hipHostMallocDefault) != hipSuccess))
     rc = fail(ARGCSR_ENOMEM, "server buffers could not be allocated");
   if (rc) {
     if (s->stream) (void)hipStreamDestroy(s->stream);
     if (s->d_scalars) (void)hipFree(s->d_scalars);
     if (s->h_scalars) (void)hipHostFree(s->h_scalars);
-    if (s->d_queues) (void)hipFree(s->d_queues);
     delete s;
     return rc;
   }
@@ -933,7 +937,6 @@ extern "C" int argcsr_server_destroy(argcsr_server* s) {
   if (s->h_desc) (void)hipHostFree(s->h_desc);
   (void)hipFree(s->d_scalars);
   (void)hipHostFree(s->h_scalars);
-  (void)hipFree(s->d_queues);
   delete s;
   return ARGCSR_OK;
 }

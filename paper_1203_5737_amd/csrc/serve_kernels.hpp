@@ -4,9 +4,12 @@
 // p32, q32 of its own length.  A step processes all requests at once: the
 // vectors are cut into tiles of kTile elements, a per-tile request table maps
 // workgroups to (request, tile), and every reduction is done per tile in a
-// fixed order, then per request over its tiles in tile order by one thread.
-// No value of one request ever enters another request's arithmetic, so each
-// result is bitwise the same whether the request runs alone or in a mix.
+// fixed order, then per request over its tiles in a fixed order.  The
+// per-request sums (p.q for alpha, r.r for beta) are formed by every workgroup
+// of the request that needs them, each in the same order, so a step needs no
+// kernel of its own for the scalars.  No value of one request ever enters
+// another request's arithmetic, so each result is bitwise the same whether
+// the request runs alone or in a mix.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,15 +41,16 @@ struct CgVec {
   int32_t phase;
   int32_t tile_begin;    // first global tile of this request
   int32_t slot;          // index into the scalar array
+  int32_t parity;        // rr[parity] is |r|^2 before this step; the step writes rr[1 - parity]
 };
 
 struct CgScalars {
-  double rr;             // current recursive (inner) or true (outer) |r|^2
+  double rr[2];          // recursive (inner) or true (outer) |r|^2, by step parity
   double alpha;
   double beta;
   double bnorm2;         // |b|^2
   double pq;             // p . A32 p of the last inner iteration
-  double pad[3];
+  double pad[2];
 };
 
 // Fixed-order block sum: each thread's values in index order, then a
@@ -74,7 +78,7 @@ static __global__ __launch_bounds__(kVecBlock) void cg_pre_kernel(const CgVec* _
   }
 }
 
-// inner: partial sums of p . q32
+// inner: partial sums of p . q32 into `partial`
 static __global__ __launch_bounds__(kVecBlock) void cg_dot_kernel(const CgVec* __restrict__ v,
                                                           const int32_t* __restrict__ tile_req,
                                                           double* __restrict__ partial) {
@@ -93,42 +97,38 @@ static __global__ __launch_bounds__(kVecBlock) void cg_dot_kernel(const CgVec* _
 
 // Sum of one request's tile partials, by one workgroup: thread t adds tiles
 // t, t+256, ... in order, then a fixed tree over the threads.  The order
-// depends only on the request's own tile count.
+// depends only on the request's own tile count, so every workgroup of the
+// request gets the same value.  Ends with a barrier, so `red` may be reused.
 __device__ __forceinline__ double tiles_sum(const double* partial, int32_t begin, int32_t n,
                                            double* red) {
   const int32_t tiles = (n + kTile - 1) / kTile;
   double s = 0.0;
   for (int32_t t = int32_t(threadIdx.x); t < tiles; t += kVecBlock) s += partial[begin + t];
-  return block_sum(s, red);
+  s = block_sum(s, red);
+  __syncthreads();
+  return s;
 }
 
-// inner: alpha = rr / (p . q); one workgroup per request
-static __global__ __launch_bounds__(kVecBlock) void cg_alpha_kernel(const CgVec* __restrict__ v,
-                                                            const double* __restrict__ partial,
-                                                            CgScalars* __restrict__ sc) {
-  __shared__ double red[kVecBlock];
-  const CgVec w = v[blockIdx.x];
-  if (w.phase != kPhaseInner) return;
-  const double pq = tiles_sum(partial, w.tile_begin, w.n, red);
-  if (threadIdx.x == 0) {
-    CgScalars& s = sc[w.slot];
-    s.pq = pq;
-    s.alpha = pq > 0.0 ? s.rr / pq : 0.0;       // pq <= 0: no step (host leaves the cycle)
-  }
-}
-
-// inner: d += alpha p, r -= alpha q32; start/outer: r = b (- q64), d = 0,
-// p = r, p32 = (float) r.  All phases: partial sums of r . r.
+// inner: alpha = rr / (p . q) from the request's p.q partials, then
+// d += alpha p, r -= alpha q32; start/outer: r = b (- q64), d = 0, p = r,
+// p32 = (float) r.  All phases: partial sums of r . r into `rr_partial`.
 static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec* __restrict__ v,
                                                              const int32_t* __restrict__ tile_req,
-                                                             const CgScalars* __restrict__ sc,
-                                                             double* __restrict__ partial) {
+                                                             CgScalars* __restrict__ sc,
+                                                             const double* __restrict__ pq_partial,
+                                                             double* __restrict__ rr_partial) {
   __shared__ double red[kVecBlock];
   const CgVec w = v[tile_req[blockIdx.x]];
-  const int32_t base = (int32_t(blockIdx.x) - w.tile_begin) * kTile;
+  const int32_t local = int32_t(blockIdx.x) - w.tile_begin;
+  const int32_t base = local * kTile;
   double s = 0.0;
   if (w.phase == kPhaseInner) {
-    const double alpha = sc[w.slot].alpha;
+    const double pq = tiles_sum(pq_partial, w.tile_begin, w.n, red);
+    const double alpha = pq > 0.0 ? sc[w.slot].rr[w.parity] / pq : 0.0;   // pq <= 0: no step
+    if (local == 0 && threadIdx.x == 0) {                                  // (host leaves the cycle)
+      sc[w.slot].pq = pq;
+      sc[w.slot].alpha = alpha;
+    }
     for (int k = 0; k < kVecPerThread; ++k) {
       const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
       if (i < w.n) {
@@ -153,33 +153,29 @@ static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec
     }
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_partial[blockIdx.x] = s;
 }
 
-// inner: rr_new = r . r, beta = rr_new / rr; start/outer: rr = r . r
-// (and |b|^2 at the start).  One workgroup per request.
-static __global__ __launch_bounds__(kVecBlock) void cg_beta_kernel(const CgVec* __restrict__ v,
-                                                           const double* __restrict__ partial,
-                                                           CgScalars* __restrict__ sc) {
-  __shared__ double red[kVecBlock];
-  const CgVec w = v[blockIdx.x];
-  const double rr = tiles_sum(partial, w.tile_begin, w.n, red);
-  if (threadIdx.x == 0) {
-    CgScalars& s = sc[w.slot];
-    if (w.phase == kPhaseInner) s.beta = s.rr > 0.0 ? rr / s.rr : 0.0;
-    else if (w.phase == kPhaseStart) s.bnorm2 = rr;
-    s.rr = rr;
-  }
-}
-
-// inner: p = r + beta p, p32 = (float) p
+// All phases: rr_new = r . r from the request's partials, stored as
+// rr[1 - parity] (and as |b|^2 at the start); inner: beta = rr_new / rr,
+// p = r + beta p, p32 = (float) p.
 static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const CgVec* __restrict__ v,
                                                                 const int32_t* __restrict__ tile_req,
-                                                                const CgScalars* __restrict__ sc) {
+                                                                CgScalars* __restrict__ sc,
+                                                                const double* __restrict__ rr_partial) {
+  __shared__ double red[kVecBlock];
   const CgVec w = v[tile_req[blockIdx.x]];
+  const int32_t local = int32_t(blockIdx.x) - w.tile_begin;
+  const double rr_new = tiles_sum(rr_partial, w.tile_begin, w.n, red);
+  if (local == 0 && threadIdx.x == 0) {
+    sc[w.slot].rr[1 - w.parity] = rr_new;
+    if (w.phase == kPhaseStart) sc[w.slot].bnorm2 = rr_new;
+  }
   if (w.phase != kPhaseInner) return;
-  const double beta = sc[w.slot].beta;
-  const int32_t base = (int32_t(blockIdx.x) - w.tile_begin) * kTile;
+  const double rr = sc[w.slot].rr[w.parity];
+  const double beta = rr > 0.0 ? rr_new / rr : 0.0;
+  if (local == 0 && threadIdx.x == 0) sc[w.slot].beta = beta;
+  const int32_t base = local * kTile;
   for (int k = 0; k < kVecPerThread; ++k) {
     const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
     if (i < w.n) {
