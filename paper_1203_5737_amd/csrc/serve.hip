@@ -183,9 +183,11 @@ struct argcsr_server {
   // per-step device buffers
   void* d_desc = nullptr;
   size_t d_desc_bytes = 0;
-  void* h_desc = nullptr;      // pinned staging
+  void* h_desc = nullptr;      // mapped pinned staging, pulled by the device
+  const void* h_desc_dev = nullptr;   // its device address
   argcsr::CgScalars* d_scalars = nullptr;
-  argcsr::CgScalars* h_scalars = nullptr;   // pinned
+  argcsr::CgScalars* h_scalars = nullptr;   // mapped pinned mirror written by the kernels
+  argcsr::CgScalars* h_scalars_dev = nullptr;
   int32_t mspmv_grid[2] = {1, 1};           // persistent grid per dtype (FP32, FP64)
   // pinned staging and its copy helper
   argcsr::PinnedArena pinned;
@@ -522,7 +524,10 @@ int ensure_desc(argcsr_server* s, size_t bytes) {
   }
   const size_t want = std::max(bytes * 2, size_t(1) << 20);
   ARGCSR_HIP(hipMalloc(&s->d_desc, want));
-  ARGCSR_HIP(hipHostMalloc(&s->h_desc, want, hipHostMallocDefault));
+  ARGCSR_HIP(hipHostMalloc(&s->h_desc, want, hipHostMallocMapped | hipHostMallocCoherent));
+  void* dev = nullptr;
+  ARGCSR_HIP(hipHostGetDevicePointer(&dev, s->h_desc, 0));
+  s->h_desc_dev = dev;
   s->d_desc_bytes = want;
   return ARGCSR_OK;
 }
@@ -597,7 +602,12 @@ int step(argcsr_server* s) {
     for (int32_t k = 0; k < nt; ++k) tile_req[t + k] = int32_t(i);
     t += nt;
   }
-  ARGCSR_HIP(hipMemcpyAsync(d, h, o_part, hipMemcpyHostToDevice, s->stream));
+  {
+    const int64_t n16 = int64_t(o_part / 16);          // o_part is a multiple of 16
+    const int64_t blocks = std::min<int64_t>((n16 + kVecBlock - 1) / kVecBlock, 64);
+    desc_pull_kernel<<<dim3(uint32_t(std::max<int64_t>(blocks, 1))), kVecBlock, 0, s->stream>>>(
+        static_cast<const int4*>(s->h_desc_dev), reinterpret_cast<int4*>(d), n16);
+  }
   WorkQueues* d_queues = reinterpret_cast<WorkQueues*>(d);
   const MatWork* d_w32 = reinterpret_cast<const MatWork*>(d + o_w32);
   const MatWork* d_w64 = reinterpret_cast<const MatWork*>(d + o_f64);
@@ -611,10 +621,10 @@ int step(argcsr_server* s) {
   if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64, d_queues + 1);
   if (ncg > 0) {
     cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, d_pq);
-    cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_pq, d_rr);
-    cg_direction_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_rr);
-    ARGCSR_HIP(hipMemcpyAsync(s->h_scalars, s->d_scalars, sizeof(CgScalars) * size_t(s->cfg.max_active),
-                              hipMemcpyDeviceToHost, s->stream));
+    cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars,
+                                                         s->h_scalars_dev, d_pq, d_rr);
+    cg_direction_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars,
+                                                            s->h_scalars_dev, d_rr);
   }
   ARGCSR_HIP(hipGetLastError());
   ARGCSR_HIP(hipStreamSynchronize(s->stream));
@@ -807,7 +817,9 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
     rc = fail(ARGCSR_EHIP, "hipStreamCreate failed");
   if (!rc && (hipMalloc(&s->d_scalars, sizeof(CgScalars) * size_t(cfg->max_active)) != hipSuccess ||
               hipHostMalloc(&s->h_scalars, sizeof(CgScalars) * size_t(cfg->max_active),
-                            hipHostMallocDefault) != hipSuccess))
+                            hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+              hipHostGetDevicePointer(reinterpret_cast<void**>(&s->h_scalars_dev), s->h_scalars,
+                                      0) != hipSuccess))
     rc = fail(ARGCSR_ENOMEM, "server buffers could not be allocated");
   if (rc) {
     if (s->stream) (void)hipStreamDestroy(s->stream);

@@ -7,7 +7,9 @@
 // fixed order, then per request over its tiles in a fixed order.  The
 // per-request sums (p.q for alpha, r.r for beta) are formed by every workgroup
 // of the request that needs them, each in the same order, so a step needs no
-// kernel of its own for the scalars.  No value of one request ever enters
+// kernel of its own for the scalars; the ones the host needs (|r|^2, |b|^2,
+// p.q) are also written straight into a mapped pinned mirror, so a step needs
+// no copy back either.  No value of one request ever enters
 // another request's arithmetic, so each result is bitwise the same whether
 // the request runs alone or in a mix.
 #pragma once
@@ -115,6 +117,7 @@ __device__ __forceinline__ double tiles_sum(const double* partial, int32_t begin
 static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec* __restrict__ v,
                                                              const int32_t* __restrict__ tile_req,
                                                              CgScalars* __restrict__ sc,
+                                                             CgScalars* __restrict__ host_sc,
                                                              const double* __restrict__ pq_partial,
                                                              double* __restrict__ rr_partial) {
   __shared__ double red[kVecBlock];
@@ -128,6 +131,7 @@ static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec
     if (local == 0 && threadIdx.x == 0) {                                  // (host leaves the cycle)
       sc[w.slot].pq = pq;
       sc[w.slot].alpha = alpha;
+      host_sc[w.slot].pq = pq;
     }
     for (int k = 0; k < kVecPerThread; ++k) {
       const int32_t i = base + k * kVecBlock + int32_t(threadIdx.x);
@@ -162,6 +166,7 @@ static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec
 static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const CgVec* __restrict__ v,
                                                                 const int32_t* __restrict__ tile_req,
                                                                 CgScalars* __restrict__ sc,
+                                                                CgScalars* __restrict__ host_sc,
                                                                 const double* __restrict__ rr_partial) {
   __shared__ double red[kVecBlock];
   const CgVec w = v[tile_req[blockIdx.x]];
@@ -169,7 +174,11 @@ static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const Cg
   const double rr_new = tiles_sum(rr_partial, w.tile_begin, w.n, red);
   if (local == 0 && threadIdx.x == 0) {
     sc[w.slot].rr[1 - w.parity] = rr_new;
-    if (w.phase == kPhaseStart) sc[w.slot].bnorm2 = rr_new;
+    host_sc[w.slot].rr[1 - w.parity] = rr_new;
+    if (w.phase == kPhaseStart) {
+      sc[w.slot].bnorm2 = rr_new;
+      host_sc[w.slot].bnorm2 = rr_new;
+    }
   }
   if (w.phase != kPhaseInner) return;
   const double rr = sc[w.slot].rr[w.parity];
@@ -184,6 +193,15 @@ static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const Cg
       w.p32[i] = float(pi);
     }
   }
+}
+
+// The step's descriptor block, read by the device from mapped pinned host
+// memory: one small kernel costs the host less than a copy call.
+static __global__ __launch_bounds__(kVecBlock) void desc_pull_kernel(const int4* __restrict__ src,
+                                                             int4* __restrict__ dst, int64_t n16) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
 }
 
 // FP64 values -> FP32 values of the same layout (nearest-even).
