@@ -471,6 +471,53 @@ def test_concurrent_conversions_on_separate_streams(ac):
     assert not errors, errors
 
 
+def random_case(seed):
+    """A seeded random matrix and conversion setting: row-length mix, block
+    size, desiredChunkSize, storage type, format and where step 1 runs."""
+    rng = np.random.default_rng([7771, seed])
+    n = int(np.exp(rng.uniform(0, np.log(40_000))))
+    mix = rng.choice(["uniform", "zipf", "constant", "sparse"])
+    if mix == "uniform":
+        L = rng.integers(0, int(rng.choice([2, 9, 60])), n)
+    elif mix == "zipf":
+        L = np.clip(rng.zipf(rng.uniform(1.6, 2.6), n), 1, 5000)
+    elif mix == "constant":
+        L = np.full(n, int(rng.integers(1, 40)))
+    else:
+        L = np.where(rng.random(n) < 0.7, 0, rng.integers(1, 6, n))
+    for pos in rng.integers(0, n, int(rng.integers(0, 4))):   # a few long rows
+        L[pos] = int(rng.integers(100, 20_000))
+    n_cols = int(max(L.max(initial=0), 1) + rng.integers(1, 30_000))
+    T = int(rng.choice([64, 128, 256]) if rng.random() < 0.6 else
+            rng.choice([1, 2, 7, 32, 100, 512, 1000, 1024]))
+    D = int(np.exp(rng.uniform(0, np.log(64))))
+    dtype = int(rng.integers(0, 4))
+    fmt = 1 if rng.random() < 0.2 else 0
+    device_grouping = bool(rng.random() < 0.5)
+    return csr_from_lengths(L, n_cols, 9000 + seed), T, D, dtype, fmt, device_grouping, rng
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_random_sweep_conversion_and_spmv(ac, part):
+    """40 seeded random cases (10 per part): the conversion bit-exact against
+    the oracle (any block size) and y within the error bound of the storage
+    type (block sizes the SpMV kernels take; the others are refused)."""
+    from paper_1203_5737_amd import _lib
+    for seed in range(10 * part, 10 * part + 10):
+        A, T, D, dtype, fmt, dg, rng = random_case(seed)
+        announce(f"sweep seed={seed}")
+        dev, M, ref = compare_conversion(ac, A, T, D, dtype, device_grouping=dg, fmt=fmt)
+        x = rng.uniform(-1, 1, A.n_cols)
+        if T not in (64, 128, 256):
+            with pytest.raises(_lib.ArgCsrError) as e:
+                gpu_spmv(ac, M, x if dtype == 0 else x.astype(np.float32))
+            assert e.value.code == _lib.EUNSUPPORTED
+        elif dtype == 0:
+            check_f64(A, x, gpu_spmv(ac, M, x))
+        else:
+            check_reduced(A, x, gpu_spmv(ac, M, x.astype(np.float32)), dtype)
+
+
 def test_spmv_deterministic(ac):
     A, x = powerlaw_sample(100_000, seed=5)
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
