@@ -521,15 +521,18 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
 
   const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
   StreamScratch ws;
-  const int64_t long_capacity = int64_t(G) + out->n_slots / (int64_t(kLongSteps) * T) + 1;
+  // items of the fill's long-row list: a group makes them only when its
+  // chunk size c exceeds stage/64 >= kMinStage/64 = 4, and then ceil(c/16)
+  // <= c/4 of them, so all groups together make at most n_slots/(4T)
+  static_assert(kMinStage / 64 >= 4 && kLongSteps == 16, "long-list bound");
+  const int64_t long_capacity = out->n_slots / (4 * int64_t(T)) + 1;
   rc = ws.alloc(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles) +
                 2 * sizeof(int32_t) * size_t(long_capacity), s);
   if (rc) return rc;
   Status* st = static_cast<Status*>(ws.ptr);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
   int64_t* heavy_tiles = tile_sums + n_tiles;
-  // (group, first step) per tile of the fill's long blocks: at most one per
-  // group plus one per kLongSteps steps of all groups
+  // (group, first step) per tile of the fill's long blocks
   int32_t* long_list = reinterpret_cast<int32_t*>(heavy_tiles + n_tiles);
   // uses the caller's slot count; it is checked against the device total
   // before anything is written to the caller's heavy_groups buffer
