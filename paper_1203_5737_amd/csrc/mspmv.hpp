@@ -1,10 +1,11 @@
-// y_m = A_m x_m for a set of matrices in ONE persistent launch, driven by
-// per-matrix prefix tables instead of a per-group work list: work item i of
-// the normal queue is group i - group_begin[m] of the matrix m with
-// group_begin[m] <= i < group_begin[m+1]; heavy item h is
-// heavy_groups_m[h - heavy_begin[m]].  The prefix tables are staged in LDS
-// once per workgroup and searched there.  Used by the serving loop, whose
-// set of matrices changes from step to step.
+// y_m = A_m x_m for a set of matrices in ONE launch, driven by per-matrix
+// prefix tables instead of a per-group work list: the first total_heavy
+// workgroups take heavy item h = heavy_groups_m[h - heavy_begin[m]] each,
+// and then wave i of the rest takes group i - group_begin[m] of the matrix m
+// with group_begin[m] <= i < group_begin[m+1].  The prefix tables are staged
+// in LDS once per workgroup and searched there.  Used by the serving loop,
+// whose set of matrices changes from step to step: the grid is sized on the
+// host for each step, so no wave takes work from a shared counter.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,12 +13,10 @@
 #include "common.hpp"
 #include "schedule.hpp"
 #include "spmv_kernels.hpp"
-#include "workqueue.hpp"
 
 namespace argcsr {
 
 constexpr int kMaxLaunchMats = 512;   // matrices per multi-matrix launch
-constexpr int kMspmvGrab = 4;         // normal items taken per queue access
 
 struct MatWork {
   const argcsr_group_info* groups;
@@ -48,8 +47,7 @@ __device__ __forceinline__ int32_t find_owner(const int32_t* begin, int32_t n, i
 
 template <int DT>
 __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
-    const MatWork* __restrict__ mw, int32_t n_mats, int32_t total_groups, int32_t total_heavy,
-    WorkQueues* q) {
+    const MatWork* __restrict__ mw, int32_t n_mats, int32_t total_groups, int32_t total_heavy) {
   using Vt = Val<DT>;
   using S = typename Vt::storage;
   using A = typename Vt::acc;
@@ -57,23 +55,18 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
   __shared__ int32_t hbeg[kMaxLaunchMats];
   __shared__ int32_t ends[kSpmvWaves][256];
   __shared__ A part_mem[(kSpmvWaves - 1) * 256];
-  __shared__ int32_t grabbed;
   for (int32_t m = threadIdx.x; m < n_mats; m += blockDim.x) {
     gbeg[m] = mw[m].group_begin;
     hbeg[m] = mw[m].heavy_begin;
   }
   __syncthreads();
   const int wv = wave_uniform(int(threadIdx.x >> 6));
+  const int32_t b = int32_t(blockIdx.x);
 
-  for (;;) {                                        // heavy groups, whole workgroup
-    if (threadIdx.x == 0) grabbed = atomicAdd(&q->heavy.next, 1);
-    __syncthreads();
-    const int32_t h = grabbed;
-    __syncthreads();
-    if (h >= total_heavy) break;
-    const int32_t m = find_owner(hbeg, n_mats, h);
+  if (b < total_heavy) {                            // a heavy group, the whole workgroup
+    const int32_t m = find_owner(hbeg, n_mats, b);
     const MatWork& w = mw[m];
-    const argcsr_group_info gi = w.groups[w.heavy[h - hbeg[m]]];
+    const argcsr_group_info gi = w.groups[w.heavy[b - hbeg[m]]];
     const S* vals = static_cast<const S*>(w.values);
     const XGather<A> x(static_cast<const A*>(w.x), w.n_cols);
     A* y = static_cast<A*>(w.y);
@@ -94,36 +87,32 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
                                    reinterpret_cast<A(*)[256]>(part_mem), wv);
         break;
     }
-    __syncthreads();
+    return;
   }
-
-  QueueCursor cursor{int(blockIdx.x % kQueues), 0};
-  int32_t i0, i1;
-  while (cursor.take(q, total_groups, kMspmvGrab, &i0, &i1)) {   // other groups, one wave each
-    int32_t m = find_owner(gbeg, n_mats, i0);
-    for (int32_t i = i0; i < i1; ++i) {
-      while (m + 1 < n_mats && gbeg[m + 1] <= i) ++m;
-      const MatWork& w = mw[m];
-      const argcsr_group_info gi = w.groups[i - gbeg[m]];
-      if (gi.chunk_size > w.heavy_chunk) continue;     // done by a heavy workgroup
-      const S* vals = static_cast<const S*>(w.values);
-      const XGather<A> x(static_cast<const A*>(w.x), w.n_cols);
-      A* y = static_cast<A*>(w.y);
-      switch (w.block_dim) {
-        case 64:
-          spmv_group<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                               vals, x, w.serial != 0, y, ends[wv]);
-          break;
-        case 128:
-          spmv_group<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                               vals, x, w.serial != 0, y, ends[wv]);
-          break;
-        default:
-          spmv_group<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                               vals, x, w.serial != 0, y, ends[wv]);
-          break;
-      }
-    }
+  // the other groups, one wave each, every XCD a contiguous range of them
+  const uint32_t nb = gridDim.x - uint32_t(total_heavy);
+  const int32_t i = int32_t(xcd_remap(uint32_t(b - total_heavy), nb)) * kSpmvWaves + wv;
+  if (i >= total_groups) return;
+  const int32_t m = find_owner(gbeg, n_mats, i);
+  const MatWork& w = mw[m];
+  const argcsr_group_info gi = w.groups[i - gbeg[m]];
+  if (gi.chunk_size > w.heavy_chunk) return;        // done by a heavy workgroup
+  const S* vals = static_cast<const S*>(w.values);
+  const XGather<A> x(static_cast<const A*>(w.x), w.n_cols);
+  A* y = static_cast<A*>(w.y);
+  switch (w.block_dim) {
+    case 64:
+      spmv_group<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                           vals, x, w.serial != 0, y, ends[wv]);
+      break;
+    case 128:
+      spmv_group<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                           vals, x, w.serial != 0, y, ends[wv]);
+      break;
+    default:
+      spmv_group<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                           vals, x, w.serial != 0, y, ends[wv]);
+      break;
   }
 }
 

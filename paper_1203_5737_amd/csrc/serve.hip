@@ -188,7 +188,6 @@ struct argcsr_server {
   argcsr::CgScalars* d_scalars = nullptr;
   argcsr::CgScalars* h_scalars = nullptr;   // mapped pinned mirror written by the kernels
   argcsr::CgScalars* h_scalars_dev = nullptr;
-  int32_t mspmv_grid[2] = {1, 1};           // persistent grid per dtype (FP32, FP64)
   // pinned staging and its copy helper
   argcsr::PinnedArena pinned;
   std::thread helper;
@@ -532,23 +531,11 @@ int ensure_desc(argcsr_server* s, size_t bytes) {
   return ARGCSR_OK;
 }
 
-// Persistent grid of mspmv_kernel<DT>: the workgroups that fit, at most 8 per CU.
 template <int DT>
-int32_t mspmv_grid_cap(int device) {
-  int cus = 0, per_cu = 0;
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mspmv_kernel<DT>, kSpmvWaves * 64, 0);
-  return std::max(1, cus * std::max(1, std::min(per_cu, 8)));
-}
-
-template <int DT>
-void launch_mspmv(argcsr_server* s, const MatWork* d_w, int32_t n, int32_t groups, int32_t heavy,
-                  WorkQueues* q) {
-  const int64_t cap = s->mspmv_grid[DT == ARGCSR_F64 ? 1 : 0];
-  const int64_t work = int64_t(heavy) + (int64_t(groups) + kMspmvGrab * kSpmvWaves - 1) /
-                                            (kMspmvGrab * kSpmvWaves);
-  const int grid = int(std::max<int64_t>(1, std::min<int64_t>(cap, work)));
-  mspmv_kernel<DT><<<grid, kSpmvWaves * 64, 0, s->stream>>>(d_w, n, groups, heavy, q);
+void launch_mspmv(argcsr_server* s, const MatWork* d_w, int32_t n, int32_t groups, int32_t heavy) {
+  const int64_t grid = int64_t(heavy) + (int64_t(groups) + kSpmvWaves - 1) / kSpmvWaves;
+  mspmv_kernel<DT><<<dim3(uint32_t(std::max<int64_t>(grid, 1))), kSpmvWaves * 64, 0, s->stream>>>(
+      d_w, n, groups, heavy);
 }
 
 // One step for every active request.
@@ -564,9 +551,8 @@ int step(argcsr_server* s) {
   }
   int32_t tiles = 0;
   for (Request* r : cg) tiles += (r->mat->m64.n_rows + kTile - 1) / kTile;
-  // descriptor block: work queues (zeroed by the upload, so no reset
-  // kernel) | MatWork f32 | MatWork f64 | CgVec | tile table | two partials
-  const size_t o_w32 = sizeof(WorkQueues) * 2;
+  // descriptor block: MatWork f32 | MatWork f64 | CgVec | tile table | two partials
+  const size_t o_w32 = 0;
   const size_t o_f64 = o_w32 + sizeof(MatWork) * f32.size();
   const size_t o_vec = o_f64 + sizeof(MatWork) * f64.size();
   const size_t o_tile = o_vec + sizeof(CgVec) * cg.size();
@@ -577,7 +563,6 @@ int step(argcsr_server* s) {
   if (rc) return rc;
   char* h = static_cast<char*>(s->h_desc);
   char* d = static_cast<char*>(s->d_desc);
-  std::memset(h, 0, o_w32);
   int32_t g32 = 0, h32 = 0, g64 = 0, h64 = 0;
   for (size_t i = 0; i < f32.size(); ++i) {
     Request* r = f32[i];
@@ -608,7 +593,6 @@ int step(argcsr_server* s) {
     desc_pull_kernel<<<dim3(uint32_t(std::max<int64_t>(blocks, 1))), kVecBlock, 0, s->stream>>>(
         static_cast<const int4*>(s->h_desc_dev), reinterpret_cast<int4*>(d), n16);
   }
-  WorkQueues* d_queues = reinterpret_cast<WorkQueues*>(d);
   const MatWork* d_w32 = reinterpret_cast<const MatWork*>(d + o_w32);
   const MatWork* d_w64 = reinterpret_cast<const MatWork*>(d + o_f64);
   const CgVec* d_vec = reinterpret_cast<const CgVec*>(d + o_vec);
@@ -617,8 +601,8 @@ int step(argcsr_server* s) {
   double* d_rr = reinterpret_cast<double*>(d + o_part2);
   const int ncg = int(cg.size());
   if (!f64.empty()) cg_pre_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles);
-  if (!f32.empty()) launch_mspmv<ARGCSR_F32>(s, d_w32, int32_t(f32.size()), g32, h32, d_queues);
-  if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64, d_queues + 1);
+  if (!f32.empty()) launch_mspmv<ARGCSR_F32>(s, d_w32, int32_t(f32.size()), g32, h32);
+  if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64);
   if (ncg > 0) {
     cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, d_pq);
     cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars,
@@ -829,8 +813,6 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
     return rc;
   }
   for (int32_t k = cfg->max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
-  s->mspmv_grid[0] = mspmv_grid_cap<ARGCSR_F32>(cfg->device);
-  s->mspmv_grid[1] = mspmv_grid_cap<ARGCSR_F64>(cfg->device);
   s->helper = std::thread(copy_helper, s);
   s->worker = std::thread(scheduler, s);
   *out = s;
