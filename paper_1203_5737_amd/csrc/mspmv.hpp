@@ -45,7 +45,9 @@ __device__ __forceinline__ int32_t find_owner(const int32_t* begin, int32_t n, i
   return lo;
 }
 
-template <int DT>
+// All matrices of a launch share T = 64*W (the server converts with one
+// block size), so each kernel instance holds one group routine only.
+template <int DT, int W, int U>
 __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
     const MatWork* __restrict__ mw, int32_t n_mats, int32_t total_groups, int32_t total_heavy) {
   using Vt = Val<DT>;
@@ -53,8 +55,8 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
   using A = typename Vt::acc;
   __shared__ int32_t gbeg[kMaxLaunchMats];
   __shared__ int32_t hbeg[kMaxLaunchMats];
-  __shared__ int32_t ends[kSpmvWaves][256];
-  __shared__ A part_mem[(kSpmvWaves - 1) * 256];
+  __shared__ int32_t ends[kSpmvWaves][64 * W];
+  __shared__ A part_mem[kSpmvWaves - 1][64 * W];
   for (int32_t m = threadIdx.x; m < n_mats; m += blockDim.x) {
     gbeg[m] = mw[m].group_begin;
     hbeg[m] = mw[m].heavy_begin;
@@ -67,26 +69,10 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
     const int32_t m = find_owner(hbeg, n_mats, b);
     const MatWork& w = mw[m];
     const argcsr_group_info gi = w.groups[w.heavy[b - hbeg[m]]];
-    const S* vals = static_cast<const S*>(w.values);
-    const XGather<A> x(static_cast<const A*>(w.x), w.n_cols);
-    A* y = static_cast<A*>(w.y);
-    switch (w.block_dim) {
-      case 64:
-        spmv_group_split<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
-                                   w.columns, vals, x, w.serial != 0, y, ends[0],
-                                   reinterpret_cast<A(*)[64]>(part_mem), wv);
-        break;
-      case 128:
-        spmv_group_split<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
-                                   w.columns, vals, x, w.serial != 0, y, ends[0],
-                                   reinterpret_cast<A(*)[128]>(part_mem), wv);
-        break;
-      default:
-        spmv_group_split<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm,
-                                   w.columns, vals, x, w.serial != 0, y, ends[0],
-                                   reinterpret_cast<A(*)[256]>(part_mem), wv);
-        break;
-    }
+    spmv_group_split<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                               static_cast<const S*>(w.values),
+                               XGather<A>(static_cast<const A*>(w.x), w.n_cols), w.serial != 0,
+                               static_cast<A*>(w.y), ends[0], part_mem, wv);
     return;
   }
   // the other groups, one wave each, every XCD a contiguous range of them
@@ -97,23 +83,10 @@ __global__ __launch_bounds__(kSpmvWaves * 64) void mspmv_kernel(
   const MatWork& w = mw[m];
   const argcsr_group_info gi = w.groups[i - gbeg[m]];
   if (gi.chunk_size > w.heavy_chunk) return;        // done by a heavy workgroup
-  const S* vals = static_cast<const S*>(w.values);
-  const XGather<A> x(static_cast<const A*>(w.x), w.n_cols);
-  A* y = static_cast<A*>(w.y);
-  switch (w.block_dim) {
-    case 64:
-      spmv_group<DT, 1, 8>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                           vals, x, w.serial != 0, y, ends[wv]);
-      break;
-    case 128:
-      spmv_group<DT, 2, 4>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                           vals, x, w.serial != 0, y, ends[wv]);
-      break;
-    default:
-      spmv_group<DT, 4, 2>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
-                           vals, x, w.serial != 0, y, ends[wv]);
-      break;
-  }
+  spmv_group<DT, W, U>(gi.first_row, gi.size, gi.offset, gi.chunk_size, w.tm, w.columns,
+                       static_cast<const S*>(w.values),
+                       XGather<A>(static_cast<const A*>(w.x), w.n_cols), w.serial != 0,
+                       static_cast<A*>(w.y), ends[wv]);
 }
 
 }  // namespace argcsr

@@ -534,8 +534,12 @@ int ensure_desc(argcsr_server* s, size_t bytes) {
 template <int DT>
 void launch_mspmv(argcsr_server* s, const MatWork* d_w, int32_t n, int32_t groups, int32_t heavy) {
   const int64_t grid = int64_t(heavy) + (int64_t(groups) + kSpmvWaves - 1) / kSpmvWaves;
-  mspmv_kernel<DT><<<dim3(uint32_t(std::max<int64_t>(grid, 1))), kSpmvWaves * 64, 0, s->stream>>>(
-      d_w, n, groups, heavy);
+  const dim3 g(uint32_t(std::max<int64_t>(grid, 1))), blk(kSpmvWaves * 64);
+  switch (s->cfg.block_dim > 0 ? s->cfg.block_dim : 64) {   // every resident matrix has it
+    case 64: mspmv_kernel<DT, 1, 8><<<g, blk, 0, s->stream>>>(d_w, n, groups, heavy); break;
+    case 128: mspmv_kernel<DT, 2, 4><<<g, blk, 0, s->stream>>>(d_w, n, groups, heavy); break;
+    default: mspmv_kernel<DT, 4, 2><<<g, blk, 0, s->stream>>>(d_w, n, groups, heavy); break;
+  }
 }
 
 // One step for every active request.
