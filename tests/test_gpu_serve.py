@@ -105,6 +105,34 @@ def test_serve_results_and_alone_vs_mix(srv_mod):
         assert ra["iterations"] == rb["iterations"]
 
 
+@pytest.mark.parametrize("T", [128, 256])
+def test_serve_block_sizes(srv_mod, T):
+    """Servers converting with T = 128 and 256 (the multi-matrix SpMV has one
+    instance per block size): SpMV on Laplacians and on a matrix with rows of
+    up to 6000 entries (whole-workgroup heavy groups), within the FP32 bound,
+    bitwise equal alone and in the mix; CG to 1e-10."""
+    print(f"\n[gpu] serve T={T}", flush=True)
+    mats = pool(3)
+    rng = np.random.default_rng(11)
+    L = np.clip(rng.zipf(1.8, 20_000), 1, 6000)
+    mats.append(synth.random_csr(L, 20_000, np.random.default_rng(12), np.random.default_rng(13)))
+    reqs = [("spmv", m, rng.uniform(-1, 1, mats[m].n_cols).astype(np.float32)) for m in (3, 0, 3, 1)]
+    reqs += [("cg", m, rng.uniform(-1, 1, mats[m].n_rows)) for m in (0, 1, 2)]
+    outs = []
+    for max_active in (16, 1):
+        with srv_mod.Server(budget_bytes=1 << 30, max_active=max_active, block_dim=T) as srv:
+            admit_all(srv, mats)
+            out, res = run_requests(srv, mats, reqs)
+        outs.append(out)
+        for (kind, m, inp), o, r in zip(reqs, out, res):
+            if kind == "spmv":
+                assert spmv_ok(mats[m], inp, o), (T, m)
+            else:
+                assert true_relres(mats[m], o, inp) <= 1e-10, (T, m)
+    for a, b in zip(*outs):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
 def test_serve_small_staging_falls_back(srv_mod):
     """A staging arena too small for most requests: those bypass it, the
     others go through it; results are the same as with ample staging."""
