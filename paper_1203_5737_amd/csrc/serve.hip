@@ -7,11 +7,13 @@
 //      resident (evicting least-recently-used idle matrices if the budget is
 //      short); SPMV/CG requests enter free slots as slots and memory allow;
 //   2. advances every active request by one step in a few launches for all
-//      of them together: one multi-matrix ARG-CSR SpMV per precision (FP32
-//      values for SpMV requests and inner CG iterations, FP64 values for the
-//      outer residual of CG), then the CG vector kernels;
-//   3. reads back the per-request scalars, retires finished requests and
-//      copies their results to the caller's host memory.
+//      of them together: a pull of the step's descriptors from mapped pinned
+//      memory, one multi-matrix ARG-CSR SpMV per precision (FP32 values for
+//      SpMV requests and inner CG iterations, FP64 values for the outer
+//      residual of CG), then the CG vector kernels, which also write the
+//      scalars the scheduler needs into a mapped pinned mirror;
+//   3. after one synchronisation, reads those scalars, retires finished
+//      requests and copies their results to the caller's host memory.
 // CG (for SPD matrices) keeps x, r, p, d and every dot product, alpha and
 // beta in FP64; inner iterations use the FP32 matrix; every inner cycle ends
 // with an outer refinement step r = b - A x with the FP64 matrix, and a solve
