@@ -187,9 +187,28 @@ def f32_variant(A, x, dev, timer, torch, ac, steps):
         c, _ = timer.run(g, max(10, steps // 5))
         if best is None or c.mean() < best[1].mean():
             best = (V, c)
+    ac.spmv(M, xd, yd)
+    err = error_vs_fp64(A, x, yd.cpu().numpy())
     return {"block_dim": 128, "desired_chunk_size": 1, "mean_ms": float(t.mean()),
             "gbps": B / (t.mean() * 1e-3) / 1e9, "csr_gbps": B / (best[1].mean() * 1e-3) / 1e9,
-            "csr_lanes_per_row": best[0], "speedup_vs_csr": float(best[1].mean() / t.mean())}
+            "csr_lanes_per_row": best[0], "speedup_vs_csr": float(best[1].mean() / t.mean()),
+            "error_vs_fp64": err}
+
+
+def error_vs_fp64(A, x, y):
+    """y from the GPU against y = A x computed here in FP64 with numpy (every
+    row, original values and x): the largest row error scaled by the row's
+    sum |a_ij x_j|, and the relative 2-norm error.  For reduced-precision
+    storage this is the total error (value rounding, FP32 x and accumulation)."""
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.rp))
+    prod = A.val * x[A.col]
+    ref = np.bincount(rows, weights=prod, minlength=A.n_rows)
+    scale = np.bincount(rows, weights=np.abs(prod), minlength=A.n_rows)
+    d = np.abs(np.asarray(y, dtype=np.float64) - ref)
+    live = scale > 0
+    return {"max_scaled": float(np.max(d[live] / scale[live])) if live.any() else 0.0,
+            "zero_rows_exact": bool(np.all(d[~live] == 0)),
+            "rel_l2": float(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300))}
 
 
 def traffic_for(workload: str, dtype_name: str, T: int, D: int):
@@ -454,6 +473,7 @@ def main():
         "convert_ms": convert_ms,
         "convert_device_grouping_ms": convert_device_ms,
         "kernel_hash": kernel_source_hash(),
+        "error_vs_fp64": error_vs_fp64(A, x, yd.cpu().numpy()),
     }
 
     if not args.no_extras:
