@@ -1,7 +1,8 @@
 // CSR -> ARG-CSR conversion on the GPU (Sec. 3 of the paper).
 //
-// Step 1 (grouping) is a sequential scan and runs on the host (plan.cpp).
-// The kernels here run steps 2-4, every group independently:
+// Step 1 (grouping) is a sequential scan; it runs on the host (plan.cpp), or
+// on the device by binary lifting (group.hip) when the caller has row_ptr on
+// the device only.  The kernels here run steps 2-4, every group independently:
 //   chunks_kernel   step 2: chunk size c_g = min{c >= 1 : sum_r max(1,ceil(L_r/c)) <= T}
 //                   (row-grouped CSR: c_g = max(1, longest row)) and
 //                   t_r = max(1, ceil(L_r/c_g)) chunks per row;
@@ -10,10 +11,12 @@
 //   heavy kernels   the launch schedule: ascending indices of groups whose
 //                   chunk loop is long (compaction by an exclusive scan)
 //   fill_kernel     step 4: every slot (j, k) of a group -- element j of chunk
-//                   k at offset + j*T + k -- is written exactly once: the
+//   fill_long_kernel k at offset + j*T + k -- is written exactly once: the
 //                   matching CSR element if chunk k's row has one there,
 //                   otherwise the artificial zero (0, -1); the CSR elements
-//                   pass through LDS so that reads and writes are coalesced.
+//                   pass through LDS so that reads and writes are coalesced
+//                   (fill_long_kernel takes the blocks of long rows, tile by
+//                   tile, from a list the fill kernel makes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
