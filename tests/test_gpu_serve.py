@@ -133,6 +133,39 @@ def test_serve_block_sizes(srv_mod, T):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
 
 
+def test_serve_clients_on_several_threads(srv_mod):
+    """Four client threads submit and wait at the same time (ctypes releases
+    the GIL, so the calls overlap in the library); every result equals the
+    one the same request gets when submitted alone."""
+    import threading
+    print("\n[gpu] serve threads", flush=True)
+    mats = pool(4)
+    per_thread = [make_requests(mats, 8, 100 + t) for t in range(4)]
+    outs = [None] * 4
+    errors = []
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=16) as srv:
+        admit_all(srv, mats)
+
+        def client(t):
+            try:
+                outs[t] = run_requests(srv, mats, per_thread[t])[0]
+            except Exception as e:                  # noqa: BLE001 - reported below
+                errors.append(repr(e))
+        threads = [threading.Thread(target=client, args=(t,)) for t in range(4)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(300)
+        assert not errors, errors
+        assert srv.stats()["completed"] == 32
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=1) as srv:
+        admit_all(srv, mats)
+        for t in range(4):
+            alone = run_requests(srv, mats, per_thread[t])[0]
+            for a, b in zip(outs[t], alone):
+                assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
 def test_serve_small_staging_falls_back(srv_mod):
     """A staging arena too small for most requests: those bypass it, the
     others go through it; results are the same as with ample staging."""
