@@ -213,6 +213,8 @@ int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim
  * Synchronous: waits for its kernels (it reads back a validation flag).
  * Errors: EINVAL (malformed CSR incl. a column outside [0, n_cols), sizes
  * not matching argcsr_plan), EUNSUPPORTED (block_dim), EOVERFLOW, EHIP.
+ * Column indices are checked while the fill moves them, so after an EINVAL
+ * for a column the contents of out's buffers are unspecified.
  */
 int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
                    const int32_t* row_ptr, const int32_t* col, const double* val,

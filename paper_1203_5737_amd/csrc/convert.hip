@@ -16,7 +16,9 @@
 //                   otherwise the artificial zero (0, -1); the CSR elements
 //                   pass through LDS so that reads and writes are coalesced
 //                   (fill_long_kernel takes the blocks of long rows, tile by
-//                   tile, from a list the fill kernel makes).
+//                   tile, from a list the fill kernel makes); every CSR element
+//                   passes through one of the two, which also check its column
+//                   index against [0, n_cols).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,29 +68,6 @@ __device__ __forceinline__ int wave_min(int v) {
     v = t < v ? t : v;
   }
   return v;
-}
-
-// Every column index in [0, n_cols): 16-byte loads over the aligned body of
-// the array, single elements for the unaligned head and the tail.
-__global__ __launch_bounds__(256) void validate_columns_kernel(
-    const int32_t* __restrict__ col, int64_t nnz, int32_t n_cols, Status* st) {
-  const uint32_t limit = uint32_t(n_cols);          // a negative index wraps above it
-  const int64_t head = min(nnz, int64_t((16 - (reinterpret_cast<uintptr_t>(col) & 15)) & 15) / 4);
-  const int64_t n4 = (nnz - head) / 4;
-  const int4* __restrict__ body = reinterpret_cast<const int4*>(col + head);
-  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  bool bad = false;
-#pragma unroll 4
-  for (int64_t i = tid; i < n4; i += stride) {
-    const int4 v = body[i];
-    bad |= (uint32_t(v.x) >= limit) | (uint32_t(v.y) >= limit) | (uint32_t(v.z) >= limit) |
-           (uint32_t(v.w) >= limit);
-  }
-  const int64_t tail = head + 4 * n4;               // head and tail: fewer than 7 elements
-  for (int64_t k = tid; k < head + (nnz - tail); k += stride)
-    bad |= uint32_t(col[k < head ? k : tail + (k - head)]) >= limit;
-  if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(&st->bad_column, 1);
 }
 
 // Step 2 + 3, one wave per group.  Row l of the group lives in lane l % 64,
@@ -301,12 +280,13 @@ __device__ inline int32_t block_extent(int32_t start, int32_t len, int32_t* lo_o
 // chunk's element from LDS.  Blocks whose range is longer than the stage are
 // left to fill_long_kernel: a group whose chunks are longer than stage/64
 // elements, the only kind that can have such blocks, appends one work item per
-// tile of kLongSteps steps to a list.
+// tile of kLongSteps steps to a list.  Every staged column index is checked
+// against [0, n_cols) (a negative one wraps above the limit as unsigned).
 template <int DT>
 __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const double* __restrict__ val, const argcsr_group_info* __restrict__ groups,
-    int32_t n_groups, int32_t T, const int32_t* __restrict__ tm, int32_t stage,
+    int32_t n_groups, int32_t n_cols, int32_t T, const int32_t* __restrict__ tm, int32_t stage,
     Status* __restrict__ st, int32_t* __restrict__ long_list,
     int32_t* __restrict__ columns, typename Val<DT>::storage* __restrict__ values) {
   using S = typename Val<DT>::storage;
@@ -333,6 +313,8 @@ __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
     }
   }
   chunk_sources(gi, rp, tm, T, lane, src_start, src_len);
+  const uint32_t limit = uint32_t(n_cols);
+  bool bad = false;
   for (int32_t k0 = 0; k0 < T; k0 += 64) {
     const int32_t k = k0 + lane;
     const bool mine = k < T;
@@ -344,7 +326,9 @@ __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
     if (extent <= stage) {
 #pragma unroll 8
       for (int32_t p = lane; p < extent; p += 64) {
-        stage_col[p] = col[lo + p];
+        const int32_t cp = col[lo + p];
+        bad |= uint32_t(cp) >= limit;
+        stage_col[p] = cp;
         stage_val[p] = Val<DT>::from_f64(val[lo + p]);
       }
       wave_lds_sync();
@@ -363,6 +347,7 @@ __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
       wave_lds_sync();   // the next block overwrites the stage
     }
   }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(&st->bad_column, 1);
 }
 
 // Step 4 for the blocks fill_kernel leaves: those whose CSR range is longer
@@ -373,12 +358,14 @@ __global__ __launch_bounds__(kMaxFillWaves * 64) void fill_kernel(
 // elements of each of 64/kLongSteps chunks (a lane past its chunk's end reads
 // an element of the block and keeps the padding value, so the loads carry no
 // branch and are issued together), and each store writes one step of the 64
-// chunks, 64 consecutive slots.
+// chunks, 64 consecutive slots.  The column indices of the elements it moves
+// are checked as in fill_kernel.
 template <int DT>
 __global__ __launch_bounds__(64) void fill_long_kernel(
     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
     const double* __restrict__ val, const argcsr_group_info* __restrict__ groups,
-    int32_t T, const int32_t* __restrict__ tm, int32_t stage, const Status* __restrict__ st,
+    int32_t n_cols, int32_t T, const int32_t* __restrict__ tm, int32_t stage,
+    Status* __restrict__ st,
     const int32_t* __restrict__ long_list, int32_t* __restrict__ columns,
     typename Val<DT>::storage* __restrict__ values) {
   using S = typename Val<DT>::storage;
@@ -391,6 +378,8 @@ __global__ __launch_bounds__(64) void fill_long_kernel(
   const int lane = lane_id();
   const int jj = lane % kLongSteps, kq = lane / kLongSteps;
   const int32_t n_items = st->long_items;
+  const uint32_t limit = uint32_t(n_cols);
+  bool bad = false;
   for (int32_t i = blockIdx.x; i < n_items; i += gridDim.x) {
     const argcsr_group_info gi = groups[long_list[2 * int64_t(i)]];
     const int32_t j0 = long_list[2 * int64_t(i) + 1];
@@ -412,6 +401,7 @@ __global__ __launch_bounds__(64) void fill_long_kernel(
         const int32_t e = ok[it] ? src_start[kc] + j : lo;
         cv[it] = col[e];
         v[it] = val[e];
+        bad |= ok[it] && uint32_t(cv[it]) >= limit;
       }
 #pragma unroll
       for (int it = 0; it < kLongSteps; ++it) {
@@ -431,6 +421,7 @@ __global__ __launch_bounds__(64) void fill_long_kernel(
       wave_lds_sync();   // the next block or item overwrites the tile and tables
     }
   }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(&st->bad_column, 1);
 }
 
 // The stage holds the blocks of chunks up to twice the matrix's mean chunk
@@ -449,12 +440,12 @@ void launch_fill(int32_t n_groups, hipStream_t s, const int32_t* rp, const int32
   const size_t lds = fill_lds_bytes<S>(int32_t(T), stage) * size_t(waves);
   const uint32_t blocks = uint32_t((int64_t(n_groups) + waves - 1) / waves);
   fill_kernel<DT><<<dim3(blocks), 64 * waves, lds, s>>>(
-      rp, col, val, out->groups, out->n_groups, out->block_dim, out->threads_mapping, stage, st,
-      long_list, out->columns, static_cast<S*>(out->values));
+      rp, col, val, out->groups, out->n_groups, out->n_cols, out->block_dim, out->threads_mapping,
+      stage, st, long_list, out->columns, static_cast<S*>(out->values));
   const int64_t long_blocks = std::min<int64_t>(n_groups, kLongGrid);
   fill_long_kernel<DT><<<dim3(uint32_t(long_blocks)), 64, sizeof(int32_t) * 2 * size_t(T), s>>>(
-      rp, col, val, out->groups, out->block_dim, out->threads_mapping, stage, st, long_list,
-      out->columns, static_cast<S*>(out->values));
+      rp, col, val, out->groups, out->n_cols, out->block_dim, out->threads_mapping, stage, st,
+      long_list, out->columns, static_cast<S*>(out->values));
 }
 
 }  // namespace
@@ -549,12 +540,6 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
     rc = device_groups.write(out->groups);
     if (rc) return rc;
   }
-  if (nnz > 0) {
-    const int64_t want = (nnz + 1023) / 1024;     // 4 elements per thread per pass
-    const int blocks = (int)(want < 8192 ? want : 8192);
-    validate_columns_kernel<<<blocks, 256, 0, s>>>(col, nnz, n_cols, st);
-    ARGCSR_HIP(hipGetLastError());
-  }
   const int wave_blocks = (G + kWaves - 1) / kWaves;
   chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, out->groups, G, T,
                                                    out->format == ARGCSR_FORMAT_RG ? 1 : 0,
@@ -570,8 +555,6 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   Status host_st{};
   ARGCSR_HIP(hipMemcpyAsync(&host_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   ARGCSR_HIP(hipStreamSynchronize(s));
-  if (host_st.bad_column)
-    return fail(ARGCSR_EINVAL, "a column index lies outside [0, %d)", n_cols);
   if (host_st.total_slots > INT32_MAX)
     return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", host_st.total_slots);
   if (host_st.total_slots != out->n_slots)
@@ -592,7 +575,10 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
     default: launch_fill<ARGCSR_F16>(G, s, row_ptr, col, val, st, long_list, out); break;
   }
   ARGCSR_HIP(hipGetLastError());
+  ARGCSR_HIP(hipMemcpyAsync(&host_st, st, sizeof(Status), hipMemcpyDeviceToHost, s));
   ARGCSR_HIP(hipStreamSynchronize(s));
+  if (host_st.bad_column)
+    return fail(ARGCSR_EINVAL, "a column index lies outside [0, %d)", n_cols);
   return ARGCSR_OK;
 }
 

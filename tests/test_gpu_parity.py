@@ -156,9 +156,9 @@ def test_convert_rejects_bad_input(ac):
 
 
 def test_convert_validates_every_column_position(ac):
-    """The column check reads 16-byte words over the aligned body of the
-    array and single elements around it: a bad index in the unaligned head,
-    the body or the tail is found, for every alignment of the array."""
+    """Every column index is checked as the fill stages it: a bad index at
+    the start, the middle or the end of the array is found, for every
+    alignment of the array's start."""
     rng = np.random.default_rng(23)
     L = rng.integers(0, 9, 500)
     A = csr_from_lengths(L, 300, 23)
@@ -182,6 +182,32 @@ def test_convert_validates_every_column_position(ac):
         M = ac.convert(dev, 32, 2)                            # every index valid
         ref = oracle.convert(A.rp, A.col, A.val, 32, 2)
         assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
+
+
+def test_convert_validates_columns_of_long_rows(ac):
+    """The chunks of rows longer than the fill's stage are moved tile by tile
+    by fill_long_kernel, which checks their columns itself: a bad index at
+    the tile and chunk boundaries of two long rows (in groups of their own,
+    chunk sizes 79 and 24, the last chunk of the second one short) is found,
+    and the matrix without it converts to the oracle's columns."""
+    rng = np.random.default_rng(31)
+    L = rng.integers(0, 6, 400)
+    L[10] = 5000          # alone in its group at T=64, D=1: 64 chunks of 79
+    L[200] = 1500         # 64 chunks of 24
+    A = csr_from_lengths(L, 6000, 31)
+    for row, c in ((10, 79), (200, 24)):
+        s0 = int(A.rp[row])
+        picks = {0, 1, 15, 16, 17, c - 1, c, c + 15, 31 * c + 16, int(L[row]) - 1}
+        for off in sorted(p for p in picks if p < int(L[row])):
+            col = A.col.copy()
+            col[s0 + off] = -1 if off % 2 else A.n_cols
+            dev = ac.to_device_csr(A.rp, col, A.val, A.n_cols, DEV)
+            with pytest.raises(ac.ArgCsrError) as e:
+                ac.convert(dev, 64, 1)
+            assert e.value.code == ac._lib.EINVAL, (row, off)
+    M = ac.convert(ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV), 64, 1)
+    ref = oracle.convert(A.rp, A.col, A.val, 64, 1)
+    assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
 
 
 # ---------------------------------------------------------------------------
