@@ -515,19 +515,36 @@ void fill_matwork(MatWork& w, const argcsr_matrix& A, const void* values, const 
   heavy += A.heavy_groups ? A.n_heavy : 0;
 }
 
+void free_desc(argcsr_server* s) {
+  if (s->d_desc) (void)hipFree(s->d_desc);
+  if (s->h_desc) (void)hipHostFree(s->h_desc);
+  s->d_desc = nullptr;
+  s->h_desc = nullptr;
+  s->h_desc_dev = nullptr;
+  s->d_desc_bytes = 0;
+}
+
+// Grows the descriptor buffers (device copy and mapped host block) to hold
+// `bytes`; on failure the server is left with none, so the next step retries.
 int ensure_desc(argcsr_server* s, size_t bytes) {
   if (bytes <= s->d_desc_bytes) return ARGCSR_OK;
   if (s->d_desc) {
     ARGCSR_HIP(hipStreamSynchronize(s->stream));
-    (void)hipFree(s->d_desc);
-    (void)hipHostFree(s->h_desc);
-    s->d_desc = s->h_desc = nullptr;
+    free_desc(s);
   }
   const size_t want = std::max(bytes * 2, size_t(1) << 20);
-  ARGCSR_HIP(hipMalloc(&s->d_desc, want));
-  ARGCSR_HIP(hipHostMalloc(&s->h_desc, want, hipHostMallocMapped | hipHostMallocCoherent));
-  void* dev = nullptr;
-  ARGCSR_HIP(hipHostGetDevicePointer(&dev, s->h_desc, 0));
+  void *d = nullptr, *h = nullptr, *dev = nullptr;
+  const bool ok =
+      hipMalloc(&d, want) == hipSuccess &&
+      hipHostMalloc(&h, want, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+      hipHostGetDevicePointer(&dev, h, 0) == hipSuccess;
+  s->d_desc = d;
+  s->h_desc = h;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_desc(s);
+    return fail(ARGCSR_ENOMEM, "cannot allocate %zu bytes of request descriptors", want);
+  }
   s->h_desc_dev = dev;
   s->d_desc_bytes = want;
   return ARGCSR_OK;
@@ -755,7 +772,7 @@ void scheduler(argcsr_server* s) {
     }
     if (!s->active.empty()) {
       const int rc = step(s);
-      if (rc != ARGCSR_OK) {                       // device error: fail everything in flight
+      if (rc != ARGCSR_OK) {       // device or allocation error: fail everything in flight
         for (Request* r : s->active) {
           r->res.status = rc;
           release_request(s, r);
@@ -933,8 +950,7 @@ extern "C" int argcsr_server_destroy(argcsr_server* s) {
   s->staging.clear();
   (void)hipStreamSynchronize(s->stream);
   (void)hipStreamDestroy(s->stream);
-  if (s->d_desc) (void)hipFree(s->d_desc);
-  if (s->h_desc) (void)hipHostFree(s->h_desc);
+  free_desc(s);
   (void)hipFree(s->d_scalars);
   (void)hipHostFree(s->h_scalars);
   delete s;
