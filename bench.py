@@ -315,7 +315,7 @@ def run_serve(args, torch, ac):
               rng.uniform(-1, 1, pool[m].n_cols).astype(np.float32)
               for m, cg in zip(mats, kinds)]
     srv = serve.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_active=args.max_active,
-                       cg_tol=1e-10)
+                       cg_tol=1e-10, cg_inner_per_step=args.cg_inner_per_step)
     records = []
     t0 = time.monotonic_ns() + 50_000_000
     arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
@@ -359,7 +359,8 @@ def run_serve(args, torch, ac):
         "config": {"workload": f"serving: Poisson {args.rate:g} req/s, 50% SpMV / 50% CG to 1e-10, "
                                f"pool of {P} SPD shifted 2D/3D Laplacians, n log-uniform [1e4,1e6], "
                                f"Zipf(1.1) popularity, {args.budget_gb:g} GB budget",
-                   "max_active": args.max_active},
+                   "max_active": args.max_active,
+                   "cg_inner_per_step": args.cg_inner_per_step or 2},
         "latency": {"all": pct(ok), "p99_ms": float(np.percentile(all_lat, 99)),
                     "warm": pct([x for x in ok if not x[2]]), "cold": pct([x for x in ok if x[2]]),
                     "spmv": pct([x for x in ok if not x[3]]), "cg": pct([x for x in ok if x[3]])},
@@ -392,6 +393,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests")
     ap.add_argument("--warm-requests", type=int, default=200, help="serve: unmeasured first requests")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct matrices")
+    ap.add_argument("--cg-inner-per-step", type=int, default=0,
+                    help="serve: inner CG iterations a step may run (0 = the server's default)")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: device memory budget")
     ap.add_argument("--max-active", type=int, default=64, help="serve: requests per step")
     args = ap.parse_args()

@@ -347,6 +347,8 @@ typedef struct {
                                   filled and drained by a copy thread so the scheduler
                                   never waits on host copies: 0 = 256 MiB, < 0 = none
                                   (then copies go straight to/from the caller's memory) */
+  int32_t cg_inner_per_step;   /* inner CG iterations one scheduler step may run for a
+                                  request, 0 (= 2) or 1..8; results do not depend on it */
 } argcsr_server_config;
 
 typedef enum {

@@ -59,7 +59,8 @@ class ServerConfig(ctypes.Structure):
                 ("device", ctypes.c_int32), ("block_dim", ctypes.c_int32),
                 ("desired_chunk_size", ctypes.c_int32), ("cg_tol", ctypes.c_double),
                 ("cg_inner_tol", ctypes.c_double), ("cg_max_inner", ctypes.c_int32),
-                ("cg_max_iter", ctypes.c_int32), ("staging_bytes", ctypes.c_int64)]
+                ("cg_max_iter", ctypes.c_int32), ("staging_bytes", ctypes.c_int64),
+                ("cg_inner_per_step", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):

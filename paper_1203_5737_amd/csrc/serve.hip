@@ -11,7 +11,10 @@
 //      memory, one multi-matrix ARG-CSR SpMV per precision (FP32 values for
 //      SpMV requests and inner CG iterations, FP64 values for the outer
 //      residual of CG), then the CG vector kernels, which also write the
-//      scalars the scheduler needs into a mapped pinned mirror;
+//      scalars the scheduler needs into a mapped pinned mirror; requests in
+//      an inner cycle then run up to cg_inner_per_step - 1 further inner
+//      iterations (FP32 SpMV and vector kernels again), each skipped on the
+//      device for a request whose cycle has stopped;
 //   3. after one synchronisation, reads those scalars, retires finished
 //      requests and copies their results to the caller's host memory.
 // CG (for SPD matrices) keeps x, r, p, d and every dot product, alpha and
@@ -572,14 +575,45 @@ int step(argcsr_server* s) {
       else if (r->phase == kPhaseOuter) f64.push_back(r);
     }
   }
-  int32_t tiles = 0;
-  for (Request* r : cg) tiles += (r->mat->m64.n_rows + kTile - 1) / kTile;
-  // descriptor block: MatWork f32 | MatWork f64 | CgVec | tile table | two partials
+  // Inner requests may run further iterations (passes) in this step, as many
+  // as their iteration limits allow; the kernels skip a request once its
+  // cycle has stopped, so later passes hold subsets of the earlier ones.
+  const int passes = s->cfg.cg_inner_per_step > 0 ? s->cfg.cg_inner_per_step : 2;
+  std::vector<std::vector<Request*>> extra(size_t(passes - 1));
+  for (Request* r : cg) {
+    if (r->phase != kPhaseInner) continue;
+    const int k = std::min({passes, s->cfg.cg_max_inner - r->inner_in_cycle,
+                            s->cfg.cg_max_iter - r->res.iterations});
+    for (int q = 2; q <= k; ++q) extra[size_t(q - 2)].push_back(r);
+  }
+  auto tiles_of = [](const std::vector<Request*>& rs) {
+    int32_t t = 0;
+    for (Request* r : rs) t += (r->mat->m64.n_rows + kTile - 1) / kTile;
+    return t;
+  };
+  auto align16 = [](size_t x) { return (x + 15) / 16 * 16; };
+  const int32_t tiles = tiles_of(cg);
+  // descriptor block: MatWork f32 | MatWork f64 | CgVec | tile table, then per
+  // further pass MatWork | CgVec | tile table, then two partial arrays (every
+  // pass's tiles are a subset of the first pass's)
   const size_t o_w32 = 0;
   const size_t o_f64 = o_w32 + sizeof(MatWork) * f32.size();
   const size_t o_vec = o_f64 + sizeof(MatWork) * f64.size();
   const size_t o_tile = o_vec + sizeof(CgVec) * cg.size();
-  const size_t o_part = (o_tile + sizeof(int32_t) * size_t(tiles) + 15) / 16 * 16;
+  struct Pass {
+    size_t o_w, o_vec, o_tile;
+    int32_t tiles, groups, heavy;
+  };
+  std::vector<Pass> xp(extra.size());
+  size_t o = align16(o_tile + sizeof(int32_t) * size_t(tiles));
+  for (size_t q = 0; q < extra.size(); ++q) {
+    xp[q].tiles = tiles_of(extra[q]);
+    xp[q].o_w = o;
+    xp[q].o_vec = o = align16(o + sizeof(MatWork) * extra[q].size());
+    xp[q].o_tile = o = align16(o + sizeof(CgVec) * extra[q].size());
+    o = align16(o + sizeof(int32_t) * size_t(xp[q].tiles));
+  }
+  const size_t o_part = o;
   const size_t o_part2 = o_part + sizeof(double) * size_t(std::max(tiles, 1));
   const size_t total = o_part2 + sizeof(double) * size_t(std::max(tiles, 1));
   int rc = ensure_desc(s, total);
@@ -605,10 +639,30 @@ int step(argcsr_server* s) {
     Request* r = cg[i];
     CgVec& v = reinterpret_cast<CgVec*>(h + o_vec)[i];
     v = CgVec{r->v64[0], r->v64[1], r->v64[2], r->v64[3], r->v64[4], r->v64[5],
-              r->p32, r->q32, r->mat->m64.n_rows, r->phase, t, r->slot, r->parity};
+              r->p32, r->q32, r->mat->m64.n_rows, r->phase, t, r->slot, r->parity, 1,
+              s->cfg.cg_inner_tol * s->cfg.cg_inner_tol * r->cycle_rr0};
     const int32_t nt = (r->mat->m64.n_rows + kTile - 1) / kTile;
     for (int32_t k = 0; k < nt; ++k) tile_req[t + k] = int32_t(i);
     t += nt;
+  }
+  for (size_t q = 0; q < extra.size(); ++q) {
+    const int32_t pass = int32_t(q) + 2;
+    int32_t tq = 0;
+    xp[q].groups = xp[q].heavy = 0;
+    int32_t* tq_req = reinterpret_cast<int32_t*>(h + xp[q].o_tile);
+    for (size_t i = 0; i < extra[q].size(); ++i) {
+      Request* r = extra[q][i];
+      MatWork& w = reinterpret_cast<MatWork*>(h + xp[q].o_w)[i];
+      fill_matwork(w, r->mat->m64, r->mat->values32, r->p32, r->q32, xp[q].groups, xp[q].heavy);
+      CgVec& v = reinterpret_cast<CgVec*>(h + xp[q].o_vec)[i];
+      v = CgVec{r->v64[0], r->v64[1], r->v64[2], r->v64[3], r->v64[4], r->v64[5],
+                r->p32, r->q32, r->mat->m64.n_rows, kPhaseInner, tq, r->slot,
+                r->parity ^ ((pass - 1) & 1), pass,
+                s->cfg.cg_inner_tol * s->cfg.cg_inner_tol * r->cycle_rr0};
+      const int32_t nt = (r->mat->m64.n_rows + kTile - 1) / kTile;
+      for (int32_t k = 0; k < nt; ++k) tq_req[tq + k] = int32_t(i);
+      tq += nt;
+    }
   }
   {
     const int64_t n16 = int64_t(o_part / 16);          // o_part is a multiple of 16
@@ -627,11 +681,23 @@ int step(argcsr_server* s) {
   if (!f32.empty()) launch_mspmv<ARGCSR_F32>(s, d_w32, int32_t(f32.size()), g32, h32);
   if (!f64.empty()) launch_mspmv<ARGCSR_F64>(s, d_w64, int32_t(f64.size()), g64, h64);
   if (ncg > 0) {
-    cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, d_pq);
+    cg_dot_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars, d_pq);
     cg_update_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars,
                                                          s->h_scalars_dev, d_pq, d_rr);
     cg_direction_kernel<<<tiles, kVecBlock, 0, s->stream>>>(d_vec, d_tiles, s->d_scalars,
                                                             s->h_scalars_dev, d_rr);
+  }
+  for (size_t q = 0; q < extra.size() && !extra[q].empty(); ++q) {
+    const auto* dw = reinterpret_cast<const MatWork*>(d + xp[q].o_w);
+    const auto* dv = reinterpret_cast<const CgVec*>(d + xp[q].o_vec);
+    const auto* dt = reinterpret_cast<const int32_t*>(d + xp[q].o_tile);
+    const int32_t tq = xp[q].tiles;
+    launch_mspmv<ARGCSR_F32>(s, dw, int32_t(extra[q].size()), xp[q].groups, xp[q].heavy);
+    cg_dot_kernel<<<tq, kVecBlock, 0, s->stream>>>(dv, dt, s->d_scalars, d_pq);
+    cg_update_kernel<<<tq, kVecBlock, 0, s->stream>>>(dv, dt, s->d_scalars, s->h_scalars_dev,
+                                                      d_pq, d_rr);
+    cg_direction_kernel<<<tq, kVecBlock, 0, s->stream>>>(dv, dt, s->d_scalars, s->h_scalars_dev,
+                                                         d_rr);
   }
   ARGCSR_HIP(hipGetLastError());
   ARGCSR_HIP(hipStreamSynchronize(s->stream));
@@ -647,11 +713,14 @@ int step(argcsr_server* s) {
       done = true;
     } else {
       const CgScalars& sc = s->h_scalars[r->slot];
-      const double rr = sc.rr[1 - r->parity];    // written by this step
-      r->parity ^= 1;
+      // inner: the step ran passes 1..n, pass j with parity parity ^ ((j-1)&1)
+      // writing rr[1 - that]; the other phases ran one pass
+      const int n = r->phase == kPhaseInner ? std::max(1, std::min(sc.passes, passes)) : 1;
+      const double rr = sc.rr[1 - (r->parity ^ ((n - 1) & 1))];
+      r->parity ^= n & 1;
       if (r->phase == kPhaseInner) {
-        r->res.iterations++;
-        r->inner_in_cycle++;
+        r->res.iterations += n;
+        r->inner_in_cycle += n;
         const bool cycle_done = sc.pq <= 0.0 ||
                                 rr <= s->cfg.cg_inner_tol * s->cfg.cg_inner_tol * r->cycle_rr0 ||
                                 r->inner_in_cycle >= s->cfg.cg_max_inner ||
@@ -810,7 +879,8 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
   if (cfg->budget_bytes <= 0 || cfg->max_active < 1 || cfg->max_active > kMaxLaunchMats ||
       !(cfg->cg_tol > 0) || !(cfg->cg_inner_tol > 0) || cfg->cg_max_inner < 1 ||
       cfg->cg_max_iter < 1 || (cfg->block_dim != 0 && cfg->block_dim != 64 &&
-                               cfg->block_dim != 128 && cfg->block_dim != 256))
+                               cfg->block_dim != 128 && cfg->block_dim != 256) ||
+      cfg->cg_inner_per_step < 0 || cfg->cg_inner_per_step > kMaxInnerPerStep)
     return fail(ARGCSR_EINVAL, "invalid server configuration");
   auto* s = new (std::nothrow) argcsr_server();
   if (!s) return fail(ARGCSR_ENOMEM, "host allocation failed");

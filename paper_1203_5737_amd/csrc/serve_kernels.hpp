@@ -9,7 +9,12 @@
 // of the request that needs them, each in the same order, so a step needs no
 // kernel of its own for the scalars; the ones the host needs (|r|^2, |b|^2,
 // p.q) are also written straight into a mapped pinned mirror, so a step needs
-// no copy back either.  No value of one request ever enters
+// no copy back either.  A step may run several inner iterations (passes) of
+// a request back to back: the direction kernel of pass j records whether the
+// request's inner cycle stops there (p.q <= 0 or |r|^2 at or below the
+// cycle's threshold, the same tests the host applies), and the kernels of
+// pass j+1 skip a request that stopped, so the iterations and their
+// arithmetic are exactly those of one pass per step.  No value of one request ever enters
 // another request's arithmetic, so each result is bitwise the same whether
 // the request runs alone or in a mix.
 #pragma once
@@ -23,6 +28,7 @@ namespace argcsr {
 constexpr int kVecBlock = 256;
 constexpr int kVecPerThread = 8;
 constexpr int kTile = kVecBlock * kVecPerThread;
+constexpr int kMaxInnerPerStep = 8;   // inner CG passes one step may run
 
 enum CgPhase : int32_t {
   kPhaseStart = 0,   // r = b, p = r, d = 0, rr = |b|^2 = bnorm2
@@ -43,17 +49,26 @@ struct CgVec {
   int32_t phase;
   int32_t tile_begin;    // first global tile of this request
   int32_t slot;          // index into the scalar array
-  int32_t parity;        // rr[parity] is |r|^2 before this step; the step writes rr[1 - parity]
+  int32_t parity;        // rr[parity] is |r|^2 before this pass; the pass writes rr[1 - parity]
+  int32_t pass;          // 1-based inner pass of the step (1 for the other phases)
+  double stop_rr;        // inner: the cycle stops once |r|^2 <= stop_rr
 };
 
 struct CgScalars {
-  double rr[2];          // recursive (inner) or true (outer) |r|^2, by step parity
+  double rr[2];          // recursive (inner) or true (outer) |r|^2, by pass parity
   double alpha;
   double beta;
   double bnorm2;         // |b|^2
   double pq;             // p . A32 p of the last inner iteration
-  double pad[2];
+  int32_t passes;        // inner passes the last step ran for this request
+  int32_t stop[kMaxInnerPerStep + 1];   // stop[j]: the cycle ended at or before pass j
+  int32_t pad[2];
 };
+
+// Passes after the first skip a request whose cycle has ended.
+__device__ __forceinline__ bool cg_skip(const CgVec& w, const CgScalars* sc) {
+  return w.pass > 1 && sc[w.slot].stop[w.pass - 1] != 0;
+}
 
 // Fixed-order block sum: each thread's values in index order, then a
 // tree over the 256 threads.
@@ -83,10 +98,11 @@ static __global__ __launch_bounds__(kVecBlock) void cg_pre_kernel(const CgVec* _
 // inner: partial sums of p . q32 into `partial`
 static __global__ __launch_bounds__(kVecBlock) void cg_dot_kernel(const CgVec* __restrict__ v,
                                                           const int32_t* __restrict__ tile_req,
+                                                          const CgScalars* __restrict__ sc,
                                                           double* __restrict__ partial) {
   __shared__ double red[kVecBlock];
   const CgVec w = v[tile_req[blockIdx.x]];
-  if (w.phase != kPhaseInner) return;
+  if (w.phase != kPhaseInner || cg_skip(w, sc)) return;
   const int32_t base = (int32_t(blockIdx.x) - w.tile_begin) * kTile;
   double s = 0.0;
   for (int k = 0; k < kVecPerThread; ++k) {
@@ -122,6 +138,7 @@ static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec
                                                              double* __restrict__ rr_partial) {
   __shared__ double red[kVecBlock];
   const CgVec w = v[tile_req[blockIdx.x]];
+  if (cg_skip(w, sc)) return;                       // uniform: one request per workgroup
   const int32_t local = int32_t(blockIdx.x) - w.tile_begin;
   const int32_t base = local * kTile;
   double s = 0.0;
@@ -161,8 +178,9 @@ static __global__ __launch_bounds__(kVecBlock) void cg_update_kernel(const CgVec
 }
 
 // All phases: rr_new = r . r from the request's partials, stored as
-// rr[1 - parity] (and as |b|^2 at the start); inner: beta = rr_new / rr,
-// p = r + beta p, p32 = (float) p.
+// rr[1 - parity] (and as |b|^2 at the start); inner: whether the cycle stops
+// at this pass (stop[pass]), beta = rr_new / rr, p = r + beta p,
+// p32 = (float) p.  A skipped pass passes the stop on to the next one.
 static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const CgVec* __restrict__ v,
                                                                 const int32_t* __restrict__ tile_req,
                                                                 CgScalars* __restrict__ sc,
@@ -171,6 +189,10 @@ static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const Cg
   __shared__ double red[kVecBlock];
   const CgVec w = v[tile_req[blockIdx.x]];
   const int32_t local = int32_t(blockIdx.x) - w.tile_begin;
+  if (cg_skip(w, sc)) {        // this pass's kernels read stop[pass - 1] only, never stop[pass]
+    if (local == 0 && threadIdx.x == 0) sc[w.slot].stop[w.pass] = 1;
+    return;
+  }
   const double rr_new = tiles_sum(rr_partial, w.tile_begin, w.n, red);
   if (local == 0 && threadIdx.x == 0) {
     sc[w.slot].rr[1 - w.parity] = rr_new;
@@ -178,6 +200,10 @@ static __global__ __launch_bounds__(kVecBlock) void cg_direction_kernel(const Cg
     if (w.phase == kPhaseStart) {
       sc[w.slot].bnorm2 = rr_new;
       host_sc[w.slot].bnorm2 = rr_new;
+    }
+    if (w.phase == kPhaseInner) {
+      sc[w.slot].stop[w.pass] = (sc[w.slot].pq <= 0.0 || rr_new <= w.stop_rr) ? 1 : 0;
+      host_sc[w.slot].passes = w.pass;
     }
   }
   if (w.phase != kPhaseInner) return;

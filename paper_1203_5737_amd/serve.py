@@ -24,10 +24,11 @@ class Server:
     def __init__(self, budget_bytes: int = 64 << 30, max_active: int = 64, device: int = 0,
                  block_dim: int = 0, desired_chunk_size: int = 0, cg_tol: float = 1e-10,
                  cg_inner_tol: float = 1e-5, cg_max_inner: int = 200, cg_max_iter: int = 5000,
-                 staging_bytes: int = 0):
+                 staging_bytes: int = 0, cg_inner_per_step: int = 0):
         cfg = ServerConfig(int(budget_bytes), int(max_active), int(device), int(block_dim),
                            int(desired_chunk_size), float(cg_tol), float(cg_inner_tol),
-                           int(cg_max_inner), int(cg_max_iter), int(staging_bytes))
+                           int(cg_max_inner), int(cg_max_iter), int(staging_bytes),
+                           int(cg_inner_per_step))
         self._h = ctypes.c_void_p(0)
         check(lib().argcsr_server_create(ctypes.byref(cfg), ctypes.byref(self._h)),
               "argcsr_server_create")

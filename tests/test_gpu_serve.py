@@ -105,6 +105,54 @@ def test_serve_results_and_alone_vs_mix(srv_mod):
         assert ra["iterations"] == rb["iterations"]
 
 
+def test_serve_inner_iterations_per_step(srv_mod):
+    """A step may run several inner CG iterations of a request; the cycle's
+    stopping tests then run on the device after each one, and later
+    iterations of a stopped request are skipped.  Results, iteration and
+    refinement counts and residuals are bitwise those of one iteration per
+    step, for 2, 3 and 8 per step, with cycles ended by the residual test
+    (cg_max_inner 200) and by the count limit inside a step (cg_max_inner 13);
+    and a solve cut off by cg_max_iter (ENOCONV) stops at the same iterate."""
+    from paper_1203_5737_amd import _lib
+    print("\n[gpu] serve inner iterations per step", flush=True)
+    mats = pool(4)
+    reqs = make_requests(mats, 12, 5)
+    for max_inner in (200, 13):
+        base = None
+        for per_step in (1, 2, 3, 8):
+            with srv_mod.Server(budget_bytes=1 << 30, max_active=16, cg_max_inner=max_inner,
+                                cg_inner_per_step=per_step) as srv:
+                admit_all(srv, mats)
+                out, res = run_requests(srv, mats, reqs)
+            got = ([o.view(np.uint8).copy() for o in out],
+                   [(r["iterations"], r["refinements"], r["relres"]) for r in res])
+            if base is None:
+                base = got
+                for (kind, m, inp), o in zip(reqs, out):
+                    if kind == "cg":
+                        assert true_relres(mats[m], o, inp) <= 1e-10, (max_inner, m)
+                continue
+            for a, b in zip(base[0], got[0]):
+                assert np.array_equal(a, b), (max_inner, per_step)
+            assert base[1] == got[1], (max_inner, per_step)
+    cg_reqs = [(m, inp) for kind, m, inp in reqs if kind == "cg"]
+    outs = []
+    for per_step in (1, 3):
+        with srv_mod.Server(budget_bytes=1 << 30, max_active=8, cg_max_iter=7,
+                            cg_inner_per_step=per_step) as srv:
+            admit_all(srv, mats)
+            got = []
+            for m, b in cg_reqs:
+                t, x = srv.cg(m, b)
+                r = srv.wait(t, 120.0)
+                srv.release(t)
+                assert r["status"] == _lib.ENOCONV and r["iterations"] == 7, r
+                got.append((x.view(np.uint8).copy(), r["relres"]))
+        outs.append(got)
+    for (xa, ra), (xb, rb) in zip(*outs):
+        assert np.array_equal(xa, xb) and ra == rb
+
+
 @pytest.mark.parametrize("T", [128, 256])
 def test_serve_block_sizes(srv_mod, T):
     """Servers converting with T = 128 and 256 (the multi-matrix SpMV has one

@@ -168,6 +168,12 @@ def test_gpu_entry_points_reject_bad_arguments_without_gpu(L):
     d.n_cols = 10
     assert L.argcsr_spmv(None, None, None, None) == _lib.EINVAL
     assert L.argcsr_csr_spmv(4, 4, 4, None, None, None, 0, 3, None, None, None) == _lib.EINVAL
+    # server configuration: inner CG iterations per step outside 0..8
+    h = ctypes.c_void_p(0)
+    for per_step in (-1, 9):
+        cfg = _lib.ServerConfig(1 << 20, 4, 0, 0, 0, 1e-10, 1e-5, 200, 5000, 0, per_step)
+        assert L.argcsr_server_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.EINVAL
+        assert not h.value
 
 
 def heavy_chunk_for(T, S, G):
