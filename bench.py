@@ -400,7 +400,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
