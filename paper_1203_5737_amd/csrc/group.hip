@@ -10,7 +10,8 @@
 // is replaced by binary lifting:
 //   1. next_kernel      J_0[r] = next(r) for every row (a binary search on
 //                       row_ptr staged in LDS), J_0[n] = n;
-//   2. jump_kernel      J_{k+1}[r] = J_k[J_k[r]]: 2^(k+1) groups ahead;
+//   2. jump_kernel      J_{k+1}[r] = J_k[J_k[r]]: 2^(k+1) groups ahead, and in
+//                       the same launch J_{k+2}[r] = J_k[J_k[J_{k+1}[r]]];
 //   3. count_kernel     the number of groups, by descending the levels from 0;
 //   4. starts_kernel    group i starts at p_i = J applied along the bits of i
 //                       (at most K lookups per group) and ends at J_0[p_i].
@@ -72,10 +73,16 @@ __global__ __launch_bounds__(kGroupBlock) void next_kernel(
   j0[r] = int32_t(base + lo);
 }
 
+// Levels k+1 and (when jk2 is given) k+2 from level k alone; every index is
+// a value of J_k, which lies in [0, n].
 __global__ __launch_bounds__(kGroupBlock) void jump_kernel(int32_t n, const int32_t* __restrict__ jk,
-                                                           int32_t* __restrict__ jk1) {
+                                                           int32_t* __restrict__ jk1,
+                                                           int32_t* __restrict__ jk2) {
   const int64_t r = int64_t(blockIdx.x) * kGroupBlock + threadIdx.x;
-  if (r <= n) jk1[r] = jk[jk[r]];
+  if (r > n) return;
+  const int32_t a = jk[jk[r]];
+  jk1[r] = a;
+  if (jk2) jk2[r] = jk[jk[a]];
 }
 
 // groups = 1 + the largest number of jumps from row 0 that stays below n
@@ -148,9 +155,10 @@ int DeviceGrouping::build(int32_t n, const int32_t* rp, int32_t block_dim, int32
   next_kernel<<<dim3(uint32_t(blocks)), kGroupBlock, 0, s>>>(
       n, rp, block_dim, row_grouped ? INT64_MAX / 2 : int64_t(desired) * block_dim,
       row_grouped ? 1 : region_rows, row_grouped ? nullptr : d_regions, levels, flags);
-  for (int32_t k = 0; k + 1 < levels_n; ++k)
-    jump_kernel<<<dim3(uint32_t(blocks)), kGroupBlock, 0, s>>>(n, levels + k * stride,
-                                                               levels + (k + 1) * stride);
+  for (int32_t k = 0; k + 1 < levels_n; k += 2)
+    jump_kernel<<<dim3(uint32_t(blocks)), kGroupBlock, 0, s>>>(
+        n, levels + k * stride, levels + (k + 1) * stride,
+        k + 2 < levels_n ? levels + (k + 2) * stride : nullptr);
   count_kernel<<<1, 64, 0, s>>>(n, levels, levels_n, stride, flags + 1);
   ARGCSR_HIP(hipGetLastError());
   int32_t host_flags[2] = {0, 0};
