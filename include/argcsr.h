@@ -284,7 +284,11 @@ int argcsr_batch_launch(argcsr_batch* b, void* stream);
 /* Work-list sizes and persistent grid of a batch (any pointer may be NULL). */
 int argcsr_batch_info(const argcsr_batch* b, int32_t* n_items, int32_t* n_heavy, int32_t* grid);
 
-/* Waits for the device, then frees the batch (NULL is a no-op). */
+/* Waits for the batch's most recent launch (an event recorded on the stream
+ * of that launch; not a device-wide synchronisation), then frees the batch
+ * (NULL is a no-op).  A caller that launched the same batch on several
+ * streams concurrently orders those streams itself before destroying it.
+ * Errors: EHIP if the wait fails (the batch is freed either way). */
 int argcsr_batch_destroy(argcsr_batch* b);
 
 /* ---- parameter choice --------------------------------------------------- */
@@ -355,13 +359,18 @@ typedef enum {
   ARGCSR_REQ_ADMIT = 0,  /* make matrix_id resident from host CSR (n_rows, n_cols,
                             row_ptr, col, val); a no-op if it already is */
   ARGCSR_REQ_SPMV = 1,   /* out[n_rows] (float) = A in[n_cols] (float), FP32 values */
-  ARGCSR_REQ_CG = 2,     /* out[n] (double) = x with A x = in (double b[n]), A SPD */
+  ARGCSR_REQ_CG = 2,     /* out[n] (double) = x with A x = in (double b[n]), A SPD,
+                            n = n_rows = n_cols */
   ARGCSR_REQ_EVICT = 3   /* drop matrix_id (EBUSY while requests use it) */
 } argcsr_request_kind;
 
 typedef struct {
   int32_t kind;                /* argcsr_request_kind */
-  int32_t n_rows, n_cols;      /* ADMIT */
+  int32_t n_rows, n_cols;      /* ADMIT: the matrix's size.  SPMV / CG: the
+                                  lengths of out (n_rows) and in (n_cols) the
+                                  caller provides; a request whose lengths are
+                                  not the resident matrix's fails with EINVAL
+                                  before any of its buffers is touched */
   int64_t matrix_id;
   const int32_t* row_ptr;      /* ADMIT, host, valid until the request completes */
   const int32_t* col;

@@ -419,39 +419,37 @@ int ora_rgcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
 }
 
 /* ------------------------------------------------------------------------ */
-/* SpMV in ARG-CSR order (Sec. 4, Listing 2): chunk k of group g sums        */
-/* values*x over its slots offset + j*blockDim + k, j < chunkSize, stopping   */
-/* at the first column -1; row l of the group then sums the partial sums of   */
-/* chunks threadsMapping[l-1] .. threadsMapping[l]-1 (0 .. tm[0]-1 for l=0)   */
-/* and overwrites its entry of y.                                             */
+/* SpMV read from the ARG-CSR storage by the format's definition (Sec. 3,    */
+/* Sec. 4): the rows of group g are firstRow .. firstRow+size-1; row r owns  */
+/* the consecutive chunks b_r .. tm[r]-1 of its group (b_r = tm[r-1] inside  */
+/* the group, 0 for its first row); the elements of a chunk k are the slots  */
+/* offset + j*blockDim + k, j = 0, 1, ..., up to the first artificial zero   */
+/* (column -1) or chunkSize slots; a row's elements are its chunks' elements */
+/* in chunk order.  y_r is the sum of value*x[column] over those elements,   */
+/* added left to right (the element order of the row, as in the CSR         */
+/* definition), and overwrites y_r; a row without elements gets 0.          */
 /* ------------------------------------------------------------------------ */
 
 void ora_argcsr_spmv(int32_t n_groups, const int32_t* groups, const int32_t* tm,
                      const int32_t* columns, const double* values,
                      int32_t block_dim, const double* x, double* y)
 {
-    double* partial = (double*)malloc(sizeof(double) * (size_t)block_dim);
     for (int32_t g = 0; g < n_groups; g++) {
         const int32_t first = groups[4 * g + 0], size = groups[4 * g + 1];
         const int32_t offset = groups[4 * g + 2], chunk = groups[4 * g + 3];
-        for (int32_t k = 0; k < block_dim; k++) {
+        for (int32_t r = first; r < first + size; r++) {
+            const int32_t b = (r == first) ? 0 : tm[r - 1];
             double sum = 0.0;
-            for (int32_t j = 0; j < chunk; j++) {
-                const int64_t s = (int64_t)offset + (int64_t)j * block_dim + k;
-                if (columns[s] == -1) break;
-                sum = sum + values[s] * x[columns[s]];
+            for (int32_t k = b; k < tm[r]; k++) {
+                for (int32_t j = 0; j < chunk; j++) {
+                    const int64_t s = (int64_t)offset + (int64_t)j * block_dim + k;
+                    if (columns[s] == -1) break;
+                    sum = sum + values[s] * x[columns[s]];
+                }
             }
-            partial[k] = sum;
-        }
-        for (int32_t l = 0; l < size; l++) {
-            const int32_t begin = (l == 0) ? 0 : tm[first + l - 1];
-            const int32_t end = tm[first + l];
-            double sum = 0.0;
-            for (int32_t i = begin; i < end; i++) sum = sum + partial[i];
-            y[first + l] = sum;
+            y[r] = sum;
         }
     }
-    free(partial);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -125,9 +125,11 @@ int ora_rgcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
                       int32_t* groups, int32_t* tm, int32_t* columns,
                       void* values);
 
-/* SpMV in ARG-CSR order, FP64 (Listing 2 semantics executed
- * sequentially): per group, chunk partial sums stopping at column -1, then
- * per row the sum of its chunks' partial sums.  values are FP64. */
+/* SpMV read from the ARG-CSR storage by the format's definition (Sec. 3,
+ * Sec. 4), FP64: each row's elements are found through the threads mapping
+ * (its chunks) and the chunk layout (slots offset + j*blockDim + k up to the
+ * first column -1), and summed left to right in the row's element order.
+ * With a correct layout this is bitwise the CSR definition.  values are FP64. */
 void ora_argcsr_spmv(int32_t n_groups, const int32_t* groups, const int32_t* tm,
                      const int32_t* columns, const double* values,
                      int32_t block_dim, const double* x, double* y);

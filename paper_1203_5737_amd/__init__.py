@@ -226,13 +226,19 @@ def csr_spmv(A: DeviceCsr, x: torch.Tensor, y: Optional[torch.Tensor] = None,
     """Plain CSR baseline y = A x (argcsr_csr_spmv).  `values` overrides A.val
     with a tensor of storage_dtype(dtype) (e.g. FP32 values)."""
     vals = A.val if values is None else values
-    if vals.dtype != _STORAGE[dtype]:
-        raise ValueError(f"values must be {_STORAGE[dtype]} for dtype {dtype}")
+    if dtype not in _STORAGE:
+        raise ValueError(f"unknown dtype {dtype}")
+    if vals.dtype != _STORAGE[dtype] or not vals.is_contiguous() or vals.numel() != A.nnz:
+        raise ValueError(f"values must be a contiguous {_STORAGE[dtype]} vector of length {A.nnz}")
     want = vector_dtype(dtype)
-    if x.dtype != want or x.numel() != A.n_cols:
-        raise ValueError(f"x must be a {want} vector of length {A.n_cols}")
+    if x.dtype != want or not x.is_contiguous() or x.numel() != A.n_cols:
+        raise ValueError(f"x must be a contiguous {want} vector of length {A.n_cols}")
     if y is None:
         y = torch.empty(A.n_rows, dtype=want, device=x.device)
+    elif y.dtype != want or not y.is_contiguous() or y.numel() != A.n_rows:
+        raise ValueError(f"y must be a contiguous {want} vector of length {A.n_rows}")
+    if y.data_ptr() == x.data_ptr() and x.numel() > 0:
+        raise ValueError("y must not alias x")
     check(lib().argcsr_csr_spmv(A.n_rows, A.n_cols, A.nnz, _ptr(A.row_ptr), _ptr(A.col),
                                 _ptr(vals), int(dtype), int(lanes_per_row), _ptr(x), _ptr(y),
                                 _stream(stream)), "argcsr_csr_spmv")

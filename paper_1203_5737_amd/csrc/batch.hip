@@ -136,6 +136,7 @@ void free_batch(argcsr_batch* b) {
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_heavy) (void)hipFree(b->d_heavy);
   if (b->queue) (void)hipFree(b->queue);
+  if (b->last) (void)hipEventDestroy(b->last);
   delete b;
 }
 
@@ -214,6 +215,11 @@ extern "C" int argcsr_batch_create(int32_t n_mats, const argcsr_matrix* mats,
   if (!b) return fail(ARGCSR_ENOMEM, "host allocation failed");
   int rc = build_batch(n_mats, mats, xs, ys, b);
   if (rc) { free_batch(b); return rc; }
+  if (hipEventCreateWithFlags(&b->last, hipEventDisableTiming) != hipSuccess) {
+    b->last = nullptr;
+    free_batch(b);
+    return fail(ARGCSR_EHIP, "hipEventCreate failed");
+  }
   // capture reset + persistent kernel into a graph on a private stream
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
@@ -244,14 +250,22 @@ extern "C" int argcsr_batch_launch(argcsr_batch* b, void* stream) {
   using namespace argcsr;
   clear_error();
   if (!b) return fail(ARGCSR_EINVAL, "batch is NULL");
-  return launch_kernels(b, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int rc = launch_kernels(b, s);
+  if (rc) return rc;
+  ARGCSR_HIP(hipEventRecord(b->last, s));
+  b->launched = true;
+  return ARGCSR_OK;
 }
 
 extern "C" int argcsr_batch_graph_launch(argcsr_batch* b, void* stream) {
   using namespace argcsr;
   clear_error();
   if (!b || !b->graph_exec) return fail(ARGCSR_EINVAL, "batch is NULL or has no graph");
-  ARGCSR_HIP(hipGraphLaunch(b->graph_exec, static_cast<hipStream_t>(stream)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ARGCSR_HIP(hipGraphLaunch(b->graph_exec, s));
+  ARGCSR_HIP(hipEventRecord(b->last, s));
+  b->launched = true;
   return ARGCSR_OK;
 }
 
@@ -270,9 +284,14 @@ extern "C" int argcsr_batch_destroy(argcsr_batch* b) {
   using namespace argcsr;
   clear_error();
   if (b) {
-    // the graph may still be in flight on a caller stream
-    ARGCSR_HIP(hipDeviceSynchronize());
+    // the last launch may still be in flight on a caller stream: wait for it
+    // alone (launches are ordered on their streams; a caller that launches
+    // on several streams at once orders them itself)
+    const hipError_t e = b->launched ? hipEventSynchronize(b->last) : hipSuccess;
     free_batch(b);
+    if (e != hipSuccess)
+      return fail(ARGCSR_EHIP, "waiting for the batch's last launch failed: %s",
+                  hipGetErrorString(e));
   }
   return ARGCSR_OK;
 }

@@ -37,4 +37,6 @@ struct argcsr_batch {
   void* queue = nullptr;     // two int32 counters
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  hipEvent_t last = nullptr;  // recorded after every launch; destroy waits for it
+  bool launched = false;
 };

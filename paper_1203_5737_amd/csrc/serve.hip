@@ -450,6 +450,11 @@ int activate(argcsr_server* s, Request* r) {
   Resident* m = it->second.get();
   const argcsr_matrix& A = m->m64;
   if (!r->q.in || !r->q.out) return fail(ARGCSR_EINVAL, "request input or output is NULL");
+  // the caller's buffers hold the lengths it states; they must be the matrix's
+  if (r->q.n_rows != A.n_rows || r->q.n_cols != A.n_cols)
+    return fail(ARGCSR_EINVAL,
+                "request for matrix %lld states %d x %d, but the resident matrix is %d x %d",
+                (long long)r->q.matrix_id, r->q.n_rows, r->q.n_cols, A.n_rows, A.n_cols);
   auto grab = [&](size_t bytes) -> void* {
     void* p = alloc_evicting(s, bytes, m->id);
     if (p) r->blocks.push_back(p);

@@ -55,17 +55,22 @@ class Server:
         return self._submit(Request(REQ_EVICT, 0, 0, int(matrix_id)), None)
 
     def spmv(self, matrix_id: int, x, n_rows: int):
-        """Queues y = A x (FP32 values, x and y FP32); returns (ticket, y)."""
-        x = np.ascontiguousarray(x, dtype=np.float32)
-        y = np.empty(n_rows, dtype=np.float32)
-        req = Request(REQ_SPMV, 0, 0, int(matrix_id), None, None, None, _p(x), _p(y))
+        """Queues y = A x (FP32 values, x and y FP32); returns (ticket, y).
+        The request states len(x) and n_rows; the server rejects it (EINVAL)
+        unless they are the resident matrix's columns and rows."""
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1)
+        y = np.empty(int(n_rows), dtype=np.float32)
+        req = Request(REQ_SPMV, y.shape[0], x.shape[0], int(matrix_id), None, None, None,
+                      _p(x), _p(y))
         return self._submit(req, (x, y)), y
 
     def cg(self, matrix_id: int, b):
-        """Queues a CG solve A x = b (FP64 b, x); returns (ticket, x)."""
-        b = np.ascontiguousarray(b, dtype=np.float64)
+        """Queues a CG solve A x = b (FP64 b, x); returns (ticket, x).  The
+        server rejects it (EINVAL) unless len(b) is the matrix's size."""
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
         x = np.empty_like(b)
-        req = Request(REQ_CG, 0, 0, int(matrix_id), None, None, None, _p(b), _p(x))
+        req = Request(REQ_CG, b.shape[0], b.shape[0], int(matrix_id), None, None, None,
+                      _p(b), _p(x))
         return self._submit(req, (b, x)), x
 
     def poll(self, ticket: int) -> dict:

@@ -31,10 +31,12 @@ MUTANTS = {
     "offset_forgets_block_dim": ("offset += (int64_t)c * block_dim;", "offset += (int64_t)c;"),
     "csr_drops_last_term": ("for (int64_t k = rp[i]; k < rp[i + 1]; k++)", "for (int64_t k = rp[i]; k + 1 < rp[i + 1]; k++)"),
     "csr_wrong_sign": ("sum = sum + val[k] * x[col[k]];", "sum = sum - val[k] * x[col[k]];"),
-    "row_reduction_wrong_begin": ("const int32_t begin = (l == 0) ? 0 : tm[first + l - 1];\n            const int32_t end = tm[first + l];\n            double sum",
-                                  "const int32_t begin = (l == 0) ? 0 : tm[first + l - 1] - 1;\n            const int32_t end = tm[first + l];\n            double sum"),
-    "chunk_sum_transposed_index": ("const int64_t s = (int64_t)offset + (int64_t)j * block_dim + k;\n                if (columns[s] == -1) break;\n                sum",
-                                   "const int64_t s = (int64_t)offset + (int64_t)k * chunk + j;\n                if (s >= (int64_t)offset + (int64_t)chunk * block_dim || columns[s] == -1) break;\n                sum"),
+    "row_chunks_wrong_begin": ("const int32_t b = (r == first) ? 0 : tm[r - 1];",
+                               "const int32_t b = (r == first) ? 0 : tm[r - 1] - 1;"),
+    "row_chunks_stop_one_early": ("for (int32_t k = b; k < tm[r]; k++) {\n                for (int32_t j = 0; j < chunk; j++) {\n                    const int64_t s = (int64_t)offset + (int64_t)j * block_dim + k;\n                    if (columns[s] == -1) break;\n                    sum",
+                                  "for (int32_t k = b; k + 1 < tm[r]; k++) {\n                for (int32_t j = 0; j < chunk; j++) {\n                    const int64_t s = (int64_t)offset + (int64_t)j * block_dim + k;\n                    if (columns[s] == -1) break;\n                    sum"),
+    "chunk_sum_transposed_index": ("const int64_t s = (int64_t)offset + (int64_t)j * block_dim + k;\n                    if (columns[s] == -1) break;\n                    sum",
+                                   "const int64_t s = (int64_t)offset + (int64_t)k * chunk + j;\n                    if (s >= (int64_t)offset + (int64_t)chunk * block_dim || columns[s] == -1) break;\n                    sum"),
     "rounding_ties_to_odd": ("fmod(k, 2.0) != 0.0", "fmod(k, 2.0) == 0.0"),
     "rounding_ties_away": ("frac > 0.5 ||", "frac >= 0.5 ||"),
     "rounding_no_subnormal_quantum": ("(ue < emin ? emin : ue) - man_bits", "ue - man_bits"),
