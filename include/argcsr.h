@@ -361,7 +361,8 @@ typedef enum {
   ARGCSR_REQ_SPMV = 1,   /* out[n_rows] (float) = A in[n_cols] (float), FP32 values */
   ARGCSR_REQ_CG = 2,     /* out[n] (double) = x with A x = in (double b[n]), A SPD,
                             n = n_rows = n_cols */
-  ARGCSR_REQ_EVICT = 3   /* drop matrix_id (EBUSY while requests use it) */
+  ARGCSR_REQ_EVICT = 3   /* drop matrix_id (EBUSY while running or queued
+                            requests use it) */
 } argcsr_request_kind;
 
 typedef struct {
@@ -400,9 +401,17 @@ typedef struct {
 int argcsr_server_create(const argcsr_server_config* cfg, argcsr_server** out);
 
 /* Queues a request (thread-safe, non-blocking) and returns its ticket.
- * Requests are taken in submission order; an SPMV/CG request for a matrix
- * that is not resident when it is started fails with ENOTFOUND.  A matrix
- * with queued or active requests is never evicted. */
+ * Requests are taken in submission order.  A matrix that a running request
+ * uses is never evicted; queued requests do not pin their matrices (an ADMIT
+ * evicts matrices no queued request names first).  An ADMIT that finds the
+ * budget full even after evicting every matrix no running request uses
+ * waits, and every request behind it with it, until running requests end
+ * and free memory; it fails with EBUDGET only if the matrix can never fit
+ * (it needs more than the whole budget, or nothing is running).  An
+ * SPMV/CG request for a matrix that is not resident when it is started
+ * fails with ENOTFOUND: submit the ADMIT (a no-op for a resident matrix)
+ * right before the request that needs it; in-order processing then keeps
+ * the matrix resident until the request starts. */
 int argcsr_server_submit(argcsr_server* s, const argcsr_request* r, uint64_t* ticket);
 
 /* Current result of a ticket (status ARGCSR_PENDING while in flight). */

@@ -4,8 +4,11 @@
 // One scheduler thread owns all device work (one stream).  Clients submit
 // requests into a queue and poll or wait on tickets.  Each scheduler step:
 //   1. takes queued requests in order: ADMIT converts a matrix and keeps it
-//      resident (evicting least-recently-used idle matrices if the budget is
-//      short); SPMV/CG requests enter free slots as slots and memory allow;
+//      resident, evicting matrices no running request uses (least recently
+//      used first, those no queued request names before the others) if the
+//      budget is short, and waiting, with every request behind it, while the
+//      matrix cannot fit until running requests end; SPMV/CG requests enter
+//      free slots as slots and memory allow;
 //   2. advances every active request by one step in a few launches for all
 //      of them together: a pull of the step's descriptors from mapped pinned
 //      memory, one multi-matrix ARG-CSR SpMV per precision (FP32 values for
@@ -130,6 +133,9 @@ struct Resident {
 };
 
 enum ReqStatus : int32_t { kPending = 1 };
+// admit(): the matrix does not fit yet; memory frees up as running requests
+// end, so the ADMIT stays at the head of the queue and is tried again
+constexpr int kAdmitWait = 2;
 
 struct Request {
   uint64_t ticket = 0;
@@ -148,6 +154,9 @@ struct Request {
   float* p32 = nullptr;
   float* q32 = nullptr;
   Resident* mat = nullptr;
+  // ADMIT: sizes from argcsr_plan, kept while the ADMIT waits for memory
+  int32_t plan_groups = -1, plan_heavy = 0;
+  int64_t plan_slots = 0;
   // pinned staging of the input (set by the copy helper when filled) and of
   // the result
   void* stage = nullptr;
@@ -225,6 +234,16 @@ bool matrix_idle(argcsr_server* s, int64_t id) {
   return s->refs.find(id) == s->refs.end();
 }
 
+// A matrix is pinned while a running request (active, or waiting for its
+// input copy) uses it; queued requests do not pin.
+bool pinned(const argcsr_server* s, const Resident* m) {
+  for (const Request* r : s->active)
+    if (r->mat == m) return true;
+  for (const Request* r : s->staging)
+    if (r->mat == m) return true;
+  return false;
+}
+
 void evict(argcsr_server* s, Resident* m) {
   for (void* p : m->blocks) s->arena.release(p);
   std::lock_guard<std::mutex> lock(s->mu);
@@ -233,25 +252,47 @@ void evict(argcsr_server* s, Resident* m) {
   s->stats.resident_bytes -= int64_t(m->bytes);
 }
 
-// Allocates from the arena, evicting least-recently-used idle matrices
-// (never `keep`) until the request fits.
+// Arena bytes that evicting every unpinned resident matrix (but `keep`)
+// would add to the free space.
+size_t evictable_bytes(const argcsr_server* s, int64_t keep) {
+  size_t b = 0;
+  for (const auto& kv : s->resident) {
+    const Resident* m = kv.second.get();
+    if (m->id != keep && !pinned(s, m)) b += m->bytes;
+  }
+  return b;
+}
+
+// Allocates from the arena, evicting unpinned matrices (never `keep`) until
+// the request fits: first those no queued request refers to, least recently
+// used first, then those that queued requests refer to (they would be
+// admitted again).  Returns nullptr when every candidate is gone.
 void* alloc_evicting(argcsr_server* s, size_t bytes, int64_t keep) {
   for (;;) {
     if (void* p = s->arena.alloc(bytes)) return p;
     Resident* victim = nullptr;
+    bool victim_idle = false;
     for (auto& kv : s->resident) {
       Resident* m = kv.second.get();
-      if (m->id == keep || !matrix_idle(s, m->id)) continue;
-      bool used = false;
-      for (Request* r : s->active) used |= r->mat == m;
-      if (used) continue;
-      if (!victim || m->last_use < victim->last_use) victim = m;
+      if (m->id == keep || pinned(s, m)) continue;
+      const bool idle = matrix_idle(s, m->id);
+      if (!victim || (idle && !victim_idle) ||
+          (idle == victim_idle && m->last_use < victim->last_use)) {
+        victim = m;
+        victim_idle = idle;
+      }
     }
     if (!victim) return nullptr;
     const int64_t id = victim->id;
     evict(s, victim);
     s->resident.erase(id);
   }
+}
+
+// Whether memory will free up without the scheduler's help: requests are
+// running (their vectors, and the pins on their matrices, go when they end).
+bool memory_will_free(const argcsr_server* s) {
+  return !s->active.empty() || !s->staging.empty();
 }
 
 int admit(argcsr_server* s, Request* r) {
@@ -281,9 +322,37 @@ int admit(argcsr_server* s, Request* r) {
   A.block_dim = T;
   A.desired_chunk_size = D;
   A.dtype = ARGCSR_F64;
-  rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, ARGCSR_FORMAT_ARG, &A.n_groups, &A.n_slots,
-                   &A.n_heavy);
-  if (rc) return rc;
+  if (r->plan_groups < 0) {       // planned once, also when the ADMIT has to wait
+    rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, ARGCSR_FORMAT_ARG, &r->plan_groups,
+                     &r->plan_slots, &r->plan_heavy);
+    if (rc) {
+      r->plan_groups = -1;
+      return rc;
+    }
+  }
+  A.n_groups = r->plan_groups;
+  A.n_slots = r->plan_slots;
+  A.n_heavy = r->plan_heavy;
+  // everything the conversion holds at once: the resident arrays and the
+  // CSR staging (released after the conversion)
+  auto rounded = [](size_t b) { return (std::max<size_t>(b, 1) + kAlign - 1) / kAlign * kAlign; };
+  const size_t need = rounded(sizeof(argcsr_group_info) * size_t(A.n_groups)) +
+                      rounded(sizeof(int32_t) * size_t(q.n_rows)) +
+                      rounded(sizeof(int32_t) * size_t(A.n_slots)) +
+                      rounded(sizeof(double) * size_t(A.n_slots)) +
+                      rounded(sizeof(float) * size_t(A.n_slots)) +
+                      rounded(sizeof(int32_t) * size_t(std::max(A.n_heavy, 1))) +
+                      rounded(sizeof(int32_t) * size_t(q.n_rows + 1)) +
+                      rounded(sizeof(int32_t) * size_t(std::max<int64_t>(nnz, 1))) +
+                      rounded(sizeof(double) * size_t(std::max<int64_t>(nnz, 1)));
+  if (need > s->arena.capacity())
+    return fail(ARGCSR_EBUDGET, "matrix %lld needs %zu bytes; the budget is %zu",
+                (long long)q.matrix_id, need, s->arena.capacity());
+  // not enough room even after evicting every unpinned matrix: wait for
+  // running requests to end, if any are running
+  if (s->arena.capacity() - s->arena.in_use() + evictable_bytes(s, q.matrix_id) < need &&
+      memory_will_free(s))
+    return kAdmitWait;
   std::vector<size_t> sizes;
   auto grab = [&](size_t bytes) -> void* {
     void* p = alloc_evicting(s, bytes, q.matrix_id);
@@ -310,6 +379,7 @@ int admit(argcsr_server* s, Request* r) {
   if (m->blocks.size() != resident_blocks + 3 || !A.groups || !A.threads_mapping || !A.columns ||
       !A.values || !m->values32 || !A.heavy_groups) {
     give_back();
+    if (memory_will_free(s)) return kAdmitWait;     // fragmented: retry after requests end
     return fail(ARGCSR_EBUDGET, "matrix %lld (%lld slots) does not fit the %zu-byte budget",
                 (long long)q.matrix_id, (long long)A.n_slots, s->arena.capacity());
   }
@@ -773,13 +843,19 @@ void scheduler(argcsr_server* s) {
       }
     }
     // admissions and new requests, in submission order
+    bool admit_waiting = false;
     while (!s->pending.empty()) {
       Request* r = s->pending.front();
       if (r->q.kind == ARGCSR_REQ_ADMIT) {
-        s->pending.pop_front();
-        r->res.t_start_ns = now_ns();
+        if (r->res.t_start_ns == 0) r->res.t_start_ns = now_ns();
         const bool was_resident = s->resident.count(r->q.matrix_id) != 0;
-        r->res.status = admit(s, r);
+        const int rc = admit(s, r);
+        if (rc == kAdmitWait) {                 // requests behind it wait too (in order)
+          admit_waiting = true;
+          break;
+        }
+        s->pending.pop_front();
+        r->res.status = rc;
         r->res.iterations = (r->res.status == ARGCSR_OK && !was_resident) ? 1 : 0;
         publish(s, r);
         delete r;
@@ -788,8 +864,7 @@ void scheduler(argcsr_server* s) {
       if (r->q.kind == ARGCSR_REQ_EVICT) {
         s->pending.pop_front();
         auto it = s->resident.find(r->q.matrix_id);
-        bool used = false;
-        for (Request* a : s->active) used |= it != s->resident.end() && a->mat == it->second.get();
+        const bool used = it != s->resident.end() && pinned(s, it->second.get());
         if (it == s->resident.end()) r->res.status = ARGCSR_ENOTFOUND;
         else if (used || !matrix_idle(s, r->q.matrix_id)) r->res.status = ARGCSR_EBUSY;
         else {
@@ -804,7 +879,7 @@ void scheduler(argcsr_server* s) {
       if (s->free_slots.empty()) break;           // wait for a slot
       const int rc = activate(s, r);
       if (rc == ARGCSR_EBUSY) {
-        if (!s->active.empty()) break;            // memory frees up as requests finish
+        if (memory_will_free(s)) break;           // memory frees up as requests finish
         r->res.status = fail(ARGCSR_EBUDGET, "request does not fit the budget");
       } else if (rc != ARGCSR_OK) {
         r->res.status = rc;
@@ -843,6 +918,11 @@ void scheduler(argcsr_server* s) {
       }
       s->staging[i] = s->staging.back();
       s->staging.pop_back();
+    }
+    if (admit_waiting && s->active.empty()) {
+      // only input copies are in flight: give the copy helper a moment
+      std::unique_lock<std::mutex> lock(s->mu);
+      s->cv_work.wait_for(lock, std::chrono::microseconds(200));
     }
     if (!s->active.empty()) {
       const int rc = step(s);

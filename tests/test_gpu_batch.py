@@ -123,3 +123,29 @@ def test_autotune_times_finalists(ac):
     M = ac.convert(dev, r["block_dim"], r["desired_chunk_size"], fmt=r["format"])
     y = ac.spmv(M, torch.from_numpy(x).to(DEV)).cpu().numpy()
     check_f64(A, x, y)
+
+
+def test_full_batch_of_256_as_benchmarked(ac):
+    """The 256-matrix batch the benchmark times (FP32, (T, D, format) chosen
+    per matrix by the autotuner with 3 timed finalists, one hipGraph replay):
+    every member within the FP32 bound of the oracle and bitwise equal to its
+    own single launch."""
+    print("\n[gpu] full batch of 256", flush=True)
+    mats = synth.workload_batch(256)
+    conv = []
+    for A, x in mats:
+        d = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+        r = ac.autotune(d, ac.F32, n_finalists=3)
+        M = ac.convert(d, r["block_dim"], r["desired_chunk_size"], ac.F32, fmt=r["format"])
+        conv.append((M, torch.from_numpy(x).to(DEV, torch.float32)))
+        del d
+    ys = [torch.full((M.n_rows,), float("nan"), dtype=torch.float32, device=DEV) for M, _ in conv]
+    b = ac.Batch([M for M, _ in conv], [xd for _, xd in conv], ys)
+    b.launch(graph=True)
+    torch.cuda.synchronize()
+    print(f"[gpu] batch info {b.info()}", flush=True)
+    for (A, x), (M, xd), y in zip(mats, conv, ys):
+        single = ac.spmv(M, xd)
+        assert torch.equal(y.view(torch.int32), single.view(torch.int32))
+        check_reduced(A, x, y.cpu().numpy().astype(np.float64), oracle.F32)
+    b.close()

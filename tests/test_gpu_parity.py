@@ -599,21 +599,23 @@ def test_full_stencil_row_grouped(ac, stencil_full):
     torch.cuda.empty_cache()
 
 
-def test_full_powerlaw_f32(ac, powerlaw_full):
+@pytest.mark.parametrize("T", [64, 128])
+def test_full_powerlaw_f32(ac, powerlaw_full, T):
     A, x = powerlaw_full
-    dev, M, ref = compare_conversion(ac, A, 64, 1, oracle.F32)
+    dev, M, ref = compare_conversion(ac, A, T, 1, oracle.F32)
     acc, tot = check_reduced(A, x, gpu_spmv(ac, M, x.astype(np.float32)), oracle.F32)
-    announce(f"powerlaw FP32: accumulation err {acc:.2e}, total {tot:.2e}")
+    announce(f"powerlaw FP32 T={T}: accumulation err {acc:.2e}, total {tot:.2e}")
 
 
-def test_full_stencil_all_dtypes(ac, stencil_full):
+@pytest.mark.parametrize("T", [64, 128])
+def test_full_stencil_all_dtypes(ac, stencil_full, T):
     A, x = stencil_full
-    dev, M, ref = compare_conversion(ac, A, 64, 27, oracle.F64)
+    dev, M, ref = compare_conversion(ac, A, T, 27, oracle.F64)
     check_f64(A, x, gpu_spmv(ac, M, x))
     del M, ref
     for dtype in (1, 2, 3):
-        M = ac.convert(dev, 64, 27, dtype)
+        M = ac.convert(dev, T, 27, dtype)
         acc, tot = check_reduced(A, x, gpu_spmv(ac, M, x.astype(np.float32)), dtype)
-        announce(f"stencil dtype={dtype}: accumulation err {acc:.2e}, total {tot:.2e}")
+        announce(f"stencil T={T} dtype={dtype}: accumulation err {acc:.2e}, total {tot:.2e}")
         del M
     torch.cuda.empty_cache()

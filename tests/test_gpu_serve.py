@@ -276,3 +276,91 @@ def test_serve_budget_eviction_and_errors(srv_mod):
             srv.poll(123456789)
     with pytest.raises(_lib.ArgCsrError):
         srv_mod.Server(budget_bytes=1 << 20, max_active=0)
+
+
+def test_serve_admissions_wait_under_memory_pressure(srv_mod):
+    """A budget that holds about two of the eight matrices: every request is
+    preceded by its ADMIT (a no-op when resident), admissions evict matrices
+    that no running request uses and wait while running requests hold the
+    memory, and every request completes, oracle-checked."""
+    print("\n[gpu] serve memory pressure", flush=True)
+    mats = pool(8, 1e4, 3e4)
+    reqs = make_requests(mats, 40, 21)
+    with srv_mod.Server(budget_bytes=16 << 20, max_active=4) as srv:
+        tickets = []
+        for kind, m, inp in reqs:
+            A = mats[m]
+            ta = srv.admit(m, A.rp, A.col, A.val, A.n_cols)
+            if kind == "spmv":
+                t, out = srv.spmv(m, inp, A.n_rows)
+            else:
+                t, out = srv.cg(m, inp)
+            tickets.append((ta, t, out))
+        for (kind, m, inp), (ta, t, out) in zip(reqs, tickets):
+            ra, r = srv.wait(ta, 120.0), srv.wait(t, 120.0)
+            assert ra["status"] == 0 and r["status"] == 0, (ra, r)
+            if kind == "spmv":
+                assert spmv_ok(mats[m], inp, out)
+            else:
+                assert true_relres(mats[m], out, inp) <= 1e-10
+        st = srv.stats()
+        assert st["failed"] == 0 and st["completed"] == len(reqs)
+        assert st["evictions"] > 0 and st["resident_bytes"] <= 16 << 20
+
+
+def test_serve_rejects_wrong_vector_lengths(srv_mod):
+    """SPMV and CG requests state the lengths of their buffers; a request
+    whose lengths are not the resident matrix's fails with EINVAL."""
+    import ctypes
+    from paper_1203_5737_amd import _lib
+    mats = pool(1)
+    A = mats[0]
+    with srv_mod.Server(budget_bytes=1 << 28, max_active=2) as srv:
+        admit_all(srv, mats)
+        t, _ = srv.spmv(0, np.zeros(A.n_cols + 1, np.float32), A.n_rows)
+        assert srv.wait(t)["status"] == _lib.EINVAL
+        t, _ = srv.spmv(0, np.zeros(A.n_cols, np.float32), A.n_rows - 1)
+        assert srv.wait(t)["status"] == _lib.EINVAL
+        t, _ = srv.cg(0, np.ones(A.n_rows - 3))
+        assert srv.wait(t)["status"] == _lib.EINVAL
+        # a request without lengths (as before they were required) is refused too
+        x = np.zeros(A.n_cols, np.float32)
+        y = np.zeros(A.n_rows, np.float32)
+        req = _lib.Request(_lib.REQ_SPMV, 0, 0, 0, None, None, None,
+                           x.ctypes.data_as(ctypes.c_void_p), y.ctypes.data_as(ctypes.c_void_p))
+        tk = ctypes.c_uint64(0)
+        _lib.check(_lib.lib().argcsr_server_submit(srv._h, ctypes.byref(req), ctypes.byref(tk)),
+                   "submit")
+        assert srv.wait(tk.value)["status"] == _lib.EINVAL
+        t, y = srv.spmv(0, np.ones(A.n_cols, np.float32), A.n_rows)
+        assert srv.wait(t)["status"] == 0 and spmv_ok(A, np.ones(A.n_cols, np.float32), y)
+
+
+def test_serve_large_matrices_alone_and_in_mix(srv_mod):
+    """Matrices above 524 288 rows (the CG kernels' per-request tile sums
+    then take more than one pass of 256 tiles), as in the serving benchmark:
+    SpMV within the FP32 bound, CG to a true 1e-10 residual with the FP64
+    oracle, and each result bitwise the same alone and in the mix."""
+    print("\n[gpu] serve large matrices", flush=True)
+    rng = np.random.default_rng(31)
+    mats = [synth.shifted_laplacian("2d", 700_000, np.random.default_rng(32)),
+            synth.shifted_laplacian("3d", 614_125, np.random.default_rng(33)),
+            synth.serve_pool_matrix(5, 1e4, 3e4)[0]]
+    assert mats[0].n_rows > 524_288 and mats[1].n_rows > 524_288
+    reqs = []
+    for m in (0, 1, 2, 0, 1):
+        reqs.append(("spmv", m, rng.uniform(-1, 1, mats[m].n_cols).astype(np.float32)))
+        reqs.append(("cg", m, rng.uniform(-1, 1, mats[m].n_rows)))
+    outs = []
+    for max_active in (16, 1):
+        with srv_mod.Server(budget_bytes=2 << 30, max_active=max_active) as srv:
+            admit_all(srv, mats)
+            out, res = run_requests(srv, mats, reqs)
+        outs.append(out)
+        for (kind, m, inp), o, r in zip(reqs, out, res):
+            if kind == "spmv":
+                assert spmv_ok(mats[m], inp, o), m
+            else:
+                assert r["relres"] <= 1e-10 and true_relres(mats[m], o, inp) <= 1e-10, m
+    for a, b in zip(*outs):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
