@@ -1,7 +1,8 @@
 """ARG-CSR SpMV benchmark on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload powerlaw|stencil27|laplace64]
+    python bench.py [--steps K] [--warmup W] [--workload powerlaw|stencil27|laplace64|mixed|batch|serve]
                     [--dtype f64|f32|bf16|f16] [--block-dim T] [--desired-chunk-size D]
+                    [--legs stencil27,batch,serve,ceilings | none]
                     [--warm] [--no-cpu-baseline] [--no-extras]
 
 A step is one y = A x in ARG-CSR (argcsr_spmv) on a matrix converted once
@@ -9,11 +10,18 @@ beforehand (conversion time is reported separately).  Inputs are resident in
 HBM when timing starts.  By default every step is preceded by a 1 GiB
 read-modify-write "flush" (not timed) so that neither the L2s nor the 256 MB
 Infinity Cache hold the matrix: the figure is HBM bandwidth, not cache
-bandwidth.  Each SpMV launch is bracketed by HIP events on the stream it is
+bandwidth.  Each launch is bracketed by HIP events on the stream it is
 launched on; `value` is algorithmic bytes / mean launch time.
 
 Algorithmic bytes per SpMV (the same for every format, so a GB/s ratio is a
 speed-up):  nnz*(s_v + 4) + n_rows*(4 + s_y) + n_cols*s_x.
+
+The default run (power-law workload) also carries, as sub-objects of its one
+JSON line: the 27-point stencil in FP64/FP32/BF16/FP16 (`stencil27`), the
+256-matrix batch in one hipGraph replay (`batch`), the request server under
+Poisson arrivals with p50/p99 latency (`serve`), and measured ceilings of the
+box (`ceilings`: the flush's copy bandwidth, a streaming read of the
+matrix's format bytes, and the random gathers of its column stream).
 
 Prints ONE JSON line.
 """
@@ -33,7 +41,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ARG-CSR SpMV GB/s (% HBM peak) vs plain CSR; served p50/p99 latency"
 HBM_PEAK_GBPS = 8000.0
+FLUSH_BYTES = 1 << 30
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_amd/csrc/spmv.hip",
                   "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp",
@@ -42,6 +52,12 @@ KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_
 DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (128, 27), "laplace64": (64, 1),
                   "mixed": (64, 1)}
 DEFAULT_REGION_ROWS = {"mixed": 4096}
+ALL_LEGS = ("stencil27", "batch", "serve", "ceilings")
+
+
+def log(msg: str) -> None:
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -86,21 +102,27 @@ def format_bytes(M, dtype: int) -> int:
 
 class Timer:
     """Times `fn` launches with HIP events on the current stream, optionally
-    evicting the caches (1 GiB read-modify-write) before each launch."""
+    evicting the caches (1 GiB read-modify-write) before each launch.  The
+    flushes themselves are timed too: their bandwidth (1 GiB read + 1 GiB
+    written) is the copy ceiling of the box."""
 
     def __init__(self, torch, cold: bool):
         self.torch = torch
         self.cold = cold
-        self.flush_buf = torch.empty(1 << 28, dtype=torch.float32, device="cuda") if cold else None
+        self.flush_buf = (torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+                          if cold else None)
+        self.flush_ms = []
 
     def run(self, fn, steps: int):
         torch = self.torch
-        starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-        ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        starts, ends = [ev() for _ in range(steps)], [ev() for _ in range(steps)]
+        fstarts = [ev() for _ in range(steps)] if self.cold else []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
             if self.cold:
+                fstarts[i].record()
                 self.flush_buf.add_(1.0)
             starts[i].record()
             fn()
@@ -108,7 +130,17 @@ class Timer:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+        if self.cold:
+            self.flush_ms += [f.elapsed_time(s) for f, s in zip(fstarts, starts)]
         return ms, wall
+
+    def copy_ceiling(self):
+        if not self.flush_ms:
+            return None
+        ms = float(np.median(self.flush_ms))
+        return {"gbps": 2 * FLUSH_BYTES / (ms * 1e-3) / 1e9, "median_ms": ms,
+                "n": len(self.flush_ms),
+                "what": "1 GiB read + 1 GiB written by the untimed flush (torch add_), HIP events"}
 
 
 def stats(ms):
@@ -142,57 +174,40 @@ def cpu_convert(A, T, D, region_rows, regions, budget_s: float = 6.0):
     return float(np.median(ts)) * 1e3, len(ts)
 
 
-def cpu_baseline(A, x, B_useful, budget_s: float = 12.0):
+def cpu_baseline(A, x, B_useful, budget_s: float = 16.0):
     """The FP64 CSR oracle on this host's cores (OpenMP row split; identical
-    result to the sequential oracle), on a bounded number of full SpMVs."""
+    result to the sequential oracle): the median of at least 5 reps, each a
+    batch of full SpMVs, within about `budget_s` seconds; then the same
+    single-threaded, as in the paper's sequential baseline."""
     import oracle
     threads = os.cpu_count() or 1
-    y = oracle.csr_spmv(A.rp, A.col, A.val, x, threads)       # warm-up
+    oracle.csr_spmv(A.rp, A.col, A.val, x, threads)           # warm-up
     t0 = time.perf_counter()
     oracle.csr_spmv(A.rp, A.col, A.val, x, threads)
     one = max(time.perf_counter() - t0, 1e-6)
-    reps = int(max(3, min(100_000, (budget_s * 0.6) / one)))
-    t0 = time.perf_counter()
+    reps = 7
+    per_rep = int(max(1, min(20_000, budget_s * 0.6 / reps / one)))
+    rep_ms = []
     for _ in range(reps):
-        oracle.csr_spmv(A.rp, A.col, A.val, x, threads)
-    mt = (time.perf_counter() - t0) / reps
-    t0 = time.perf_counter()
-    st_reps = max(1, min(reps, int((budget_s * 0.4) / max(one * threads, 1e-6))))
-    for _ in range(st_reps):
+        t0 = time.perf_counter()
+        for _ in range(per_rep):
+            oracle.csr_spmv(A.rp, A.col, A.val, x, threads)
+        rep_ms.append((time.perf_counter() - t0) / per_rep * 1e3)
+    mt = float(np.median(rep_ms))
+    st_ms = []
+    for _ in range(5):
+        t0 = time.perf_counter()
         oracle.csr_spmv(A.rp, A.col, A.val, x, 1)
-    st = (time.perf_counter() - t0) / st_reps
-    del y
-    return {"value": B_useful / mt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"full matrix, {reps} SpMVs on {threads} threads (OpenMP row split) "
-                      f"+ {st_reps} single-threaded",
-            "ms_per_spmv": mt * 1e3, "single_thread_gbps": B_useful / st / 1e9,
-            "single_thread_ms": st * 1e3, "cpu_model": cpu_model()}
-
-
-def f32_variant(A, x, dev, timer, torch, ac, steps):
-    """The same matrix with FP32 values, x and y (T=128, D=1), against plain
-    CSR in FP32, timed the same way."""
-    B = useful_bytes(A, 1)
-    M = ac.convert(dev, 128, 1, 1)
-    xd = torch.from_numpy(x).to("cuda", torch.float32)
-    yd = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
-    f = lambda: ac.spmv(M, xd, yd)
-    timer.run(f, 5)
-    t, _ = timer.run(f, steps)
-    vals = dev.val.to(torch.float32)
-    best = None
-    for V in (8, 16, 32, 64):
-        g = lambda V=V: ac.csr_spmv(dev, xd, yd, values=vals, dtype=1, lanes_per_row=V)
-        timer.run(g, 3)
-        c, _ = timer.run(g, max(10, steps // 5))
-        if best is None or c.mean() < best[1].mean():
-            best = (V, c)
-    ac.spmv(M, xd, yd)
-    err = error_vs_fp64(A, x, yd.cpu().numpy())
-    return {"block_dim": 128, "desired_chunk_size": 1, "mean_ms": float(t.mean()),
-            "gbps": B / (t.mean() * 1e-3) / 1e9, "csr_gbps": B / (best[1].mean() * 1e-3) / 1e9,
-            "csr_lanes_per_row": best[0], "speedup_vs_csr": float(best[1].mean() / t.mean()),
-            "error_vs_fp64": err}
+        st_ms.append((time.perf_counter() - t0) * 1e3)
+        if sum(st_ms) > budget_s * 400:                        # 40% of the budget, in ms
+            break
+    st = float(np.median(st_ms))
+    return {"value": B_useful / (mt * 1e-3) / 1e9, "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full matrix; median of {reps} reps of {per_rep} SpMVs on {threads} threads "
+                      f"(OpenMP row split), and median of {len(st_ms)} single-threaded SpMVs",
+            "ms_per_spmv": mt, "rep_ms": rep_ms, "single_thread_gbps": B_useful / (st * 1e-3) / 1e9,
+            "single_thread_ms": st, "cpu_model": cpu_model()}
 
 
 def error_vs_fp64(A, x, y):
@@ -226,14 +241,88 @@ def traffic_for(workload: str, dtype_name: str, T: int, D: int):
     return None
 
 
-def run_batch(args, torch, ac):
-    """256 matrices (n log-uniform in [1e3, 2e5], half U{5..50} nonzeros per
-    row, half clip(Zipf(2.2), 1, min(5000, n))), FP32 values, (T, D)
-    autotuned per matrix; a step is ONE replay of the batch's hipGraph
-    (queue reset + persistent kernel over all matrices' groups)."""
+def best_csr(ac, timer, dev, xd, yd, vals, dtype, steps, lanes=(0, 1, 2, 4, 8, 16, 32, 64)):
+    """Plain CSR on the same GPU with the best lanes-per-row of a sweep."""
+    best = None
+    for V in lanes:
+        f = lambda V=V: ac.csr_spmv(dev, xd, yd, values=vals, dtype=dtype, lanes_per_row=V)
+        timer.run(f, 3)
+        t, _ = timer.run(f, max(10, steps // 5))
+        if best is None or t.mean() < best[1].mean():
+            best = (V, t)
+    V, _ = best
+    f = lambda: ac.csr_spmv(dev, xd, yd, values=vals, dtype=dtype, lanes_per_row=V)
+    t, _ = timer.run(f, steps)
+    return V, t
+
+
+def f32_variant(A, x, dev, timer, torch, ac, steps):
+    """The same matrix with FP32 values, x and y (T=128, D=1), against plain
+    CSR in FP32, timed the same way."""
+    B = useful_bytes(A, 1)
+    M = ac.convert(dev, 128, 1, 1)
+    xd = torch.from_numpy(x).to("cuda", torch.float32)
+    yd = torch.empty(A.n_rows, dtype=torch.float32, device="cuda")
+    f = lambda: ac.spmv(M, xd, yd)
+    timer.run(f, 5)
+    t, _ = timer.run(f, steps)
+    vals = dev.val.to(torch.float32)
+    V, c = best_csr(ac, timer, dev, xd, yd, vals, 1, max(10, steps // 2), (8, 16, 32, 64))
+    ac.spmv(M, xd, yd)
+    err = error_vs_fp64(A, x, yd.cpu().numpy())
+    gbps = B / (t.mean() * 1e-3) / 1e9
+    return {"block_dim": 128, "desired_chunk_size": 1, "mean_ms": float(t.mean()),
+            "gbps": gbps, "frac": gbps / HBM_PEAK_GBPS,
+            "csr_gbps": B / (c.mean() * 1e-3) / 1e9,
+            "csr_lanes_per_row": V, "speedup_vs_csr": float(c.mean() / t.mean()),
+            "error_vs_fp64": err}
+
+
+# ---------------------------------------------------------------------------
+# legs of the default run
+# ---------------------------------------------------------------------------
+
+def leg_stencil27(torch, ac, timer, steps):
+    """27-point stencil 128^3 (T=128, D=27) in every value type, cold, with
+    the error against FP64 and plain CSR (FP64) beside it."""
+    A, x, desc = load_workload("stencil27")
+    T, D = DEFAULT_PARAMS["stencil27"]
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")
+    out = {"workload": desc, "n_rows": A.n_rows, "nnz": A.nnz, "block_dim": T,
+           "desired_chunk_size": D, "steps": steps}
+    for name, dtype in DTYPES.items():
+        log(f"stencil27 {name}")
+        M = ac.convert(dev, T, D, dtype)
+        vdt = ac.vector_dtype(dtype)
+        xd = torch.from_numpy(x).to("cuda", vdt)
+        yd = torch.empty(A.n_rows, dtype=vdt, device="cuda")
+        f = lambda: ac.spmv(M, xd, yd)
+        timer.run(f, 3)
+        t, _ = timer.run(f, steps)
+        B = useful_bytes(A, dtype)
+        gbps = B / (t.mean() * 1e-3) / 1e9
+        rec = stats(t) | {"gbps": gbps, "frac": gbps / HBM_PEAK_GBPS, "useful_bytes": B,
+                          "padding_ratio": M.n_slots / A.nnz,
+                          "traffic": traffic_for("stencil27", name, T, D),
+                          "error_vs_fp64": error_vs_fp64(A, x, yd.cpu().numpy())}
+        if dtype == 0:
+            V, c = best_csr(ac, timer, dev, xd, yd, dev.val, 0, steps, (4, 8, 16, 32))
+            rec["csr_gbps"] = B / (c.mean() * 1e-3) / 1e9
+            rec["csr_lanes_per_row"] = V
+            rec["speedup_vs_csr"] = float(c.mean() / t.mean())
+        out[name] = rec
+        del M, xd, yd
+    del dev
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_record(torch, ac, count, dtype, steps, warmup, cold=True, extras=True):
+    """`count` matrices (n log-uniform in [1e3, 2e5], half U{5..50} nonzeros
+    per row, half clip(Zipf(2.2), 1, min(5000, n))), (T, D, format) autotuned
+    per matrix; a step is ONE replay of the batch's hipGraph (queue reset +
+    persistent kernel over all matrices' groups)."""
     import synth
-    dtype = DTYPES[args.dtype]
-    count = args.batch_count
     mats = synth.workload_batch(count)
     vdt = ac.vector_dtype(dtype)
     devs, Ms, xs, ys, tunes = [], [], [], [], []
@@ -247,130 +336,239 @@ def run_batch(args, torch, ac):
         xs.append(torch.from_numpy(x).to("cuda", vdt))
         ys.append(torch.empty(A.n_rows, dtype=vdt, device="cuda"))
     setup_s = time.perf_counter() - t0
+    log(f"batch: {count} matrices tuned and converted in {setup_s:.1f} s")
     B = sum(useful_bytes(A, dtype) for A, _ in mats)
     nnz = sum(A.nnz for A, _ in mats)
     batch = ac.Batch(Ms, xs, ys)
-    timer = Timer(torch, cold=not args.warm)
+    timer = Timer(torch, cold=cold)
     run = lambda: batch.launch(graph=True)
-    timer.run(run, args.warmup)
-    ms, wall = timer.run(run, args.steps)
-    mean_s = ms.mean() * 1e-3
-    gbps = B / mean_s / 1e9
-    out = {
-        "metric": METRIC, "value": round(gbps, 2), "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": float(ms.mean()),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": f"batch of {count} matrices, n log-uniform [1e3,2e5], half U{{5..50}} "
-                               "nnz/row, half clip(Zipf(2.2),1,min(5000,n)); one hipGraph replay "
-                               "per step", "n_rows": sum(A.n_rows for A, _ in mats), "nnz": nnz,
-                   "value_dtype": args.dtype,
-                   "timing": "warm" if args.warm else "cold (1 GiB flush before each step, untimed)"},
-        "roofline": {"bound": "hbm", "achieved": round(gbps, 2), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None},
-        "spmv": stats(ms) | {"gflops": 2 * nnz / mean_s / 1e9, "useful_bytes": B,
-                             "wall_ms_per_step": wall * 1e3 / args.steps} | batch.info(),
-        "setup_s": setup_s,
-        "tuned": {(f"T{T}/RG" if fm else f"T{T}/D{D}"): sum(1 for t in tunes
-                                                          if (t[0], t[1], t[3]) == (T, D, fm))
-                  for T, D, fm in sorted({(t[0], t[1], t[3]) for t in tunes})},
-        "kernel_hash": kernel_source_hash(),
-    }
-    if not args.no_extras:
+    timer.run(run, warmup)
+    ms, wall = timer.run(run, steps)
+    gbps = B / (ms.mean() * 1e-3) / 1e9
+    # every member against y = A x in FP64 (numpy), after the last replay
+    errs = [error_vs_fp64(A, x, y.cpu().numpy()) for (A, x), y in zip(mats, ys)]
+    rec = {"workload": f"batch of {count} matrices, n log-uniform [1e3,2e5], half U{{5..50}} "
+                       "nnz/row, half clip(Zipf(2.2),1,min(5000,n)); one hipGraph replay per step",
+           "n_mats": count, "n_rows": sum(A.n_rows for A, _ in mats), "nnz": nnz,
+           "value_dtype": DTYPE_NAMES[dtype], "useful_bytes": B, "gbps": gbps,
+           "frac": gbps / HBM_PEAK_GBPS, "steps": steps,
+           "spmv": stats(ms) | {"gflops": 2 * nnz / (ms.mean() * 1e-3) / 1e9,
+                                "wall_ms_per_step": wall * 1e3 / steps} | batch.info(),
+           "error_vs_fp64": {"max_scaled": max(e["max_scaled"] for e in errs),
+                             "max_rel_l2": max(e["rel_l2"] for e in errs),
+                             "zero_rows_exact": all(e["zero_rows_exact"] for e in errs)},
+           "setup_s": setup_s,
+           "tuned": {(f"T{T}/RG" if fm else f"T{T}/D{D}"): sum(1 for t in tunes
+                                                             if (t[0], t[1], t[3]) == (T, D, fm))
+                     for T, D, fm in sorted({(t[0], t[1], t[3]) for t in tunes})}}
+    if extras:
         loop = lambda: [ac.spmv(M, x, y) for M, x, y in zip(Ms, xs, ys)]
         timer.run(loop, 2)
-        t, _ = timer.run(loop, max(5, args.steps // 4))
-        out["single_launch_loop"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
-        direct = lambda: batch.launch(graph=False)
-        t, _ = timer.run(direct, max(5, args.steps // 4))
-        out["batch_direct_launch"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
+        t, _ = timer.run(loop, max(5, steps // 4))
+        rec["single_launch_loop"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
         vals = [d.val.to(ac.storage_dtype(dtype)) if dtype != 0 else d.val for d in devs]
-        csr = lambda: [ac.csr_spmv(d, x, y, values=v, dtype=dtype) for d, x, y, v in zip(devs, xs, ys, vals)]
+        csr = lambda: [ac.csr_spmv(d, x, y, values=v, dtype=dtype)
+                       for d, x, y, v in zip(devs, xs, ys, vals)]
         timer.run(csr, 2)
-        t, _ = timer.run(csr, max(5, args.steps // 4))
-        out["csr_loop"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
-        out["speedup_vs_csr_loop"] = out["csr_loop"]["mean_ms"] / float(ms.mean())
+        t, _ = timer.run(csr, max(5, steps // 4))
+        rec["csr_loop"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
+        rec["speedup_vs_csr_loop"] = rec["csr_loop"]["mean_ms"] / float(ms.mean())
     batch.close()
-    print(json.dumps(out))
+    del Ms, devs, xs, ys
+    torch.cuda.empty_cache()
+    return rec
 
 
-def run_serve(args, torch, ac):
-    """Open-loop serving: Poisson arrivals at --rate req/s of SpMV and CG
-    requests (50/50) on a pool of SPD shifted 2D/3D Laplacians with n
-    log-uniform in [1e4, 1e6]; request matrix ~ Zipf(1.1) over the pool.
-    Latency runs from the scheduled arrival to the result in host memory."""
-    import threading
+def serve_record(ac, pool_size, n_requests, n_warm, rate, budget_gb, budget_frac, max_active,
+                 cg_inner_per_step, n_check=16):
+    """Open-loop serving: Poisson arrivals at `rate` req/s of SpMV and CG
+    requests (50/50) on SPD shifted 2D/3D Laplacians with n log-uniform in
+    [1e4, 1e6]; request matrix ~ Zipf(1.1) over a pool of `pool_size`
+    matrices, each generated from its own seed (only the ones the request
+    sequence names).  Every request is submitted as ADMIT (a no-op when the
+    matrix is resident) followed by the SpMV or CG.  The device budget is
+    `budget_gb`, or, when that is 0, `budget_frac` of the device footprint of
+    the matrices the run uses, so that admissions have to evict.  Latency runs
+    from the scheduled arrival to the result in host memory; a failed request
+    counts as infinitely late."""
+    from concurrent.futures import ThreadPoolExecutor
     import synth
     from paper_1203_5737_amd import serve
     rng = np.random.default_rng(np.random.SeedSequence([12035737, 4, 999999]))
-    P = args.pool
-    pool = [synth.serve_pool_matrix(i)[0] for i in range(P)]
+    P = pool_size
     zipf_w = 1.0 / np.arange(1, P + 1) ** 1.1
     zipf_w /= zipf_w.sum()
-    n_req = args.requests + args.warm_requests
+    n_req = n_requests + n_warm
     mats = rng.choice(P, size=n_req, p=zipf_w)
     kinds = rng.random(n_req) < 0.5                      # True: CG
-    gaps = rng.exponential(1.0 / args.rate, n_req)
+    gaps = rng.exponential(1.0 / rate, n_req)
+    used = sorted(set(int(m) for m in mats))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(8) as ex:
+        pool = dict(zip(used, ex.map(lambda i: synth.serve_pool_matrix(i)[0], used)))
+    gen_s = time.perf_counter() - t0
+    log(f"serve: {len(used)} matrices generated in {gen_s:.1f} s")
     inputs = [rng.uniform(-1, 1, pool[m].n_rows) if cg else
               rng.uniform(-1, 1, pool[m].n_cols).astype(np.float32)
               for m, cg in zip(mats, kinds)]
-    srv = serve.Server(budget_bytes=int(args.budget_gb * (1 << 30)), max_active=args.max_active,
-                       cg_tol=1e-10, cg_inner_per_step=args.cg_inner_per_step)
+    # device footprint of a resident matrix: groups, mapping, columns, FP64
+    # and FP32 values, heavy list (the server's layout)
+    T = 64
+    foot = 0
+    for m in used:
+        A = pool[m]
+        D = int(min(64, max(1, round(A.nnz / max(A.n_rows, 1)))))
+        G, S, H = ac.plan(A.rp, T, D)
+        foot += 16 * G + 4 * A.n_rows + 16 * S + 4 * max(H, 1)
+    budget = int(budget_gb * (1 << 30)) if budget_gb > 0 else int(budget_frac * foot)
+    srv = serve.Server(budget_bytes=budget, max_active=max_active, cg_tol=1e-10,
+                       cg_inner_per_step=cg_inner_per_step)
     records = []
-    t0 = time.monotonic_ns() + 50_000_000
-    arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
+    tstart = time.monotonic_ns() + 50_000_000
+    arrivals = tstart + np.cumsum(gaps * 1e9).astype(np.int64)
     for k in range(n_req):
         while time.monotonic_ns() < arrivals[k]:
             pass
         m = int(mats[k])
         A = pool[m]
-        # ADMIT is a no-op for a resident matrix; it converts the matrix again
-        # after an eviction.  Its result says whether it converted (cold).
         ta = srv.admit(m, A.rp, A.col, A.val, A.n_cols)
         if kinds[k]:
-            t, _ = srv.cg(m, inputs[k])
+            t, out = srv.cg(m, inputs[k])
         else:
-            t, _ = srv.spmv(m, inputs[k], pool[m].n_rows)
-        records.append((t, ta, int(arrivals[k]), bool(kinds[k]), m))
+            t, out = srv.spmv(m, inputs[k], A.n_rows)
+        records.append((t, ta, int(arrivals[k]), bool(kinds[k]), m, out))
+    log(f"serve: {n_req} requests submitted")
     results = []
-    for t, ta, arr, cg, m in records:
+    for t, ta, arr, cg, m, out in records:
         r = srv.wait(t, 600.0)
-        cold = srv.wait(ta, 600.0)["iterations"] == 1
+        ra = srv.wait(ta, 600.0)
+        cold = ra["status"] == 0 and ra["iterations"] == 1
         srv.release(ta)
-        results.append((r, arr, cold, cg, m))
-    wall = (max(r["t_done_ns"] for r, *_ in results) - t0) * 1e-9
-    stats = srv.stats()
+        results.append((r, arr, cold, cg, m, out))
+    wall = (max(r["t_done_ns"] for r, *_ in results) - tstart) * 1e-9
+    st = srv.stats()
     srv.close()
-    meas = results[args.warm_requests:]
-    ok = [x for x in meas if x[0]["status"] == 0]
-    lat = lambda xs: np.array([(r["t_done_ns"] - arr) * 1e-6 for r, arr, *_ in xs])
+    meas = results[n_warm:]
+
+    def lat(xs):
+        return np.array([(r["t_done_ns"] - arr) * 1e-6 if r["status"] == 0 else np.inf
+                         for r, arr, *_ in xs])
+
     def pct(xs):
         a = lat(xs)
         return {"n": int(a.size), "p50_ms": float(np.percentile(a, 50)) if a.size else None,
                 "p99_ms": float(np.percentile(a, 99)) if a.size else None}
-    all_lat = lat(ok)
+
+    ok_idx = [k for k in range(n_warm, n_req) if results[k][0]["status"] == 0]
+    ok = [results[k] for k in ok_idx]
+    # a sample of the results checked here with numpy (CSR definition in
+    # FP64): SpMV within the FP32 dot-product bound on the FP32-rounded
+    # values, CG by its true residual
+    check = {"spmv_checked": 0, "spmv_ok": 0, "cg_checked": 0, "cg_max_true_relres": 0.0}
+    srng = np.random.default_rng(7)
+    for k in [ok_idx[i] for i in srng.permutation(len(ok_idx))[:n_check]]:
+        r, arr, cold, cg, m, out = results[k]
+        A = pool[m]
+        rows = np.repeat(np.arange(A.n_rows), np.diff(A.rp))
+        inp = inputs[k]
+        if cg:
+            Ax = np.bincount(rows, weights=A.val * out[A.col], minlength=A.n_rows)
+            rr = float(np.linalg.norm(inp - Ax) / np.linalg.norm(inp))
+            check["cg_checked"] += 1
+            check["cg_max_true_relres"] = max(check["cg_max_true_relres"], rr)
+        else:
+            v32 = A.val.astype(np.float32).astype(np.float64)
+            xx = inp.astype(np.float64)
+            prod = v32 * xx[A.col]
+            ref = np.bincount(rows, weights=prod, minlength=A.n_rows)
+            scale = np.bincount(rows, weights=np.abs(prod), minlength=A.n_rows)
+            L = np.diff(A.rp) + 1
+            u = 2.0 ** -24
+            good = np.all(np.abs(out.astype(np.float64) - ref) <= L * u / (1 - L * u) * scale)
+            check["spmv_checked"] += 1
+            check["spmv_ok"] += int(good)
+    warm = [x for x in meas if not x[2]]
+    coldr = [x for x in meas if x[2]]
     sp_bytes = sum(useful_bytes(pool[m], 1) * (1 if not cg else max(1, r["iterations"]))
-                   for r, _, _, cg, m in ok)
-    out = {
-        "metric": METRIC, "value": float(np.percentile(all_lat, 50)), "unit": "ms (p50 latency)",
-        "n_gpus": 1, "steps": len(meas), "warmup": args.warm_requests,
-        "ms_per_step": float(all_lat.mean()), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 SpMV / f64 CG", "data": "synthetic",
-        "config": {"workload": f"serving: Poisson {args.rate:g} req/s, 50% SpMV / 50% CG to 1e-10, "
-                               f"pool of {P} SPD shifted 2D/3D Laplacians, n log-uniform [1e4,1e6], "
-                               f"Zipf(1.1) popularity, {args.budget_gb:g} GB budget",
-                   "max_active": args.max_active,
-                   "cg_inner_per_step": args.cg_inner_per_step or 2},
-        "latency": {"all": pct(ok), "p99_ms": float(np.percentile(all_lat, 99)),
-                    "warm": pct([x for x in ok if not x[2]]), "cold": pct([x for x in ok if x[2]]),
-                    "spmv": pct([x for x in ok if not x[3]]), "cg": pct([x for x in ok if x[3]])},
+                   for r, _, _, cg, m, _ in ok)
+    return {
+        "workload": f"serving: Poisson {rate:g} req/s, 50% SpMV / 50% CG to 1e-10, pool of {P} SPD "
+                    f"shifted 2D/3D Laplacians (n log-uniform [1e4,1e6], Zipf(1.1) popularity), "
+                    f"budget {budget / (1 << 30):.2f} GiB"
+                    + ("" if budget_gb > 0 else
+                       f" = {budget_frac:g} x the {foot / (1 << 30):.2f} GiB device footprint of the "
+                       f"{len(used)} matrices the requests use"),
+        "requests": n_requests, "warm_up_requests": n_warm, "max_active": max_active,
+        "cg_inner_per_step": cg_inner_per_step or 2,
+        "p50_ms": pct(meas)["p50_ms"], "p99_ms": pct(meas)["p99_ms"],
+        "latency": {"all": pct(meas), "warm": pct(warm), "cold": pct(coldr),
+                    "spmv": pct([x for x in meas if not x[3]]),
+                    "cg": pct([x for x in meas if x[3]])},
         "throughput_req_s": len(results) / wall,
         "aggregate_spmv_gbps_lower_bound": sp_bytes / wall / 1e9,
         "failed": len(meas) - len(ok),
-        "cg_max_relres": max((r["relres"] for r, _, _, cg, _ in ok if cg), default=None),
-        "cg_mean_iterations": float(np.mean([r["iterations"] for r, _, _, cg, _ in ok if cg] or [0])),
-        "server": stats,
+        "cg_max_relres": max((r["relres"] for r, _, _, cg, _, _ in ok if cg), default=None),
+        "cg_mean_iterations": float(np.mean([r["iterations"] for r, _, _, cg, _, _ in ok if cg] or [0])),
+        "check": check,
+        "pool_generation_s": gen_s, "matrices_used": len(used),
+        "footprint_bytes": foot, "budget_bytes": budget,
+        "server": st,
     }
+
+
+def leg_ceilings(torch, ac, M, dtype, timer, steps):
+    """Measured ceilings of the box for this matrix: a streaming read of its
+    format bytes (values + columns, 16-byte loads) and the random gathers of
+    its column stream alone (every column of the slots, x[column] summed,
+    no values and no row sums), both cold like the SpMV."""
+    out = {}
+    sink = torch.empty(ac.PROBE_SINK_ELEMS, dtype=torch.float64, device="cuda")
+    fb = M.n_slots * (VALUE_BYTES[dtype] + 4)
+    f = lambda: (ac.probe_read(M.values, sink), ac.probe_read(M.columns, sink))
+    timer.run(f, 3)
+    t, _ = timer.run(f, steps)
+    out["stream_read"] = {"gbps": fb / (t.mean() * 1e-3) / 1e9, "bytes": fb, **stats(t),
+                          "what": "values and columns read once, 16-byte non-temporal loads"}
+    x = torch.zeros(M.n_cols, dtype=ac.vector_dtype(dtype), device="cuda")
+    g = lambda: ac.probe_gather(M.columns, x, sink)
+    timer.run(g, 3)
+    t, _ = timer.run(g, steps)
+    n_g = M.nnz
+    out["gather"] = {"gathers_per_s": n_g / (t.mean() * 1e-3), "gathers": n_g, **stats(t),
+                     "column_bytes_gbps": 4 * M.n_slots / (t.mean() * 1e-3) / 1e9,
+                     "what": "the column stream read and x[column] gathered and summed"}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# standalone workloads
+# ---------------------------------------------------------------------------
+
+def run_batch(args, torch, ac):
+    dtype = DTYPES[args.dtype]
+    rec = batch_record(torch, ac, args.batch_count, dtype, args.steps, args.warmup,
+                       cold=not args.warm, extras=not args.no_extras)
+    out = {"metric": METRIC, "value": round(rec["gbps"], 2), "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["spmv"]["mean_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": rec["workload"], "n_rows": rec["n_rows"], "nnz": rec["nnz"],
+                      "value_dtype": args.dtype,
+                      "timing": "warm" if args.warm else "cold (1 GiB flush before each step, untimed)"},
+           "roofline": {"bound": "hbm", "achieved": round(rec["gbps"], 2), "peak": HBM_PEAK_GBPS,
+                        "unit": "GB/s", "frac": round(rec["frac"], 4), "traffic": None},
+           "batch": rec, "kernel_hash": kernel_source_hash()}
+    print(json.dumps(out))
+
+
+def run_serve(args, torch, ac):
+    rec = serve_record(ac, args.pool, args.requests, args.warm_requests, args.rate,
+                       args.budget_gb, args.budget_frac, args.max_active, args.cg_inner_per_step)
+    out = {"metric": METRIC, "value": rec["p50_ms"], "unit": "ms (p50 latency)", "n_gpus": 1,
+           "steps": args.requests, "warmup": args.warm_requests,
+           "ms_per_step": float(rec["latency"]["all"]["p50_ms"]), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 SpMV / f64 CG",
+           "data": "synthetic", "config": {"workload": rec["workload"]}, "serve": rec}
     print(json.dumps(out))
 
 
@@ -385,6 +583,9 @@ def main():
     ap.add_argument("--desired-chunk-size", type=int, default=None)
     ap.add_argument("--region-rows", type=int, default=None,
                     help="desiredChunkSize per region of this many rows (0: one D)")
+    ap.add_argument("--legs", default=",".join(ALL_LEGS),
+                    help="extra legs of the power-law run: comma list of "
+                         f"{', '.join(ALL_LEGS)}, or 'none'")
     ap.add_argument("--warm", action="store_true", help="no cache flush between steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the CSR and warm timings")
@@ -392,10 +593,13 @@ def main():
     ap.add_argument("--rate", type=float, default=1000.0, help="serve: arrivals per second")
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests")
     ap.add_argument("--warm-requests", type=int, default=200, help="serve: unmeasured first requests")
-    ap.add_argument("--pool", type=int, default=64, help="serve: distinct matrices")
+    ap.add_argument("--pool", type=int, default=512, help="serve: distinct matrices")
     ap.add_argument("--cg-inner-per-step", type=int, default=0,
                     help="serve: inner CG iterations a step may run (0 = the server's default)")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: device memory budget")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="serve: device memory budget (0: --budget-frac of the footprint used)")
+    ap.add_argument("--budget-frac", type=float, default=0.4,
+                    help="serve: budget as a fraction of the used matrices' device footprint")
     ap.add_argument("--max-active", type=int, default=64, help="serve: requests per step")
     args = ap.parse_args()
 
@@ -416,14 +620,22 @@ def main():
         if args.dtype == "f64" and "--dtype" not in sys.argv:
             args.dtype = "f32"                        # the batch workload is quoted in FP32
         return run_batch(args, torch, ac)
+    legs = [] if args.legs in ("", "none") else args.legs.split(",")
+    for leg in legs:
+        if leg not in ALL_LEGS:
+            raise SystemExit(f"unknown leg {leg}")
+    if args.workload != "powerlaw":
+        legs = [leg for leg in legs if leg == "ceilings"]
     dtype = DTYPES[args.dtype]
     T0, D0 = DEFAULT_PARAMS.get(args.workload, (64, 1))
     T = args.block_dim or T0
     D = args.desired_chunk_size or D0
 
+    log(f"{args.workload}: generating")
     A, x, desc = load_workload(args.workload)
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")
     torch.cuda.synchronize()
+    log(f"{args.workload}: n={A.n_rows} nnz={A.nnz}; converting")
     region_rows = (args.region_rows if args.region_rows is not None
                    else DEFAULT_REGION_ROWS.get(args.workload, 0))
     regions = ac.choose_region_desired(A.rp, region_rows) if region_rows else None
@@ -453,6 +665,7 @@ def main():
 
     timer = Timer(torch, cold=not args.warm)
     spmv = lambda: ac.spmv(M, xd, yd)
+    log(f"{args.workload}: timing {args.steps} SpMVs")
     timer.run(spmv, args.warmup)
     ms, wall = timer.run(spmv, args.steps)
     mean_s = ms.mean() * 1e-3
@@ -480,21 +693,13 @@ def main():
     }
 
     if not args.no_extras:
+        log("extras: warm, plain CSR, FP32, row-grouped")
         # the same SpMV without flushes (matrix may stay in the Infinity Cache)
         warm_ms, _ = Timer(torch, cold=False).run(spmv, args.steps)
         out["spmv_warm"] = stats(warm_ms) | {"gbps": B / (warm_ms.mean() * 1e-3) / 1e9}
         # plain CSR on the same GPU, same timing; best lanes-per-row of a sweep
         vals = dev.val if dtype == 0 else dev.val.to(ac.storage_dtype(dtype))
-        best = None
-        for V in (0, 1, 2, 4, 8, 16, 32, 64):
-            f = lambda V=V: ac.csr_spmv(dev, xd, yd, values=vals, dtype=dtype, lanes_per_row=V)
-            timer.run(f, 3)
-            t, _ = timer.run(f, max(10, args.steps // 5))
-            if best is None or t.mean() < best[1].mean():
-                best = (V, t)
-        V, t = best
-        f = lambda: ac.csr_spmv(dev, xd, yd, values=vals, dtype=dtype, lanes_per_row=V)
-        t, _ = timer.run(f, args.steps)
+        V, t = best_csr(ac, timer, dev, xd, yd, vals, dtype, args.steps)
         csr_gbps = B / (t.mean() * 1e-3) / 1e9
         out["csr"] = stats(t) | {"gbps": csr_gbps, "lanes_per_row": V}
         out["speedup_vs_csr"] = gbps / csr_gbps
@@ -522,12 +727,38 @@ def main():
                                          "padding_ratio": Mrg.n_slots / max(A.nnz, 1)}
         del Mrg
 
+    if "ceilings" in legs:
+        log("ceilings")
+        out["ceilings"] = leg_ceilings(torch, ac, M, dtype, timer, max(10, args.steps // 2))
+    copy = timer.copy_ceiling()
+    if copy:
+        out.setdefault("ceilings", {})["copy"] = copy
+        out["roofline"]["achievable_gbps"] = round(copy["gbps"], 1)
+        out["roofline"]["frac_of_achievable"] = round(gbps / copy["gbps"], 4)
+
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(A, x, useful_bytes(A, 0))   # the oracle is FP64
         conv_ms, conv_reps = cpu_convert(A, T, D, region_rows, regions)
         out["cpu_baseline"]["convert_ms"] = conv_ms
         out["cpu_baseline"]["convert_sample"] = (f"whole matrix, T={T} D={D}, single thread, "
                                                  f"median of {conv_reps}")
+    del M, dev, xd, yd
+    torch.cuda.empty_cache()
+
+    leg_steps = max(10, min(args.steps, 30))
+    if "stencil27" in legs:
+        log("leg: stencil27")
+        out["stencil27"] = leg_stencil27(torch, ac, Timer(torch, cold=not args.warm), leg_steps)
+    if "batch" in legs:
+        log("leg: batch")
+        out["batch"] = batch_record(torch, ac, args.batch_count, 1, leg_steps,
+                                    max(2, args.warmup // 2), cold=not args.warm)
+    if "serve" in legs:
+        log("leg: serve")
+        out["serve"] = serve_record(ac, args.pool, args.requests, args.warm_requests, args.rate,
+                                    args.budget_gb, args.budget_frac, args.max_active,
+                                    args.cg_inner_per_step)
     print(json.dumps(out))
 
 

@@ -327,6 +327,31 @@ int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
 /* Forgets all cached autotune choices. */
 int argcsr_autotune_clear_cache(void);
 
+/* ---- measurement probes ------------------------------------------------ */
+
+/* Not part of the SpMV path: two kernels that measure the ceilings an SpMV
+ * on this GPU is held against (the HBM roofline of an SpMV is its bytes over
+ * the achievable bandwidth; its random x gathers have a rate of their own).
+ * Each wave folds what it read into one value and writes it to
+ * sink[wave], so `sink` is device double[ARGCSR_PROBE_SINK] (caller-owned;
+ * its contents are meaningless).  Asynchronous on `stream`. */
+#define ARGCSR_PROBE_SINK 16384
+
+/* Reads bytes/16 16-byte words of the device buffer `buf` (16-byte aligned)
+ * once, with non-temporal loads, each wave a contiguous kilobyte per load.
+ * Errors: EINVAL, EHIP. */
+int argcsr_probe_read(const void* buf, int64_t bytes, double* sink, void* stream);
+
+/* Reads the device index stream idx[n] in tiles of 512 consecutive entries
+ * per wave and gathers x[idx[i]] for every idx[i] >= 0 (all of a tile's
+ * gathers in flight at once), x being device FP64 (x_bytes 8) or FP32
+ * (x_bytes 4) of n_x elements; indices must lie in [-1, n_x).  Run on the
+ * column array of a converted matrix, it isolates the cost of the SpMV's x
+ * gathers.  Errors: EINVAL, EUNSUPPORTED (x above the 32-bit gather range),
+ * EHIP. */
+int argcsr_probe_gather(const int32_t* idx, int64_t n, const void* x, int32_t n_x,
+                        int32_t x_bytes, double* sink, void* stream);
+
 /* ---- serving ----------------------------------------------------------- */
 
 /* A request server: converted matrices stay resident on one GPU inside a

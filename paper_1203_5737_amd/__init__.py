@@ -18,6 +18,7 @@ from typing import Optional
 import numpy as np
 import torch
 
+from . import _lib as _lib_mod
 from ._lib import (BF16, F16, F32, F64, FORMAT_ARG, FORMAT_RG, ArgCsrError, MatrixDesc,
                    TuneResult, check, lib)
 
@@ -287,6 +288,39 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+PROBE_SINK_ELEMS = _lib_mod.PROBE_SINK
+
+
+def probe_read(t: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """Streams the bytes of device tensor `t` once (argcsr_probe_read); a
+    ceiling measurement, not part of the SpMV path."""
+    _check_sink(sink)
+    if not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("t must be a contiguous device tensor")
+    check(lib().argcsr_probe_read(_ptr(t), t.numel() * t.element_size(), _ptr(sink),
+                                  _stream(stream)), "argcsr_probe_read")
+
+
+def probe_gather(idx: torch.Tensor, x: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """Reads the int32 index stream `idx` (e.g. a converted matrix's columns)
+    and gathers x[idx] for idx >= 0 (argcsr_probe_gather); a ceiling
+    measurement, not part of the SpMV path."""
+    _check_sink(sink)
+    if idx.dtype != torch.int32 or not idx.is_contiguous() or not idx.is_cuda:
+        raise ValueError("idx must be a contiguous int32 device tensor")
+    if x.dtype not in (torch.float64, torch.float32) or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("x must be a contiguous FP64 or FP32 device tensor")
+    check(lib().argcsr_probe_gather(_ptr(idx), idx.numel(), _ptr(x), x.numel(),
+                                    x.element_size(), _ptr(sink), _stream(stream)),
+          "argcsr_probe_gather")
+
+
+def _check_sink(sink: torch.Tensor) -> None:
+    if (sink.dtype != torch.float64 or not sink.is_contiguous() or not sink.is_cuda
+            or sink.numel() < PROBE_SINK_ELEMS):
+        raise ValueError(f"sink must be a contiguous FP64 device tensor of {PROBE_SINK_ELEMS}")
 
 
 def autotune(A: DeviceCsr, dtype: int = F64, n_finalists: int = 4, stream=None) -> dict:

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libargcsr.so")
 OK, EINVAL, EOVERFLOW, ENOMEM, EHIP, EBUDGET, EBUSY, ENOTFOUND, EUNSUPPORTED, ENOCONV = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 PENDING = 1
+PROBE_SINK = 16384                    # ARGCSR_PROBE_SINK
 REQ_ADMIT, REQ_SPMV, REQ_CG, REQ_EVICT = 0, 1, 2, 3
 F64, F32, BF16, F16 = 0, 1, 2, 3
 FORMAT_ARG, FORMAT_RG = 0, 1          # argcsr_format
@@ -109,6 +110,8 @@ SIGNATURES = {
     "argcsr_autotune": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, i32, i32,
                                        ctypes.POINTER(TuneResult), vp]),
     "argcsr_autotune_clear_cache": (ctypes.c_int, []),
+    "argcsr_probe_read": (ctypes.c_int, [vp, i64, vp, vp]),
+    "argcsr_probe_gather": (ctypes.c_int, [vp, i64, vp, i32, i32, vp, vp]),
     "argcsr_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
     "argcsr_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(Request),
                                             ctypes.POINTER(ctypes.c_uint64)]),

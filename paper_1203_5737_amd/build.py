@@ -26,6 +26,7 @@ SOURCES = [
     "batch.hip",
     "tune.cpp",
     "serve.hip",
+    "probes.hip",
 ]
 
 ARCH = "gfx950"

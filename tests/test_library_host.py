@@ -222,3 +222,21 @@ def test_autotune_model_ranking_on_host(L, ora):
         assert abs(r["model_us"] - best[0]) < 1e-9 * max(1.0, best[0])
         assert r["n_candidates"] == 24 and r["n_timed"] == 0 and r["from_cache"] == 0
         assert ac.autotune(d, dt, n_finalists=0)["from_cache"] == 1
+
+
+def test_probes_reject_bad_arguments(L):
+    """The measurement probes validate their arguments on the host before
+    any launch (no GPU call is made on these paths)."""
+    from paper_1203_5737_amd import _lib
+    assert L.argcsr_probe_read(None, -1, None, None) == _lib.EINVAL
+    assert L.argcsr_probe_read(ctypes.c_void_p(16), 64, None, None) == _lib.EINVAL   # no sink
+    assert L.argcsr_probe_read(ctypes.c_void_p(8), 64, ctypes.c_void_p(16), None) == _lib.EINVAL
+    assert L.argcsr_probe_read(None, 0, None, None) == _lib.OK                        # nothing to read
+    assert L.argcsr_probe_gather(None, 10, None, 5, 3, None, None) == _lib.EINVAL      # x_bytes
+    assert L.argcsr_probe_gather(None, -1, None, 5, 8, None, None) == _lib.EINVAL
+    assert L.argcsr_probe_gather(ctypes.c_void_p(16), 10, ctypes.c_void_p(16), 2**30, 8,
+                                 ctypes.c_void_p(16), None) == _lib.EUNSUPPORTED
+    assert L.argcsr_probe_gather(None, 0, None, 5, 4, None, None) == _lib.OK
+    assert _lib.PROBE_SINK == 16384
+    hdr = open(os.path.join(ROOT, "include", "argcsr.h")).read()
+    assert "#define ARGCSR_PROBE_SINK 16384" in hdr
