@@ -71,6 +71,8 @@ def _bind(L):
         "ora_f16_value": (f64, [u16]),
         "ora_cg": (i32, [i32, vp, vp, vp, vp, vp, f64, i32, vp]),
         "ora_round_array": (None, [i64, vp, i32, vp]),
+        "ora_stage": (i64, [i32, vp, vp, i32, i32, i32, vp, vp, vp, i64, vp]),
+        "ora_unstage": (None, [i32, vp, i32, vp, vp, vp, vp]),
         "ora_decode_array": (None, [i64, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
@@ -237,6 +239,57 @@ def argcsr_spmv(a: ArgCsr, x) -> np.ndarray:
     lib().ora_argcsr_spmv(a.n_groups, _p(a.groups), _p(a.tm), _p(a.columns), _p(vals),
                           a.block_dim, _p(x), _p(y))
     return y
+
+
+@dataclass
+class Staging:
+    """Staging of x for a converted matrix (reading R11, oracle.h)."""
+    tile_ptr: np.ndarray     # int32 [G+1]
+    tile_start: np.ndarray   # int32 [n_tiles] first column of each tile
+    tile_len: np.ndarray     # int32 [n_tiles] columns in each tile (1..64)
+    local: np.ndarray        # uint16 [S] 64*q + (c - tile_start), 0xFFFF = artificial zero
+
+    @property
+    def n_tiles(self) -> int:
+        return int(self.tile_start.shape[0])
+
+    def max_tiles(self) -> int:
+        return int(np.diff(self.tile_ptr).max()) if self.tile_ptr.size > 1 else 0
+
+
+STAGE_TOO_MANY_TILES = -1      # ORA_EINVAL: a group needs more than max_tiles tiles
+
+
+def stage(a: ArgCsr, gap: int, max_tiles: int):
+    """Windows and tiles of x per group and the 16-bit local column of every
+    slot (ora_stage); returns a Staging, or STAGE_TOO_MANY_TILES."""
+    g, c = _c(a.groups, np.int32), _c(a.columns, np.int32)
+    tile_ptr = np.zeros(a.n_groups + 1, dtype=np.int32)
+    n = lib().ora_stage(a.n_groups, _p(g), _p(c), a.block_dim, int(gap), int(max_tiles),
+                        _p(tile_ptr), None, None, 0, None)
+    if n < 0:
+        if n == STAGE_TOO_MANY_TILES:
+            return STAGE_TOO_MANY_TILES
+        raise ValueError(f"ora_stage failed: {n}")
+    ts = np.zeros(max(n, 1), dtype=np.int32)
+    tl = np.zeros(max(n, 1), dtype=np.int32)
+    local = np.zeros(max(a.n_slots, 1), dtype=np.uint16)
+    n2 = lib().ora_stage(a.n_groups, _p(g), _p(c), a.block_dim, int(gap), int(max_tiles),
+                         _p(tile_ptr), _p(ts), _p(tl), n, _p(local))
+    if n2 != n:
+        raise ValueError(f"ora_stage failed: {n2}")
+    return Staging(tile_ptr, ts[:n].copy(), tl[:n].copy(), local[:a.n_slots].copy())
+
+
+def unstage(a: ArgCsr, st: Staging) -> np.ndarray:
+    """The column index every slot names, from its local index (ora_unstage)."""
+    out = np.empty(max(a.n_slots, 1), dtype=np.int32)
+    ts = st.tile_start if st.tile_start.size else np.zeros(1, np.int32)
+    lib().ora_unstage(a.n_groups, _p(_c(a.groups, np.int32)), a.block_dim,
+                      _p(_c(st.tile_ptr, np.int32)), _p(_c(ts, np.int32)),
+                      _p(_c(st.local if st.local.size else np.zeros(1, np.uint16), np.uint16)),
+                      _p(out))
+    return out[:a.n_slots]
 
 
 def argcsr_to_csr(a: ArgCsr, nnz_capacity: int):

@@ -453,6 +453,116 @@ void ora_argcsr_spmv(int32_t n_groups, const int32_t* groups, const int32_t* tm,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Staging of x for banded matrices (a storage extension, reading R11): the   */
+/* paper's kernel fetches the data each group reuses into fast shared memory  */
+/* (Sec. 4); here the part of x a group reads is listed so that it can be     */
+/* staged the same way.  For group g: u_0 < u_1 < ... are the distinct       */
+/* column indices its slots hold (artificial zeros excluded).  A window is a  */
+/* maximal run of them in which two neighbours have at most `gap` absent      */
+/* columns between them (u_{i+1} - u_i - 1 <= gap); window [s, e] covers      */
+/* every column s..e.  Each window is cut into tiles of 64 consecutive        */
+/* columns from its start (the last tile may be shorter).  The tiles of g,    */
+/* in column order, are tile_start/tile_len[tile_ptr[g] .. tile_ptr[g+1]).    */
+/* A slot holding column c gets the local index 64*q + (c - tile_start) for  */
+/* the q-th tile of its group that contains c; an artificial zero gets        */
+/* 0xFFFF.  Returns the number of tiles, or ORA_EINVAL when a group needs     */
+/* more than max_tiles (<= 1023) tiles, or ORA_EOVERFLOW when tile_cap is     */
+/* too small.  With tile_start == NULL only tile_ptr is filled.               */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_i32(const void* a, const void* b)
+{
+    const int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+int64_t ora_stage(int32_t n_groups, const int32_t* groups, const int32_t* columns,
+                  int32_t block_dim, int32_t gap, int32_t max_tiles, int32_t* tile_ptr,
+                  int32_t* tile_start, int32_t* tile_len, int64_t tile_cap,
+                  uint16_t* local)
+{
+    if (gap < 0 || max_tiles < 1 || max_tiles > 1023 || block_dim < 1) return ORA_EINVAL;
+    int64_t total = 0;
+    int64_t biggest = 1;
+    for (int32_t g = 0; g < n_groups; g++) {
+        const int64_t slots = (int64_t)groups[4 * g + 3] * block_dim;
+        if (slots > biggest) biggest = slots;
+    }
+    int32_t* u = (int32_t*)malloc(sizeof(int32_t) * (size_t)biggest);
+    int32_t* ts = (int32_t*)malloc(sizeof(int32_t) * (size_t)(max_tiles + 1));
+    int32_t* tl = (int32_t*)malloc(sizeof(int32_t) * (size_t)(max_tiles + 1));
+    if (!u || !ts || !tl) { free(u); free(ts); free(tl); return ORA_ENOMEM; }
+    tile_ptr[0] = 0;
+    int64_t rc = 0;
+    for (int32_t g = 0; g < n_groups && rc == 0; g++) {
+        const int64_t offset = groups[4 * g + 2];
+        const int64_t slots = (int64_t)groups[4 * g + 3] * block_dim;
+        /* the distinct columns of the group, ascending */
+        int64_t m = 0;
+        for (int64_t s = 0; s < slots; s++)
+            if (columns[offset + s] != -1) u[m++] = columns[offset + s];
+        qsort(u, (size_t)m, sizeof(int32_t), cmp_i32);
+        int64_t distinct = 0;
+        for (int64_t i = 0; i < m; i++)
+            if (distinct == 0 || u[i] != u[distinct - 1]) u[distinct++] = u[i];
+        /* windows, then tiles of 64 columns */
+        int32_t nt = 0;
+        int64_t i = 0;
+        while (i < distinct && rc == 0) {
+            const int64_t start = u[i];
+            int64_t last = u[i];
+            while (i + 1 < distinct && (int64_t)u[i + 1] - last - 1 <= gap) last = u[++i];
+            i++;
+            for (int64_t t = start; t <= last; t += 64) {
+                if (nt == max_tiles) { rc = ORA_EINVAL; break; }
+                ts[nt] = (int32_t)t;
+                tl[nt] = (int32_t)(last - t + 1 < 64 ? last - t + 1 : 64);
+                nt++;
+            }
+        }
+        if (rc) break;
+        if (tile_start) {
+            if (total + nt > tile_cap) { rc = ORA_EOVERFLOW; break; }
+            for (int32_t q = 0; q < nt; q++) {
+                tile_start[total + q] = ts[q];
+                tile_len[total + q] = tl[q];
+            }
+            /* local index of every slot: the tile holding its column */
+            for (int64_t s = 0; s < slots; s++) {
+                const int32_t c = columns[offset + s];
+                uint16_t v = 0xFFFF;
+                if (c != -1) {
+                    for (int32_t q = 0; q < nt; q++)
+                        if (c >= ts[q] && c < ts[q] + tl[q]) { v = (uint16_t)(64 * q + (c - ts[q])); break; }
+                }
+                local[offset + s] = v;
+            }
+        }
+        total += nt;
+        tile_ptr[g + 1] = (int32_t)total;
+    }
+    free(u); free(ts); free(tl);
+    return rc ? rc : total;
+}
+
+/* The inverse of the local indices: the column index each slot names,      */
+/* tile_start[tile_ptr[g] + local/64] + local%64, -1 for 0xFFFF.             */
+void ora_unstage(int32_t n_groups, const int32_t* groups, int32_t block_dim,
+                 const int32_t* tile_ptr, const int32_t* tile_start,
+                 const uint16_t* local, int32_t* columns_out)
+{
+    for (int32_t g = 0; g < n_groups; g++) {
+        const int64_t offset = groups[4 * g + 2];
+        const int64_t slots = (int64_t)groups[4 * g + 3] * block_dim;
+        for (int64_t s = 0; s < slots; s++) {
+            const uint16_t v = local[offset + s];
+            columns_out[offset + s] = v == 0xFFFF ? -1
+                : tile_start[tile_ptr[g] + v / 64] + v % 64;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Inverse conversion: walk each row's chunks in order, emitting elements     */
 /* until the artificial-zero marker.                                          */
 /* ------------------------------------------------------------------------ */

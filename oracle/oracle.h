@@ -39,6 +39,11 @@
  *       -- the more regular the rows, the larger desiredChunkSize -- applied
  *       locally): the group that opens at row s uses the value of the region
  *       holding s for its nonzero limit.
+ *   R11 Staging of x (an extension; Sec. 4 stages the data each group
+ *       reuses in shared memory, not x): the columns a group's slots name
+ *       are merged into windows (holes of at most `gap` absent columns
+ *       bridged) and cut into tiles of 64 columns; slots then hold 16-bit
+ *       positions in the group's staged tiles (0xFFFF = artificial zero).
  *   R9  Row-grouped CSR (the Sliced-ELLPACK-style storage Sec. 3 builds on,
  *       compared against in Sec. 5): slices of blockDim consecutive rows,
  *       one chunk per row, chunk size = the slice's longest row, but at
@@ -58,7 +63,7 @@ extern "C" {
 enum { ORA_F64 = 0, ORA_F32 = 1, ORA_BF16 = 2, ORA_F16 = 3 };
 
 /* Return codes. */
-enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_EOVERFLOW = -2 };
+enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_EOVERFLOW = -2, ORA_ENOMEM = -3 };
 
 /* CSR SpMV by definition (Sec. 2):
  * y_i = sum_{k=rp[i]}^{rp[i+1]-1} val[k] * x[col[k]], left to right, FP64.
@@ -124,6 +129,24 @@ int ora_rgcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
                       const double* val, int32_t block_dim, int32_t dtype,
                       int32_t* groups, int32_t* tm, int32_t* columns,
                       void* values);
+
+/* Staging of x for banded matrices (reading R11): per group, the distinct
+ * columns of its slots merged into windows (at most `gap` absent columns
+ * between neighbours inside a window), each window cut into tiles of 64
+ * columns; local[slot] = 64*q + (c - tile_start) for the group's q-th tile
+ * holding column c, 0xFFFF for an artificial zero.  tile_ptr has
+ * n_groups+1 entries.  Returns the tile count, ORA_EINVAL if a group needs
+ * more than max_tiles (<= 1023) tiles, ORA_EOVERFLOW if tile_cap is too
+ * small; with tile_start == NULL only tile_ptr is filled (sizing). */
+int64_t ora_stage(int32_t n_groups, const int32_t* groups, const int32_t* columns,
+                  int32_t block_dim, int32_t gap, int32_t max_tiles, int32_t* tile_ptr,
+                  int32_t* tile_start, int32_t* tile_len, int64_t tile_cap,
+                  uint16_t* local);
+
+/* Column index of every slot from its local index (-1 for 0xFFFF). */
+void ora_unstage(int32_t n_groups, const int32_t* groups, int32_t block_dim,
+                 const int32_t* tile_ptr, const int32_t* tile_start,
+                 const uint16_t* local, int32_t* columns_out);
 
 /* SpMV read from the ARG-CSR storage by the format's definition (Sec. 3,
  * Sec. 4), FP64: each row's elements are found through the threads mapping

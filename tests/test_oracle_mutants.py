@@ -48,6 +48,11 @@ MUTANTS = {
     "rg_layout_row_major": ("columns[offset + e * block_dim + l] = col[rp[r] + e];\n                store_value(values, dtype, offset + e * block_dim + l,",
                             "columns[offset + l * w + e] = col[rp[r] + e];\n                store_value(values, dtype, offset + l * w + e,"),
     "rg_mapping_exclusive": ("tm[r] = (int32_t)(l + 1);", "tm[r] = (int32_t)l;"),
+    "stage_gap_strict": ("(int64_t)u[i + 1] - last - 1 <= gap", "(int64_t)u[i + 1] - last - 1 < gap"),
+    "stage_tiles_of_63": ("for (int64_t t = start; t <= last; t += 64) {", "for (int64_t t = start; t <= last; t += 63) {"),
+    "stage_local_window_packed": ("v = (uint16_t)(64 * q + (c - ts[q]));", "v = (uint16_t)(q + (c - ts[q]));"),
+    "stage_tile_drops_last_column": ("tl[nt] = (int32_t)(last - t + 1 < 64 ? last - t + 1 : 64);",
+                                     "tl[nt] = (int32_t)(last - t < 64 ? last - t : 64);"),
     "rg_slices_offset_by_one": ("groups[4 * g + 0] = (int32_t)first;", "groups[4 * g + 0] = (int32_t)first + (g > 0);"),
 }
 
@@ -72,6 +77,9 @@ BATTERY = [
     pins.test_rgcsr_equals_argcsr_with_unbounded_budget,
     pins.test_rgcsr_partial_last_slice_keeps_one_chunk_per_row,
     pins.test_rgcsr_roundtrip_and_spmv_is_csr_order,
+    pins.test_stage_hand_worked_example,
+    pins.test_stage_laplace_closed_form,
+    pins.test_stage_matches_occupancy_definition,
 ]
 
 

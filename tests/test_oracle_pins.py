@@ -643,3 +643,129 @@ def test_regions_groups_are_greedy_maximal(ora, lengths, T, region_rows, seed):
             assert size + 1 > T or rp[e + 1] - rp[first] > limit
         nxt = e
     assert nxt == n
+
+
+# ---------------------------------------------------------------------------
+# staging of x for banded matrices (reading R11)
+# ---------------------------------------------------------------------------
+
+def _stage_example():
+    """One group (T = 4, D = 18): rows with columns {0,1,2}, {5,9,10},
+    {200..263} and {300}; chunk size 64, one chunk per row."""
+    cols = [[0, 1, 2], [5, 9, 10], list(range(200, 264)), [300]]
+    rp = np.cumsum([0] + [len(c) for c in cols]).astype(np.int32)
+    col = np.concatenate(cols).astype(np.int32)
+    return rp, col, np.ones(col.size)
+
+
+def test_stage_hand_worked_example(ora):
+    rp, col, val = _stage_example()
+    a = ora.convert(rp, col, val, 4, 18)
+    assert a.n_groups == 1 and a.groups[0, 3] == 64
+    want = {
+        # gap: (tile starts, tile lengths, {column: local index})
+        0: ([0, 5, 9, 200, 300], [3, 1, 2, 64, 1], {0: 0, 2: 2, 5: 64, 9: 128, 10: 129,
+                                                    200: 192, 263: 255, 300: 256}),
+        2: ([0, 9, 200, 300], [6, 2, 64, 1], {0: 0, 5: 5, 9: 64, 10: 65, 200: 128,
+                                              263: 191, 300: 192}),
+        3: ([0, 200, 300], [11, 64, 1], {5: 5, 9: 9, 10: 10, 200: 64, 263: 127, 300: 128}),
+        # the hole 11..199 (189 columns) stays open; 264..299 (36) is bridged
+        100: ([0, 200, 264], [11, 64, 37], {0: 0, 9: 9, 200: 64, 263: 127, 300: 164}),
+        # one window 0..300, cut every 64 columns: the local index is the column
+        200: ([0, 64, 128, 192, 256], [64, 64, 64, 64, 45], {c: c for c in (0, 9, 200, 263, 300)}),
+    }
+    for gap, (starts, lens, loc) in want.items():
+        st = ora.stage(a, gap, 16)
+        assert list(st.tile_ptr) == [0, len(starts)], gap
+        assert list(st.tile_start) == starts and list(st.tile_len) == lens, gap
+        pos = {int(c): int(l) for c, l in zip(a.columns, st.local) if c >= 0}
+        for c, l in loc.items():
+            assert pos[c] == l, (gap, c)
+        assert np.all(st.local[a.columns < 0] == 0xFFFF)
+        assert np.array_equal(ora.unstage(a, st), a.columns)
+    assert ora.stage(a, 0, 4) == ora.STAGE_TOO_MANY_TILES          # needs 5 tiles
+
+
+def test_stage_laplace_closed_form(ora):
+    """5-point Laplacian on a 64x64 grid, T = 64, D = 5: group i is grid line
+    i and reads lines i-1, i, i+1 whole, one tile each (gap 0); column k of
+    line L has local index 64*(L - max(i-1, 0)) + k."""
+    s = 64
+    A = synth.laplace2d(s, s)
+    a = ora.convert(A.rp, A.col, A.val, s, 5)
+    assert a.n_groups == s and np.all(a.groups[:, 1] == s)
+    st = ora.stage(a, 0, 8)
+    for i in range(s):
+        lines = [L for L in (i - 1, i, i + 1) if 0 <= L < s]
+        tb, te = st.tile_ptr[i], st.tile_ptr[i + 1]
+        assert list(st.tile_start[tb:te]) == [64 * L for L in lines]
+        assert np.all(st.tile_len[tb:te] == 64)
+        off, c = a.groups[i, 2], a.groups[i, 3]
+        sl = slice(off, off + c * s)
+        cols, loc = a.columns[sl], st.local[sl]
+        live = cols >= 0
+        L, k = cols[live] // s, cols[live] % s
+        assert np.array_equal(loc[live], 64 * (L - max(i - 1, 0)) + k)
+        assert np.all(loc[~live] == 0xFFFF)
+
+
+def _stage_by_occupancy(a, gap):
+    """The same tiles from a different formulation: an occupancy array over
+    each group's column range, holes of at most `gap` filled where a present
+    column lies on both sides, runs of the result cut every 64 columns."""
+    tiles = []
+    T = a.block_dim
+    for g in range(a.n_groups):
+        off, c = a.groups[g, 2], a.groups[g, 3]
+        cols = a.columns[off:off + c * T]
+        cols = cols[cols >= 0]
+        out = []
+        if cols.size:
+            lo, hi = cols.min(), cols.max()
+            occ = np.zeros(hi - lo + 1, dtype=bool)
+            occ[cols - lo] = True
+            present = np.nonzero(occ)[0]
+            for p, q in zip(present[:-1], present[1:]):
+                if q - p - 1 <= gap:
+                    occ[p:q] = True
+            edges = np.diff(np.concatenate([[0], occ.astype(np.int8), [0]]))
+            for s0, e0 in zip(np.nonzero(edges == 1)[0], np.nonzero(edges == -1)[0]):
+                for t in range(s0, e0, 64):
+                    out.append((int(lo + t), int(min(64, e0 - t))))
+        tiles.append(out)
+    return tiles
+
+
+def test_stage_matches_occupancy_definition(ora):
+    rng = np.random.default_rng(17)
+    for trial in range(40):
+        n = int(rng.integers(1, 300))
+        n_cols = int(rng.integers(1, 2000))
+        band = int(rng.integers(1, 200))
+        L = rng.integers(0, 12, n)
+        rows = []
+        for r in range(n):
+            centre = int(r * n_cols / max(n, 1))
+            lo, hi = max(0, centre - band), min(n_cols, centre + band + 1)
+            k = min(int(L[r]), hi - lo)
+            rows.append(np.sort(rng.choice(np.arange(lo, hi), k, replace=False)))
+        rp = np.cumsum([0] + [len(x) for x in rows]).astype(np.int32)
+        col = np.concatenate(rows).astype(np.int32) if rp[-1] else np.zeros(0, np.int32)
+        T = int(rng.choice([1, 5, 64, 128]))
+        D = int(rng.choice([1, 2, 8]))
+        gap = int(rng.choice([0, 1, 3, 17]))
+        a = ora.convert(rp, col, np.ones(col.size), T, D)
+        st = ora.stage(a, gap, 1023)
+        want = _stage_by_occupancy(a, gap)
+        assert list(np.diff(st.tile_ptr)) == [len(t) for t in want], trial
+        flat = [t for ts in want for t in ts]
+        assert list(zip(st.tile_start.tolist(), st.tile_len.tolist())) == flat, trial
+        assert np.array_equal(ora.unstage(a, st), a.columns), trial
+        # a local index addresses a column inside its tile
+        for g in range(a.n_groups):
+            off, c = a.groups[g, 2], a.groups[g, 3]
+            loc = st.local[off:off + c * T]
+            live = loc != 0xFFFF
+            q = loc[live] // 64
+            assert np.all(q < np.diff(st.tile_ptr)[g])
+            assert np.all(loc[live] % 64 < st.tile_len[st.tile_ptr[g] + q])

@@ -1,5 +1,5 @@
 """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (CPU):
-conversion, inverse, both SpMV forms, rounding and CG on random inputs,
+conversion, inverse, both SpMV forms, rounding, staging and CG on random inputs,
 including empty rows and matrices, must run without any sanitizer report."""
 import os
 import shutil
@@ -48,6 +48,21 @@ int main(void) {
     int *rp2 = malloc(sizeof(int) * (n + 1)), *col2 = malloc(sizeof(int) * (nnz + 1));
     if (ora_argcsr_to_csr(n, G, groups, tm, cols, v64, T, rp2, col2, val2) != nnz) return 4;
     if (n > 0 && memcmp(rp, rp2, sizeof(int) * (n + 1)) != 0) return 5;
+    {   /* staging of x: sizing pass, filling pass, inverse */
+      int *tp = malloc(sizeof(int) * (G + 1));
+      int gap = (int)(rnd() % 5);
+      int64_t nt = ora_stage(G, groups, cols, T, gap, 1023, tp, NULL, NULL, 0, NULL);
+      if (nt >= 0) {
+        int *ts = malloc(sizeof(int) * (nt + 1)), *tl = malloc(sizeof(int) * (nt + 1));
+        uint16_t *loc = malloc(sizeof(uint16_t) * (S64 + 1));
+        int *back = malloc(sizeof(int) * (S64 + 1));
+        if (ora_stage(G, groups, cols, T, gap, 1023, tp, ts, tl, nt, loc) != nt) return 10;
+        ora_unstage(G, groups, T, tp, ts, loc, back);
+        if (S64 > 0 && memcmp(back, cols, sizeof(int) * S64) != 0) return 11;
+        free(ts); free(tl); free(loc); free(back);
+      }
+      free(tp);
+    }
     ora_round_array(nnz, val, 2, vals);
     {   /* row-grouped CSR in the same arrays, decoded back */
       int RG; int64_t RS;
