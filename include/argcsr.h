@@ -221,6 +221,31 @@ int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
                    argcsr_matrix* out, void* stream);
 
 /*
+ * argcsr_convert_noalloc -- argcsr_convert for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): it calls no hipMalloc, hipFree or other
+ * allocating routine.  Its scratch (status words, scan partials and the
+ * fill's long-row list) is a fixed 16 MiB array in device memory, one copy
+ * per GPU, held by the library until the process ends; the caller still
+ * passes every input and output, as for argcsr_convert, and the result is
+ * byte for byte the same.
+ *   arguments as for argcsr_convert, except that row_ptr_host is required
+ *   (step 1 runs on the host; device grouping needs scratch proportional to
+ *   n_rows*log2(n_rows))
+ * A matrix whose scratch would exceed 16 MiB -- 24 + 16*ceil(n_groups/1024)
+ * + 8*(n_slots/(4*block_dim) + 1) bytes, i.e. n_slots above about
+ * 8*10^6*block_dim -- is rejected with EINVAL before anything is written.
+ * The scratch keeps the last call's contents; each call clears what must
+ * start at zero.  Calls are serialised by a process-wide lock and are
+ * synchronous, so calls from several host threads never overlap on a GPU.
+ * `stream` must belong to the current device.
+ * Errors: as argcsr_convert.
+ */
+int argcsr_convert_noalloc(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                           const int32_t* row_ptr, const int32_t* col, const double* val,
+                           argcsr_matrix* out, void* stream);
+
+/*
  * argcsr_spmv -- y = A x for a converted matrix (Sec. 4, Listing 2
  * semantics: each chunk sums value*x[column] up to its first -1, each row
  * sums its chunks; y is overwritten, empty rows give 0).

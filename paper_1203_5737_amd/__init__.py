@@ -161,14 +161,18 @@ def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, 
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
             dtype: int = F64, stream=None, schedule: bool = True,
             device_grouping: bool = False, fmt: int = FORMAT_ARG, region_rows: int = 0,
-            region_desired=None) -> ArgCsrMatrix:
+            region_desired=None, noalloc: bool = False) -> ArgCsrMatrix:
     """CSR -> ARG-CSR (or, with fmt=FORMAT_RG, row-grouped CSR) on the GPU
     (argcsr_convert); allocates the result.  `schedule` also builds the
     heavy-group launch schedule.  With `device_grouping` step 1 runs on the
     device and the host copy of row_ptr is not used (argcsr_plan_device,
     row_ptr_host = NULL).  `region_desired` (with `region_rows`) gives
     ARG-CSR a desiredChunkSize per region of rows (argcsr_plan_regions; the
-    sizes are planned on the host)."""
+    sizes are planned on the host).  `noalloc` converts with
+    argcsr_convert_noalloc (the library allocates no device memory; the
+    result tensors are still allocated here, as the caller's outputs)."""
+    if noalloc and device_grouping:
+        raise ValueError("argcsr_convert_noalloc groups the rows on the host")
     if fmt == FORMAT_RG:
         desired_chunk_size = 0
     regions = None
@@ -196,9 +200,10 @@ def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
         d.region_rows = int(region_rows)
         d.region_desired = regions.ctypes.data_as(ctypes.c_void_p)
     rp_host = None if device_grouping else A.row_ptr_host.ctypes.data_as(ctypes.c_void_p)
-    check(lib().argcsr_convert(A.n_rows, A.n_cols, rp_host,
-                               _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val), ctypes.byref(d),
-                               _stream(stream)), "argcsr_convert")
+    fn, name = ((lib().argcsr_convert_noalloc, "argcsr_convert_noalloc") if noalloc
+                else (lib().argcsr_convert, "argcsr_convert"))
+    check(fn(A.n_rows, A.n_cols, rp_host, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val),
+             ctypes.byref(d), _stream(stream)), name)
     out.nnz = int(d.nnz)
     out.heavy_chunk = int(d.heavy_chunk)
     if not schedule:

@@ -99,6 +99,8 @@ SIGNATURES = {
     "argcsr_plan_device": (ctypes.c_int, [i32, vp, i32, i32, i32, ctypes.POINTER(i32),
                                           ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
+    "argcsr_convert_noalloc": (ctypes.c_int, [i32, i32, vp, vp, vp, vp,
+                                              ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),
     "argcsr_csr_spmv": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, vp, vp, vp]),
     "argcsr_batch_create": (ctypes.c_int, [i32, ctypes.POINTER(MatrixDesc), ctypes.POINTER(vp),

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -451,11 +452,68 @@ void launch_fill(int32_t n_groups, hipStream_t s, const int32_t* rp, const int32
 }  // namespace
 }  // namespace argcsr
 
-extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
-                              const int32_t* row_ptr, const int32_t* col, const double* val,
-                              argcsr_matrix* out, void* stream) {
-  using namespace argcsr;
-  clear_error();
+// Fixed scratch of argcsr_convert_noalloc: one copy per GPU (this process's
+// code object), held until the process ends.  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace argcsr {
+namespace {
+
+// Device scratch of one conversion: status words, the two tile-sum arrays of
+// the offset and heavy scans, and the fill's long-row list.  Items of that
+// list: a group makes them only when its chunk size c exceeds
+// stage/64 >= kMinStage/64 = 4, and then ceil(c/16) <= c/4 of them, so all
+// groups together make at most n_slots/(4T).
+static_assert(kMinStage / 64 >= 4 && kLongSteps == 16, "long-list bound");
+struct ConvertScratch {
+  int32_t n_tiles;
+  int64_t long_capacity;
+  size_t bytes;
+};
+
+ConvertScratch convert_scratch(int32_t n_groups, int64_t n_slots, int32_t T) {
+  ConvertScratch c;
+  c.n_tiles = (n_groups + kScanTile - 1) / kScanTile;
+  c.long_capacity = n_slots / (4 * int64_t(T)) + 1;
+  c.bytes = sizeof(Status) + 2 * sizeof(int64_t) * size_t(c.n_tiles) +
+            2 * sizeof(int32_t) * size_t(c.long_capacity);
+  return c;
+}
+
+constexpr int kMaxDevices = 64;
+// Step-1 groups of argcsr_convert_noalloc pass through this host buffer on
+// their way to the device (copied and waited for chunk by chunk).
+constexpr int32_t kGroupChunk = 1 << 16;
+argcsr_group_info g_group_chunk[kGroupChunk];
+std::mutex g_noalloc_mu;                    // one argcsr_convert_noalloc at a time
+void* g_noalloc_ptr[kMaxDevices] = {};       // device address of `scratch`, per device
+
+// The current device's address of `scratch` (looked up once per device,
+// with that device current).  Caller holds g_noalloc_mu.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  ARGCSR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ARGCSR_EUNSUPPORTED, "device %d", dev);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ARGCSR_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return ARGCSR_OK;
+}
+
+// All four steps.  With `fixed` (argcsr_convert_noalloc) the scratch is the
+// given device memory of fixed_bytes, step 1 runs on the host from
+// row_ptr_host (required) and its groups reach the device through
+// g_group_chunk; nothing is allocated.
+int convert_impl(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                 const int32_t* row_ptr, const int32_t* col, const double* val,
+                 argcsr_matrix* out, hipStream_t s, bool fixed) {
   if (!out) return fail(ARGCSR_EINVAL, "out is NULL");
   if (n_rows < 0 || n_cols < 0) return fail(ARGCSR_EINVAL, "negative dimension");
   if (out->n_rows != n_rows || out->n_cols != n_cols)
@@ -469,24 +527,64 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
     return fail(ARGCSR_EINVAL, "desired_chunk_size < 1");
   if (out->dtype < ARGCSR_F64 || out->dtype > ARGCSR_F16)
     return fail(ARGCSR_EINVAL, "unknown dtype %d", out->dtype);
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (out->n_groups < 0 || out->n_slots < 0) return fail(ARGCSR_EINVAL, "negative size in out");
+  const int32_t* regions = out->format == ARGCSR_FORMAT_ARG ? out->region_desired : nullptr;
+  int rc = check_regions(n_rows, out->region_rows, regions);
+  if (rc) return rc;
+  void* fixed_ptr = nullptr;
+  if (fixed) {
+    if (!row_ptr_host)
+      return fail(ARGCSR_EINVAL, "argcsr_convert_noalloc needs row_ptr_host (step 1 on the host)");
+    const ConvertScratch need = convert_scratch(out->n_groups, out->n_slots, T);
+    if (need.bytes > kNoAllocScratchBytes)
+      return fail(ARGCSR_EINVAL,
+                  "the conversion needs %zu bytes of scratch, more than the %zu bytes "
+                  "argcsr_convert_noalloc holds", need.bytes, kNoAllocScratchBytes);
+  }
   // step 1: on the host from row_ptr_host, or on the device (group.hip)
   std::vector<argcsr_group_info> host_groups;
   DeviceGrouping device_groups;
   int64_t nnz = 0;
   int32_t G = 0;
-  int rc = ARGCSR_OK;
-  const int32_t* regions = out->format == ARGCSR_FORMAT_ARG ? out->region_desired : nullptr;
-  rc = check_regions(n_rows, out->region_rows, regions);
-  if (rc) return rc;
+  bool groups_uploaded = false;
   if (row_ptr_host) {
     rc = check_row_ptr(n_rows, row_ptr_host);
     if (rc) return rc;
     nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
-    rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, out->format, &host_groups,
-                    out->region_rows, regions);
-    if (rc) return rc;
-    G = (int32_t)host_groups.size();
+    if (fixed) {
+      if (out->n_groups > 0 && !out->groups) return fail(ARGCSR_EINVAL, "NULL device buffer");
+      rc = noalloc_scratch(&fixed_ptr);
+      if (rc) return rc;
+      // groups go to out->groups a chunk at a time, never past out->n_groups
+      int32_t filled = 0;
+      auto flush = [&]() -> int {
+        if (filled == 0) return ARGCSR_OK;
+        ARGCSR_HIP(hipMemcpyAsync(out->groups + (G - filled), g_group_chunk,
+                                  sizeof(argcsr_group_info) * size_t(filled),
+                                  hipMemcpyHostToDevice, s));
+        ARGCSR_HIP(hipStreamSynchronize(s));       // the buffer is reused next
+        filled = 0;
+        return ARGCSR_OK;
+      };
+      rc = for_each_group(n_rows, row_ptr_host, T, out->desired_chunk_size, out->format,
+                          out->region_rows, regions, [&](int32_t first, int32_t size) -> int {
+                            if (G >= out->n_groups)
+                              return fail(ARGCSR_EINVAL, "out->n_groups = %d but the matrix "
+                                          "has more groups", out->n_groups);
+                            g_group_chunk[filled++] = argcsr_group_info{first, size, 0, 0};
+                            ++G;
+                            return filled == kGroupChunk ? flush() : 0;
+                          });
+      if (rc) return rc;
+      rc = flush();
+      if (rc) return rc;
+      groups_uploaded = true;
+    } else {
+      rc = group_rows(n_rows, row_ptr_host, T, out->desired_chunk_size, out->format,
+                      &host_groups, out->region_rows, regions);
+      if (rc) return rc;
+      G = (int32_t)host_groups.size();
+    }
   } else {
     if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
     rc = device_groups.build(n_rows, row_ptr, T, out->desired_chunk_size, out->format, s,
@@ -513,17 +611,16 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
       (nnz > 0 && (!col || !val)))
     return fail(ARGCSR_EINVAL, "NULL device buffer");
 
-  const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
+  const ConvertScratch cs = convert_scratch(G, out->n_slots, T);
+  const int32_t n_tiles = cs.n_tiles;
   StreamScratch ws;
-  // items of the fill's long-row list: a group makes them only when its
-  // chunk size c exceeds stage/64 >= kMinStage/64 = 4, and then ceil(c/16)
-  // <= c/4 of them, so all groups together make at most n_slots/(4T)
-  static_assert(kMinStage / 64 >= 4 && kLongSteps == 16, "long-list bound");
-  const int64_t long_capacity = out->n_slots / (4 * int64_t(T)) + 1;
-  rc = ws.alloc(sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles) +
-                2 * sizeof(int32_t) * size_t(long_capacity), s);
-  if (rc) return rc;
-  Status* st = static_cast<Status*>(ws.ptr);
+  void* base = fixed_ptr;
+  if (!fixed) {
+    rc = ws.alloc(cs.bytes, s);
+    if (rc) return rc;
+    base = ws.ptr;
+  }
+  Status* st = static_cast<Status*>(base);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
   int64_t* heavy_tiles = tile_sums + n_tiles;
   // (group, first step) per tile of the fill's long blocks
@@ -534,8 +631,9 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
 
   clear_status_kernel<<<1, 1, 0, s>>>(st);
   if (row_ptr_host) {
-    ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
-                              sizeof(argcsr_group_info) * size_t(G), hipMemcpyHostToDevice, s));
+    if (!groups_uploaded)
+      ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
+                                sizeof(argcsr_group_info) * size_t(G), hipMemcpyHostToDevice, s));
   } else {
     rc = device_groups.write(out->groups);
     if (rc) return rc;
@@ -580,6 +678,26 @@ extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row
   if (host_st.bad_column)
     return fail(ARGCSR_EINVAL, "a column index lies outside [0, %d)", n_cols);
   return ARGCSR_OK;
+}
+
+}  // namespace
+}  // namespace argcsr
+
+extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                              const int32_t* row_ptr, const int32_t* col, const double* val,
+                              argcsr_matrix* out, void* stream) {
+  argcsr::clear_error();
+  return argcsr::convert_impl(n_rows, n_cols, row_ptr_host, row_ptr, col, val, out,
+                              static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" int argcsr_convert_noalloc(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                                      const int32_t* row_ptr, const int32_t* col,
+                                      const double* val, argcsr_matrix* out, void* stream) {
+  argcsr::clear_error();
+  std::lock_guard<std::mutex> lock(argcsr::g_noalloc_mu);
+  return argcsr::convert_impl(n_rows, n_cols, row_ptr_host, row_ptr, col, val, out,
+                              static_cast<hipStream_t>(stream), true);
 }
 
 extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,

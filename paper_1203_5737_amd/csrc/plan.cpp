@@ -38,20 +38,11 @@ int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
                int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups,
                int32_t region_rows, const int32_t* region_desired) {
   groups->clear();
-  const bool rg = format == ARGCSR_FORMAT_RG;
-  int32_t start = 0;
-  while (start < n_rows) {
-    // extend the group from `start` as far as both limits allow (at least one row)
-    const int32_t d = region_desired ? region_desired[start / region_rows] : desired;
-    const int64_t budget = rg ? INT64_MAX / 2 : int64_t(d) * int64_t(block_dim);
-    int32_t end = start + 1;
-    const int32_t row_cap = (int32_t)std::min<int64_t>(n_rows, int64_t(start) + block_dim);
-    const int64_t base = rp[start];
-    while (end < row_cap && int64_t(rp[end + 1]) - base <= budget) ++end;
-    groups->push_back(argcsr_group_info{start, end - start, 0, 0});
-    start = end;
-  }
-  return ARGCSR_OK;
+  return for_each_group(n_rows, rp, block_dim, desired, format, region_rows, region_desired,
+                        [groups](int32_t first, int32_t size) {
+                          groups->push_back(argcsr_group_info{first, size, 0, 0});
+                          return 0;
+                        });
 }
 
 int32_t longest_row(const int32_t* rp, int32_t first, int32_t size) {

@@ -24,6 +24,30 @@ int group_rows(int32_t n_rows, const int32_t* rp, int32_t block_dim,
                int32_t desired, int32_t format, std::vector<argcsr_group_info>* groups,
                int32_t region_rows = 0, const int32_t* region_desired = nullptr);
 
+// The scan of group_rows, handing each group to emit(first_row, size) in
+// row order; a nonzero return from emit stops the scan and is returned.
+template <class Emit>
+int for_each_group(int32_t n_rows, const int32_t* rp, int32_t block_dim, int32_t desired,
+                   int32_t format, int32_t region_rows, const int32_t* region_desired,
+                   Emit&& emit) {
+  const bool rg = format == ARGCSR_FORMAT_RG;
+  int32_t start = 0;
+  while (start < n_rows) {
+    // extend the group from `start` as far as both limits allow (at least one row)
+    const int32_t d = region_desired ? region_desired[start / region_rows] : desired;
+    const int64_t budget = rg ? INT64_MAX / 2 : int64_t(d) * int64_t(block_dim);
+    int32_t end = start + 1;
+    const int64_t cap = int64_t(start) + block_dim;
+    const int32_t row_cap = cap < n_rows ? int32_t(cap) : n_rows;
+    const int64_t base = rp[start];
+    while (end < row_cap && int64_t(rp[end + 1]) - base <= budget) ++end;
+    const int rc = emit(start, end - start);
+    if (rc) return rc;
+    start = end;
+  }
+  return 0;
+}
+
 // Checks a region table: region_rows >= 1 and every entry >= 1.
 int check_regions(int32_t n_rows, int32_t region_rows, const int32_t* region_desired);
 
