@@ -279,14 +279,18 @@ def test_serve_budget_eviction_and_errors(srv_mod):
 
 
 def test_serve_admissions_wait_under_memory_pressure(srv_mod):
-    """A budget that holds about two of the eight matrices: every request is
-    preceded by its ADMIT (a no-op when resident), admissions evict matrices
-    that no running request uses and wait while running requests hold the
-    memory, and every request completes, oracle-checked."""
+    """A budget of 6 MiB, about half of the 11.6 MB the eight matrices take
+    when all are resident (the largest needs 3.6 MB while it is converted),
+    and every matrix is used: every request is preceded by its ADMIT (a no-op
+    when resident), admissions must evict matrices that no running request
+    uses and wait while running requests hold the memory, and every request
+    completes, oracle-checked."""
     print("\n[gpu] serve memory pressure", flush=True)
+    budget = 6 << 20
     mats = pool(8, 1e4, 3e4)
     reqs = make_requests(mats, 40, 21)
-    with srv_mod.Server(budget_bytes=16 << 20, max_active=4) as srv:
+    assert len({m for _, m, _ in reqs}) == len(mats)
+    with srv_mod.Server(budget_bytes=budget, max_active=4) as srv:
         tickets = []
         for kind, m, inp in reqs:
             A = mats[m]
@@ -305,7 +309,7 @@ def test_serve_admissions_wait_under_memory_pressure(srv_mod):
                 assert true_relres(mats[m], out, inp) <= 1e-10
         st = srv.stats()
         assert st["failed"] == 0 and st["completed"] == len(reqs)
-        assert st["evictions"] > 0 and st["resident_bytes"] <= 16 << 20
+        assert st["evictions"] > 0 and st["resident_bytes"] <= budget
 
 
 def test_serve_rejects_wrong_vector_lengths(srv_mod):
