@@ -47,11 +47,16 @@ DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_amd/csrc/spmv.hip",
                   "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp",
-                  "paper_1203_5737_amd/csrc/schedule.hpp"]
+                  "paper_1203_5737_amd/csrc/schedule.hpp",
+                  "paper_1203_5737_amd/csrc/spmv_staged.hpp", "paper_1203_5737_amd/csrc/stage.hpp"]
 # (block_dim, desired_chunk_size) per workload unless given on the command line
 DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (128, 27), "laplace64": (64, 1),
                   "mixed": (64, 1)}
 DEFAULT_REGION_ROWS = {"mixed": 4096}
+# block_dim of the staged 27-point stencil per value type (x tiles in LDS,
+# gap 0; a sweep of T in {64, 128, 256} and both ways of reading x on the
+# MI355X picked these)
+STAGED_STENCIL_T = {"f64": 64, "f32": 128, "bf16": 128, "f16": 128}
 ALL_LEGS = ("stencil27", "batch", "serve", "ceilings")
 
 
@@ -310,8 +315,27 @@ def leg_stencil27(torch, ac, timer, steps):
             rec["csr_gbps"] = B / (c.mean() * 1e-3) / 1e9
             rec["csr_lanes_per_row"] = V
             rec["speedup_vs_csr"] = float(c.mean() / t.mean())
+        # x staged per group in LDS, 16-bit positions instead of columns
+        Ts = STAGED_STENCIL_T[name]
+        if Ts != T:
+            del M
+            M = ac.convert(dev, Ts, D, dtype)
+        Ms = ac.stage(M, gap=0, lds=True, keep_columns=False)
+        fs = lambda: ac.spmv(Ms, xd, yd)
+        timer.run(fs, 3)
+        ts, _ = timer.run(fs, steps)
+        gs = B / (ts.mean() * 1e-3) / 1e9
+        rec["staged"] = stats(ts) | {
+            "block_dim": Ts, "gap": 0, "x_in_lds": True, "gbps": gs, "frac": gs / HBM_PEAK_GBPS,
+            "max_group_tiles": Ms.stage_max_tiles, "tiles": Ms.n_stage_tiles,
+            "format_bytes_staged": Ms.n_slots * (VALUE_BYTES[dtype] + 2),
+            "speedup_vs_plain": float(t.mean() / ts.mean()),
+            "traffic": traffic_for("stencil27-staged", name, Ts, D),
+            "error_vs_fp64": error_vs_fp64(A, x, yd.cpu().numpy())}
+        if "csr_gbps" in rec:
+            rec["staged"]["speedup_vs_csr"] = gs / rec["csr_gbps"]
         out[name] = rec
-        del M, xd, yd
+        del M, Ms, xd, yd
     del dev
     torch.cuda.empty_cache()
     return out
@@ -601,6 +625,10 @@ def main():
     ap.add_argument("--budget-frac", type=float, default=0.4,
                     help="serve: budget as a fraction of the used matrices' device footprint")
     ap.add_argument("--max-active", type=int, default=64, help="serve: requests per step")
+    ap.add_argument("--stage-gap", type=int, default=-1,
+                    help="stage x per group with this window gap (-1: no staging)")
+    ap.add_argument("--stage-lds", type=int, default=1,
+                    help="staged SpMV reads x from LDS (1) or gathers it through the tile table (0)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -662,6 +690,12 @@ def main():
     yd = torch.empty(A.n_rows, dtype=vdt, device="cuda")
     B = useful_bytes(A, dtype)
     Bf = format_bytes(M, dtype)
+    staging = None
+    if args.stage_gap >= 0:
+        M = ac.stage(M, gap=args.stage_gap, lds=bool(args.stage_lds))
+        staging = {"gap": args.stage_gap, "x_in_lds": bool(args.stage_lds),
+                   "max_group_tiles": M.stage_max_tiles, "tiles": M.n_stage_tiles}
+    traffic_key = args.workload + ("-staged" if staging else "")
 
     timer = Timer(torch, cold=not args.warm)
     spmv = lambda: ac.spmv(M, xd, yd)
@@ -682,7 +716,7 @@ def main():
                    "timing": "warm" if args.warm else "cold (1 GiB flush before each step, untimed)"},
         "roofline": {"bound": "hbm", "achieved": round(gbps, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_for(args.workload, args.dtype, T, D)},
+                     "traffic": traffic_for(traffic_key, args.dtype, T, D)},
         "spmv": stats(ms) | {"gflops": 2 * A.nnz / mean_s / 1e9, "useful_bytes": B,
                              "format_bytes": Bf, "padding_ratio": M.n_slots / max(A.nnz, 1),
                              "n_groups": M.n_groups, "wall_ms_per_step": wall * 1e3 / args.steps},
@@ -691,6 +725,8 @@ def main():
         "kernel_hash": kernel_source_hash(),
         "error_vs_fp64": error_vs_fp64(A, x, yd.cpu().numpy()),
     }
+    if staging:
+        out["staging"] = staging
 
     if not args.no_extras:
         log("extras: warm, plain CSR, FP32, row-grouped")

@@ -117,6 +117,29 @@ typedef struct {
    * argcsr_convert only. */
   int32_t region_rows;
   const int32_t* region_desired;
+  /* Staging of x (optional; an extension of the format for banded
+   * matrices, made by argcsr_stage_plan + argcsr_stage).  With local != NULL
+   * argcsr_spmv reads each slot's 16-bit position in its group's staged
+   * tiles of x instead of its column (columns may then be NULL for
+   * argcsr_spmv; batches and the server use columns and ignore staging):
+   *   tile_ptr[n_groups+1]        first tile of each group (exclusive scan)
+   *   tile_start[n_stage_tiles]   first column of each tile
+   *   tile_len[n_stage_tiles]     columns in each tile, 1..64
+   *   local[n_slots]              64*q + (column - tile_start[tile_ptr[g]+q])
+   *                               for the group's q-th tile, 0xFFFF for an
+   *                               artificial zero
+   * stage_gap is the window gap the tiles were made with, stage_max_tiles
+   * the largest group's tile count (it sizes the SpMV's LDS), stage_lds
+   * selects how the SpMV reads x: 1 = the group's tiles are loaded into LDS
+   * first, 0 = x is gathered from memory at tile_start + position. */
+  int32_t stage_gap;
+  int32_t n_stage_tiles;
+  int32_t stage_max_tiles;
+  int32_t stage_lds;
+  int32_t* tile_ptr;
+  int32_t* tile_start;
+  int32_t* tile_len;
+  uint16_t* local;
 } argcsr_matrix;
 
 /* Message describing the calling thread's most recent failure ("" if none). */
@@ -274,6 +297,44 @@ int argcsr_csr_spmv(int32_t n_rows, int32_t n_cols, int64_t nnz,
                     const int32_t* row_ptr, const int32_t* col, const void* val,
                     int32_t dtype, int32_t lanes_per_row, const void* x, void* y,
                     void* stream);
+
+/* ---- staging of x for banded matrices --------------------------------- */
+
+/*
+ * Sec. 4 has each block stage in shared memory the data its threads reuse.
+ * In a banded matrix (a stencil, a finite-difference operator) the rows of a
+ * group name a few runs of consecutive columns, so the part of x a group
+ * reads is small and can be staged the same way.  Per group, the distinct
+ * columns its slots name are merged into windows (neighbouring columns stay
+ * in one window when at most `gap` columns between them are absent) and
+ * every window is cut into tiles of 64 consecutive columns (the last one
+ * shorter); each slot then holds a 16-bit position in the group's tiles.
+ * A group may need at most 64 tiles and its columns may span at most 2^18
+ * columns (the staging marks them in a bitmap in LDS); a matrix with a
+ * group beyond either limit is not staged (ARGCSR_EUNSUPPORTED).
+ */
+
+/*
+ * argcsr_stage_plan -- the tile count of every group of a converted matrix.
+ *   A          converted matrix (groups and columns on the device)
+ *   gap        >= 0, absent columns bridged inside one window
+ *   tile_ptr   device int32[n_groups+1], out: first tile of each group
+ *   n_tiles    out: total tiles; max_group_tiles out (may be NULL): the
+ *              largest group's count
+ * Synchronous.  Errors: EINVAL, EUNSUPPORTED (a group beyond the limits),
+ * ENOMEM, EHIP.
+ */
+int argcsr_stage_plan(const argcsr_matrix* A, int32_t gap, int32_t* tile_ptr,
+                      int32_t* n_tiles, int32_t* max_group_tiles, void* stream);
+
+/*
+ * argcsr_stage -- fills tile_start, tile_len and local of A (device buffers
+ * of n_stage_tiles, n_stage_tiles and n_slots entries) from A's groups and
+ * columns, with A->stage_gap and the tile_ptr that argcsr_stage_plan made
+ * for that gap.  Synchronous.  Errors: EINVAL (tile_ptr not from the plan of
+ * this gap, NULL buffers), EUNSUPPORTED, ENOMEM, EHIP.
+ */
+int argcsr_stage(argcsr_matrix* A, void* stream);
 
 /* ---- many matrices in one launch -------------------------------------- */
 

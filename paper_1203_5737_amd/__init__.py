@@ -23,7 +23,7 @@ from ._lib import (BF16, F16, F32, F64, FORMAT_ARG, FORMAT_RG, ArgCsrError, Matr
                    TuneResult, check, lib)
 
 __all__ = ["F64", "F32", "BF16", "F16", "ArgCsrError", "ArgCsrMatrix", "DeviceCsr",
-           "plan", "convert", "spmv", "csr_spmv", "to_device_csr", "storage_dtype",
+           "plan", "convert", "stage", "spmv", "csr_spmv", "to_device_csr", "storage_dtype",
            "vector_dtype", "Batch", "autotune", "autotune_clear_cache"]
 
 _STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}
@@ -94,19 +94,34 @@ class ArgCsrMatrix:
     n_heavy: int = 0
     heavy_chunk: int = 0
     format: int = FORMAT_ARG                      # FORMAT_ARG or FORMAT_RG
+    # staging of x (stage()): positions in the group's tiles replace columns
+    stage_gap: int = -1
+    stage_max_tiles: int = 0
+    stage_lds: int = 1
+    tile_ptr: Optional[torch.Tensor] = None       # int32 [n_groups+1]
+    tile_start: Optional[torch.Tensor] = None     # int32 [n_tiles]
+    tile_len: Optional[torch.Tensor] = None       # int32 [n_tiles]
+    local: Optional[torch.Tensor] = None          # int16 bits of uint16 [n_slots]
+
+    @property
+    def n_stage_tiles(self) -> int:
+        return 0 if self.tile_start is None else int(self.tile_start.numel())
 
     def desc(self) -> MatrixDesc:
         return MatrixDesc(self.n_rows, self.n_cols, self.block_dim, self.desired_chunk_size,
                           self.dtype, self.n_groups, self.nnz, self.n_slots,
                           _ptr(self.groups), _ptr(self.threads_mapping), _ptr(self.columns),
                           _ptr(self.values), self.n_heavy, self.heavy_chunk,
-                          _ptr(self.heavy_groups), self.format, 0, None)
+                          _ptr(self.heavy_groups), self.format, 0, None,
+                          self.stage_gap, self.n_stage_tiles, self.stage_max_tiles,
+                          self.stage_lds, _ptr(self.tile_ptr), _ptr(self.tile_start),
+                          _ptr(self.tile_len),
+                          _ptr(self.local) if self.local is not None else ctypes.c_void_p(0))
 
     def nbytes(self) -> int:
-        ts = [self.groups, self.threads_mapping, self.columns, self.values]
-        if self.heavy_groups is not None:
-            ts.append(self.heavy_groups)
-        return sum(t.numel() * t.element_size() for t in ts)
+        ts = [self.groups, self.threads_mapping, self.columns, self.values, self.heavy_groups,
+              self.tile_ptr, self.tile_start, self.tile_len, self.local]
+        return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
 def plan(row_ptr_host, block_dim: int, desired_chunk_size: int, fmt: int = FORMAT_ARG):
@@ -208,6 +223,33 @@ def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
     out.heavy_chunk = int(d.heavy_chunk)
     if not schedule:
         out.n_heavy = 0
+    return out
+
+
+def stage(A: ArgCsrMatrix, gap: int = 0, lds: bool = True, stream=None,
+          keep_columns: bool = True) -> ArgCsrMatrix:
+    """Staging of x for banded matrices (argcsr_stage_plan + argcsr_stage):
+    returns a matrix sharing A's arrays plus the group tile tables and the
+    16-bit positions that argcsr_spmv then reads instead of the columns.
+    `lds` selects how the SpMV reads x (the group's tiles loaded into LDS
+    first, or gathered from memory through the tile table); without
+    `keep_columns` the result drops its reference to the column array."""
+    dev = A.groups.device
+    tile_ptr = torch.empty(A.n_groups + 1, dtype=torch.int32, device=dev)
+    d = A.desc()
+    nt, mx = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib().argcsr_stage_plan(ctypes.byref(d), int(gap), _ptr(tile_ptr), ctypes.byref(nt),
+                                  ctypes.byref(mx), _stream(stream)), "argcsr_stage_plan")
+    out = ArgCsrMatrix(**{f: getattr(A, f) for f in A.__dataclass_fields__})
+    out.stage_gap, out.stage_max_tiles, out.stage_lds = int(gap), int(mx.value), int(bool(lds))
+    out.tile_ptr = tile_ptr
+    out.tile_start = torch.empty(nt.value, dtype=torch.int32, device=dev)
+    out.tile_len = torch.empty(nt.value, dtype=torch.int32, device=dev)
+    out.local = torch.empty(A.n_slots, dtype=torch.int16, device=dev)
+    d = out.desc()
+    check(lib().argcsr_stage(ctypes.byref(d), _stream(stream)), "argcsr_stage")
+    if not keep_columns:
+        out.columns = torch.empty(0, dtype=torch.int32, device=dev)
     return out
 
 

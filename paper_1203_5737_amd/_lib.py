@@ -45,7 +45,11 @@ class MatrixDesc(ctypes.Structure):
                 ("n_heavy", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
                 ("heavy_groups", ctypes.c_void_p),
                 ("format", ctypes.c_int32), ("region_rows", ctypes.c_int32),
-                ("region_desired", ctypes.c_void_p)]
+                ("region_desired", ctypes.c_void_p),
+                ("stage_gap", ctypes.c_int32), ("n_stage_tiles", ctypes.c_int32),
+                ("stage_max_tiles", ctypes.c_int32), ("stage_lds", ctypes.c_int32),
+                ("tile_ptr", ctypes.c_void_p), ("tile_start", ctypes.c_void_p),
+                ("tile_len", ctypes.c_void_p), ("local", ctypes.c_void_p)]
 
 
 class TuneResult(ctypes.Structure):
@@ -101,6 +105,9 @@ SIGNATURES = {
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_convert_noalloc": (ctypes.c_int, [i32, i32, vp, vp, vp, vp,
                                               ctypes.POINTER(MatrixDesc), vp]),
+    "argcsr_stage_plan": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), i32, vp, ctypes.POINTER(i32),
+                                         ctypes.POINTER(i32), vp]),
+    "argcsr_stage": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),
     "argcsr_csr_spmv": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, vp, vp, vp]),
     "argcsr_batch_create": (ctypes.c_int, [i32, ctypes.POINTER(MatrixDesc), ctypes.POINTER(vp),

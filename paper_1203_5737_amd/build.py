@@ -27,6 +27,7 @@ SOURCES = [
     "tune.cpp",
     "serve.hip",
     "probes.hip",
+    "stage.hip",
 ]
 
 ARCH = "gfx950"

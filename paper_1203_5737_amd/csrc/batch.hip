@@ -159,6 +159,8 @@ int build_batch(int32_t n, const argcsr_matrix* mats, const void* const* xs, voi
       return fail(ARGCSR_EINVAL, "matrix %d has dtype %d, batch dtype is %d", m, A.dtype, b->dtype);
     if (A.n_groups > 0 && (!xs[m] || !ys[m]))
       return fail(ARGCSR_EINVAL, "matrix %d: x or y is NULL", m);
+    if (A.n_groups > 0 && !A.columns)
+      return fail(ARGCSR_EINVAL, "matrix %d: a batch reads columns (staging is not used)", m);
     hm[m] = BatchMat{A.groups, A.threads_mapping, A.columns, A.values, xs[m], ys[m],
                      A.block_dim, A.n_groups, A.n_cols,
                      serial_gathers(A.dtype == ARGCSR_F64 ? 8 : A.dtype == ARGCSR_F32 ? 4 : 2,

@@ -22,6 +22,7 @@
 
 #include "common.hpp"
 #include "spmv_kernels.hpp"
+#include "spmv_staged.hpp"
 
 namespace argcsr {
 namespace {
@@ -42,12 +43,44 @@ void launch(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
       A->heavy_groups, n_heavy, heavy_chunk, serial ? 1 : 0);
 }
 
+template <int DT, int W, int U, bool XLDS>
+int launch_staged(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
+  using Vt = Val<DT>;
+  const bool sched = A->heavy_groups != nullptr && A->n_heavy > 0;
+  const int32_t n_heavy = sched ? A->n_heavy : 0;
+  const int32_t heavy_chunk = sched ? A->heavy_chunk : INT32_MAX;
+  const int blocks = n_heavy + (A->n_groups + kSpmvWaves - 1) / kSpmvWaves;
+  const int32_t lds_tiles = A->stage_max_tiles > 0 ? A->stage_max_tiles : 1;
+  const size_t lds = size_t(kSpmvWaves) * staged_region_bytes<DT, W, XLDS>(lds_tiles);
+  auto* kern = &argcsr_spmv_staged_kernel<DT, W, U, XLDS>;
+  if (lds > 64 * 1024)
+    ARGCSR_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  kern<<<blocks, kSpmvWaves * 64, lds, s>>>(
+      A->groups, A->n_groups, A->threads_mapping, A->local,
+      static_cast<const typename Vt::storage*>(A->values), A->tile_ptr, A->tile_start,
+      A->tile_len, lds_tiles,
+      static_cast<const typename Vt::acc*>(x), A->n_cols, static_cast<typename Vt::acc*>(y),
+      A->heavy_groups, n_heavy, heavy_chunk);
+  return ARGCSR_OK;
+}
+
+template <int DT, int W, int U>
+int launch_w(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
+  if (!A->local) {
+    launch<DT, W, U>(A, x, y, s);
+    return ARGCSR_OK;
+  }
+  return A->stage_lds ? launch_staged<DT, W, U, true>(A, x, y, s)
+                      : launch_staged<DT, W, U, false>(A, x, y, s);
+}
+
 template <int DT>
-void launch_dt(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
+int launch_dt(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
   switch (A->block_dim) {
-    case 64: launch<DT, 1, 8>(A, x, y, s); break;
-    case 128: launch<DT, 2, 4>(A, x, y, s); break;
-    default: launch<DT, 4, 2>(A, x, y, s); break;
+    case 64: return launch_w<DT, 1, 8>(A, x, y, s);
+    case 128: return launch_w<DT, 2, 4>(A, x, y, s);
+    default: return launch_w<DT, 4, 2>(A, x, y, s);
   }
 }
 
@@ -66,8 +99,15 @@ int check_matrix(const argcsr_matrix* A) {
   if (int64_t(A->n_cols) * (A->dtype == ARGCSR_F64 ? 8 : 4) > kMaxVectorBytes)
     return fail(ARGCSR_EUNSUPPORTED, "x of %d columns exceeds the %lld-byte gather range",
                 A->n_cols, (long long)kMaxVectorBytes);
-  if (A->n_groups > 0 && (!A->groups || !A->threads_mapping || !A->columns || !A->values))
+  if (A->n_groups > 0 && (!A->groups || !A->threads_mapping || !A->values ||
+                          (!A->columns && !A->local)))
     return fail(ARGCSR_EINVAL, "NULL device buffer in matrix descriptor");
+  if (A->local) {
+    if (A->n_stage_tiles < 0 || A->stage_max_tiles < 0 || A->stage_max_tiles > kStageMaxTiles)
+      return fail(ARGCSR_EINVAL, "malformed staging sizes");
+    if (!A->tile_ptr || (A->n_stage_tiles > 0 && (!A->tile_start || !A->tile_len)))
+      return fail(ARGCSR_EINVAL, "NULL staging buffer in matrix descriptor");
+  }
   if (A->heavy_groups && (A->n_heavy < 0 || A->n_heavy > A->n_groups ||
                           A->heavy_chunk != heavy_chunk_for(A->block_dim, A->n_slots,
                                                             A->n_groups)))
@@ -87,11 +127,12 @@ extern "C" int argcsr_spmv(const argcsr_matrix* A, const void* x, void* y, void*
   if (x == y) return fail(ARGCSR_EINVAL, "y must not alias x");
   hipStream_t s = static_cast<hipStream_t>(stream);
   switch (A->dtype) {
-    case ARGCSR_F64: launch_dt<ARGCSR_F64>(A, x, y, s); break;
-    case ARGCSR_F32: launch_dt<ARGCSR_F32>(A, x, y, s); break;
-    case ARGCSR_BF16: launch_dt<ARGCSR_BF16>(A, x, y, s); break;
-    default: launch_dt<ARGCSR_F16>(A, x, y, s); break;
+    case ARGCSR_F64: rc = launch_dt<ARGCSR_F64>(A, x, y, s); break;
+    case ARGCSR_F32: rc = launch_dt<ARGCSR_F32>(A, x, y, s); break;
+    case ARGCSR_BF16: rc = launch_dt<ARGCSR_BF16>(A, x, y, s); break;
+    default: rc = launch_dt<ARGCSR_F16>(A, x, y, s); break;
   }
+  if (rc) return rc;
   ARGCSR_HIP(hipGetLastError());
   return ARGCSR_OK;
 }

@@ -240,3 +240,54 @@ def test_probes_reject_bad_arguments(L):
     assert _lib.PROBE_SINK == 16384
     hdr = open(os.path.join(ROOT, "include", "argcsr.h")).read()
     assert "#define ARGCSR_PROBE_SINK 16384" in hdr
+
+
+# -- packed FP32 ------------------------------------------------------------
+
+LLVM_OBJDUMP = "/opt/rocm/llvm/bin/llvm-objdump"
+PACKED_FP32 = re.compile(r"\bv_pk_(fma|add|mul)_f32\b")
+
+
+def _device_asm(src_text, flags, tmp_path):
+    from paper_1203_5737_amd import build
+    src = tmp_path / "probe.hip"
+    src.write_text(src_text)
+    r = subprocess.run([build.HIPCC, *flags, "-S", "--cuda-device-only", str(src), "-o",
+                        str(tmp_path / "probe.s")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return (tmp_path / "probe.s").read_text()
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="needs hipcc")
+def test_build_flags_keep_packed_fp32_out(tmp_path):
+    """The build's feature flag works on the device pass (the warning about it
+    comes from the host pass): ordinary float2 code that hipcc -O3 turns into
+    v_pk_fma_f32 without the flag gets none with the build's flags."""
+    from paper_1203_5737_amd import build
+    src = ("#include <hip/hip_runtime.h>\n"
+           "__global__ void k(const float2* a, const float2* b, float2* c) {\n"
+           "  int i = threadIdx.x + blockIdx.x * blockDim.x; float2 x = a[i], y = b[i];\n"
+           "  c[i] = make_float2(x.x * y.x + 1.5f, x.y * y.y + 1.5f); }\n")
+    plain = [f"--offload-arch={build.ARCH}", "-O3", "-x", "hip"]
+    assert PACKED_FP32.search(_device_asm(src, plain, tmp_path)), "probe no longer packs"
+    assert not PACKED_FP32.search(_device_asm(src, build.FLAGS, tmp_path))
+
+
+@pytest.mark.skipif(not os.path.exists(LLVM_OBJDUMP), reason="needs llvm-objdump")
+def test_built_library_has_no_packed_fp32(L, tmp_path):
+    """No v_pk_{fma,add,mul}_f32 in the gfx950 code objects of the built
+    library (disassembled from the offload bundles of libargcsr.so)."""
+    import shutil
+    from paper_1203_5737_amd import _lib
+    lib = tmp_path / "lib.so"
+    shutil.copy(_lib.LIB_PATH, lib)
+    subprocess.run([LLVM_OBJDUMP, "--offloading", str(lib)], cwd=tmp_path, check=True,
+                   capture_output=True)
+    objs = sorted(p for p in tmp_path.iterdir() if "amdgcn" in p.name)
+    assert objs, "no device code objects found"
+    for o in objs:
+        asm = subprocess.run([LLVM_OBJDUMP, "-d", "--mcpu=gfx950", str(o)], capture_output=True,
+                             text=True).stdout
+        assert "s_endpgm" in asm or not asm.strip()
+        hit = PACKED_FP32.search(asm)
+        assert not hit, f"{o.name}: {hit.group(0)}"
