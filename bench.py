@@ -48,7 +48,9 @@ VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
 KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_amd/csrc/spmv.hip",
                   "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp",
                   "paper_1203_5737_amd/csrc/schedule.hpp",
-                  "paper_1203_5737_amd/csrc/spmv_staged.hpp", "paper_1203_5737_amd/csrc/stage.hpp"]
+                  "paper_1203_5737_amd/csrc/spmv_staged.hpp", "paper_1203_5737_amd/csrc/stage.hpp",
+                  "paper_1203_5737_amd/csrc/batch.hip", "paper_1203_5737_amd/csrc/workqueue.hpp",
+                  "paper_1203_5737_amd/csrc/tune.cpp"]
 # (block_dim, desired_chunk_size) per workload unless given on the command line
 DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (128, 27), "laplace64": (64, 1),
                   "mixed": (64, 1)}
@@ -287,6 +289,28 @@ def f32_variant(A, x, dev, timer, torch, ac, steps):
 # legs of the default run
 # ---------------------------------------------------------------------------
 
+def tuned_record(ac, dev, dtype, xd, yd, timer, steps):
+    """What argcsr_autotune picks for the matrix (4 finalists timed cold by
+    the tuner), converted and timed here the same way as the fixed choice."""
+    r = ac.autotune(dev, dtype, n_finalists=4)
+    M = ac.convert(dev, r["block_dim"], r["desired_chunk_size"], dtype, fmt=r["format"])
+    f = lambda: ac.spmv(M, xd, yd)
+    timer.run(f, 3)
+    t, _ = timer.run(f, steps)
+    B = useful_bytes_of(dev, dtype)
+    return stats(t) | {"block_dim": r["block_dim"], "desired_chunk_size": r["desired_chunk_size"],
+                       "format": "row-grouped" if r["format"] else "ARG-CSR",
+                       "tuner_median_us": r["measured_us"], "model_us": r["model_us"],
+                       "candidates_timed": r["n_timed"],
+                       "gbps": B / (t.mean() * 1e-3) / 1e9}
+
+
+def useful_bytes_of(dev, dtype: int) -> int:
+    sv = VALUE_BYTES[dtype]
+    sx = 8 if dtype == 0 else 4
+    return dev.nnz * (sv + 4) + dev.n_rows * (4 + sx) + dev.n_cols * sx
+
+
 def leg_stencil27(torch, ac, timer, steps):
     """27-point stencil 128^3 (T=128, D=27) in every value type, cold, with
     the error against FP64 and plain CSR (FP64) beside it."""
@@ -315,6 +339,7 @@ def leg_stencil27(torch, ac, timer, steps):
             rec["csr_gbps"] = B / (c.mean() * 1e-3) / 1e9
             rec["csr_lanes_per_row"] = V
             rec["speedup_vs_csr"] = float(c.mean() / t.mean())
+            rec["tuned"] = tuned_record(ac, dev, dtype, xd, yd, timer, steps)
         # x staged per group in LDS, 16-bit positions instead of columns
         Ts = STAGED_STENCIL_T[name]
         if Ts != T:
@@ -376,6 +401,7 @@ def batch_record(torch, ac, count, dtype, steps, warmup, cold=True, extras=True)
            "n_mats": count, "n_rows": sum(A.n_rows for A, _ in mats), "nnz": nnz,
            "value_dtype": DTYPE_NAMES[dtype], "useful_bytes": B, "gbps": gbps,
            "frac": gbps / HBM_PEAK_GBPS, "steps": steps,
+           "traffic": traffic_for("batch", DTYPE_NAMES[dtype], "auto", "auto"),
            "spmv": stats(ms) | {"gflops": 2 * nnz / (ms.mean() * 1e-3) / 1e9,
                                 "wall_ms_per_step": wall * 1e3 / steps} | batch.info(),
            "error_vs_fp64": {"max_scaled": max(e["max_scaled"] for e in errs),
@@ -580,7 +606,7 @@ def run_batch(args, torch, ac):
                       "value_dtype": args.dtype,
                       "timing": "warm" if args.warm else "cold (1 GiB flush before each step, untimed)"},
            "roofline": {"bound": "hbm", "achieved": round(rec["gbps"], 2), "peak": HBM_PEAK_GBPS,
-                        "unit": "GB/s", "frac": round(rec["frac"], 4), "traffic": None},
+                        "unit": "GB/s", "frac": round(rec["frac"], 4), "traffic": rec["traffic"]},
            "batch": rec, "kernel_hash": kernel_source_hash()}
     print(json.dumps(out))
 
@@ -741,6 +767,9 @@ def main():
         out["speedup_vs_csr"] = gbps / csr_gbps
         if dtype == 0 and args.workload == "powerlaw":
             out["f32"] = f32_variant(A, x, dev, timer, torch, ac, args.steps)
+        if regions is None:
+            log("extras: autotuned choice")
+            out["tuned"] = tuned_record(ac, dev, dtype, xd, yd, timer, args.steps)
         if regions is not None:
             # the same matrix with one desiredChunkSize for every row
             out["uniform_desired"] = {}

@@ -383,7 +383,8 @@ typedef struct {
   int32_t block_dim;           /* chosen T */
   int32_t desired_chunk_size;  /* chosen D (0 for ARGCSR_FORMAT_RG) */
   double model_us;             /* cost-model estimate of one SpMV */
-  double measured_us;          /* mean of timed SpMVs (warm caches); < 0 if not timed */
+  double measured_us;          /* median of timed SpMVs, each after a cache flush
+                                  (cold, as in a batch); < 0 if not timed */
   int32_t from_cache;          /* 1 if the choice came from the process cache */
   int32_t n_candidates;        /* candidates planned */
   int32_t n_timed;             /* candidates converted and timed */
@@ -395,10 +396,13 @@ typedef struct {
  * matrix.  The paper makes desiredChunkSize the key, matrix-dependent
  * parameter, block size 128 its best on its GPU, and advises trying more
  * than one format, row-grouped CSR winning on finite-difference matrices
- * (Sec. 5).  Every ARG-CSR pair in {64,128,256} x {1,2,4,8,16,32,64} and
- * row-grouped CSR at {64,128,256} (24 candidates) is sized with
+ * (Sec. 5).  Every ARG-CSR pair in {64,128,256} x {1,2,4,8,16,32,64, the
+ * longest and the mean row length when at most 64} and row-grouped CSR at
+ * {64,128,256} (24 to 30 candidates) is sized with
  * argcsr_plan, ranked by a cost model (padded bytes, group count, long
- * groups), and the best n_finalists are converted and timed on `stream`.
+ * groups), and the best n_finalists are converted and timed on `stream`,
+ * each launch after a 512 MiB read-modify-write that evicts the caches
+ * (the median of 7 decides).
  * The choice is cached for the process under a signature of the row-length
  * distribution.
  *   arguments as for argcsr_convert; dtype is the value storage type

@@ -115,7 +115,7 @@ def test_autotune_times_finalists(ac):
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
     r = ac.autotune(dev, ac.F64, n_finalists=3)
     assert r["n_timed"] == 3 and r["measured_us"] > 0 and r["from_cache"] == 0
-    assert r["block_dim"] in (64, 128, 256) and r["n_candidates"] == 24
+    assert r["block_dim"] in (64, 128, 256) and 24 <= r["n_candidates"] <= 30
     assert r["format"] in (ac.FORMAT_ARG, ac.FORMAT_RG)
     assert r["desired_chunk_size"] >= 1 or r["format"] == ac.FORMAT_RG
     r2 = ac.autotune(dev, ac.F64, n_finalists=3)
