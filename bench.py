@@ -263,6 +263,15 @@ def best_csr(ac, timer, dev, xd, yd, vals, dtype, steps, lanes=(0, 1, 2, 4, 8, 1
     return V, t
 
 
+def binned_csr(ac, timer, dev, xd, yd, vals, dtype, steps):
+    """Plain CSR with rows binned by length, a lane count per bin."""
+    bins = ac.csr_bins(dev)
+    f = lambda: ac.csr_spmv_binned(dev, xd, bins, yd, values=vals, dtype=dtype)
+    timer.run(f, 3)
+    t, _ = timer.run(f, steps)
+    return t, [int(v) for v in np.diff(bins.bin_start)]
+
+
 def f32_variant(A, x, dev, timer, torch, ac, steps):
     """The same matrix with FP32 values, x and y (T=128, D=1), against plain
     CSR in FP32, timed the same way."""
@@ -275,13 +284,16 @@ def f32_variant(A, x, dev, timer, torch, ac, steps):
     t, _ = timer.run(f, steps)
     vals = dev.val.to(torch.float32)
     V, c = best_csr(ac, timer, dev, xd, yd, vals, 1, max(10, steps // 2), (8, 16, 32, 64))
+    cb, _ = binned_csr(ac, timer, dev, xd, yd, vals, 1, max(10, steps // 2))
     ac.spmv(M, xd, yd)
     err = error_vs_fp64(A, x, yd.cpu().numpy())
     gbps = B / (t.mean() * 1e-3) / 1e9
     return {"block_dim": 128, "desired_chunk_size": 1, "mean_ms": float(t.mean()),
             "gbps": gbps, "frac": gbps / HBM_PEAK_GBPS,
             "csr_gbps": B / (c.mean() * 1e-3) / 1e9,
-            "csr_lanes_per_row": V, "speedup_vs_csr": float(c.mean() / t.mean()),
+            "csr_binned_gbps": B / (cb.mean() * 1e-3) / 1e9,
+            "csr_lanes_per_row": V,
+            "speedup_vs_csr": float(min(c.mean(), cb.mean()) / t.mean()),
             "error_vs_fp64": err}
 
 
@@ -336,8 +348,11 @@ def leg_stencil27(torch, ac, timer, steps):
                           "error_vs_fp64": error_vs_fp64(A, x, yd.cpu().numpy())}
         if dtype == 0:
             V, c = best_csr(ac, timer, dev, xd, yd, dev.val, 0, steps, (4, 8, 16, 32))
+            cb, _ = binned_csr(ac, timer, dev, xd, yd, dev.val, 0, steps)
             rec["csr_gbps"] = B / (c.mean() * 1e-3) / 1e9
+            rec["csr_binned_gbps"] = B / (cb.mean() * 1e-3) / 1e9
             rec["csr_lanes_per_row"] = V
+            c = c if c.mean() <= cb.mean() else cb
             rec["speedup_vs_csr"] = float(c.mean() / t.mean())
             rec["tuned"] = tuned_record(ac, dev, dtype, xd, yd, timer, steps)
         # x staged per group in LDS, 16-bit positions instead of columns
@@ -358,7 +373,7 @@ def leg_stencil27(torch, ac, timer, steps):
             "traffic": traffic_for("stencil27-staged", name, Ts, D),
             "error_vs_fp64": error_vs_fp64(A, x, yd.cpu().numpy())}
         if "csr_gbps" in rec:
-            rec["staged"]["speedup_vs_csr"] = gs / rec["csr_gbps"]
+            rec["staged"]["speedup_vs_csr"] = gs / max(rec["csr_gbps"], rec["csr_binned_gbps"])
         out[name] = rec
         del M, Ms, xd, yd
     del dev
@@ -422,7 +437,14 @@ def batch_record(torch, ac, count, dtype, steps, warmup, cold=True, extras=True)
         timer.run(csr, 2)
         t, _ = timer.run(csr, max(5, steps // 4))
         rec["csr_loop"] = stats(t) | {"gbps": B / (t.mean() * 1e-3) / 1e9}
-        rec["speedup_vs_csr_loop"] = rec["csr_loop"]["mean_ms"] / float(ms.mean())
+        bins = [ac.csr_bins(d) for d in devs]
+        binned = lambda: [ac.csr_spmv_binned(d, x, b, y, values=v, dtype=dtype)
+                          for d, x, y, v, b in zip(devs, xs, ys, vals, bins)]
+        timer.run(binned, 2)
+        tb, _ = timer.run(binned, max(5, steps // 4))
+        rec["csr_binned_loop"] = stats(tb) | {"gbps": B / (tb.mean() * 1e-3) / 1e9}
+        rec["speedup_vs_csr_loop"] = (min(rec["csr_loop"]["mean_ms"],
+                                          rec["csr_binned_loop"]["mean_ms"]) / float(ms.mean()))
     batch.close()
     del Ms, devs, xs, ys
     torch.cuda.empty_cache()
@@ -764,7 +786,11 @@ def main():
         V, t = best_csr(ac, timer, dev, xd, yd, vals, dtype, args.steps)
         csr_gbps = B / (t.mean() * 1e-3) / 1e9
         out["csr"] = stats(t) | {"gbps": csr_gbps, "lanes_per_row": V}
-        out["speedup_vs_csr"] = gbps / csr_gbps
+        tb, counts = binned_csr(ac, timer, dev, xd, yd, vals, dtype, args.steps)
+        binned_gbps = B / (tb.mean() * 1e-3) / 1e9
+        out["csr_binned"] = stats(tb) | {"gbps": binned_gbps, "rows_per_bin": counts}
+        # against the better of the two plain-CSR kernels
+        out["speedup_vs_csr"] = gbps / max(csr_gbps, binned_gbps)
         if dtype == 0 and args.workload == "powerlaw":
             out["f32"] = f32_variant(A, x, dev, timer, torch, ac, args.steps)
         if regions is None:

@@ -211,6 +211,43 @@ int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim
                        int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
                        int64_t* n_slots, int32_t* n_heavy, void* stream);
 
+/* A device plan: steps 1-3 of Sec. 3 (groups with their chunk sizes, the
+ * threads mapping) of one matrix, kept in device memory the library owns,
+ * so that a caller with row_ptr on the device only sizes and converts the
+ * matrix without grouping its rows twice. */
+typedef struct argcsr_device_plan argcsr_device_plan;
+
+/*
+ * argcsr_plan_device_keep -- argcsr_plan_device that keeps its steps 1-3 in
+ * *plan for argcsr_convert_planned (free it with argcsr_device_plan_destroy).
+ * The plan holds 16 bytes per group and 4 per row of device memory.
+ *   arguments as for argcsr_plan_device; plan out (NULL on error)
+ * Synchronous.  Errors: as argcsr_plan_device.
+ */
+int argcsr_plan_device_keep(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
+                            int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
+                            int64_t* n_slots, int32_t* n_heavy, argcsr_device_plan** plan,
+                            void* stream);
+
+/*
+ * argcsr_convert_planned -- argcsr_convert of the planned matrix: copies the
+ * plan's groups and threads mapping into out's buffers and runs step 4
+ * (offsets, launch schedule, fill) only.  The result equals argcsr_convert's
+ * byte for byte.
+ *   plan     from argcsr_plan_device_keep on the same row_ptr
+ *   out      as for argcsr_convert; n_rows, block_dim, desired_chunk_size,
+ *            format, n_groups and n_slots must be the plan's (EINVAL
+ *            otherwise); no region table
+ *   row_ptr, col, val, stream as for argcsr_convert (row_ptr_host is not used)
+ * Synchronous.  Errors: as argcsr_convert.
+ */
+int argcsr_convert_planned(const argcsr_device_plan* plan, int32_t n_cols, const int32_t* row_ptr,
+                           const int32_t* col, const double* val, argcsr_matrix* out,
+                           void* stream);
+
+/* Frees a device plan (NULL is a no-op).  No conversion may be running with it. */
+int argcsr_device_plan_destroy(argcsr_device_plan* plan);
+
 /*
  * argcsr_convert -- CSR -> ARG-CSR on the GPU (Sec. 3, all four steps).
  * Steps 2-4 (chunk size, threads mapping, offsets, fill) run as HIP kernels
@@ -297,6 +334,40 @@ int argcsr_csr_spmv(int32_t n_rows, int32_t n_cols, int64_t nnz,
                     const int32_t* row_ptr, const int32_t* col, const void* val,
                     int32_t dtype, int32_t lanes_per_row, const void* x, void* y,
                     void* stream);
+
+/* Plain CSR with rows binned by length (still the Sec. 2 definition and
+ * the CSR arrays alone, plus a row list): bin k = 0..6 holds the rows with
+ * 2^(k-1) < L <= 2^k nonzeros (bin 0: L <= 1), bin 7 the rows longer than
+ * 64; argcsr_csr_spmv_binned gives bin k < 7 2^k lanes per row (each such
+ * row summed exactly as argcsr_csr_spmv with lanes_per_row = 2^k) and each
+ * row of bin 7 a workgroup of 256 lanes, all in one launch. */
+#define ARGCSR_CSR_BINS 8
+
+/*
+ * argcsr_csr_bin_rows -- the binning.
+ *   row_ptr    device int32[n_rows+1] (non-decreasing; not checked)
+ *   rows       device int32[n_rows], out: row indices bin by bin, ascending
+ *              within a bin
+ *   bin_start  host int32[ARGCSR_CSR_BINS+1], out: bin k's rows are
+ *              rows[bin_start[k] .. bin_start[k+1])
+ * Synchronous; uses stream-ordered scratch of 32 bytes per 256 rows.
+ * Errors: EINVAL, EHIP.
+ */
+int argcsr_csr_bin_rows(int32_t n_rows, const int32_t* row_ptr, int32_t* rows,
+                        int32_t* bin_start, void* stream);
+
+/*
+ * argcsr_csr_spmv_binned -- y = A x over the binned rows.
+ *   rows, bin_start  as made by argcsr_csr_bin_rows for this row_ptr (rows
+ *                    is trusted: every entry must be a row index, as the
+ *                    column indices must be valid for argcsr_csr_spmv)
+ *   other arguments as for argcsr_csr_spmv
+ * Asynchronous on `stream`.  Errors: EINVAL, EHIP.
+ */
+int argcsr_csr_spmv_binned(int32_t n_rows, int32_t n_cols, int64_t nnz,
+                           const int32_t* row_ptr, const int32_t* col, const void* val,
+                           int32_t dtype, const int32_t* rows, const int32_t* bin_start,
+                           const void* x, void* y, void* stream);
 
 /* ---- staging of x for banded matrices --------------------------------- */
 

@@ -23,7 +23,8 @@ from ._lib import (BF16, F16, F32, F64, FORMAT_ARG, FORMAT_RG, ArgCsrError, Matr
                    TuneResult, check, lib)
 
 __all__ = ["F64", "F32", "BF16", "F16", "ArgCsrError", "ArgCsrMatrix", "DeviceCsr",
-           "plan", "convert", "stage", "spmv", "csr_spmv", "to_device_csr", "storage_dtype",
+           "plan", "convert", "stage", "spmv", "csr_spmv", "csr_bins", "csr_spmv_binned",
+           "to_device_csr", "storage_dtype",
            "vector_dtype", "Batch", "autotune", "autotune_clear_cache"]
 
 _STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}
@@ -176,49 +177,74 @@ def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, 
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
             dtype: int = F64, stream=None, schedule: bool = True,
             device_grouping: bool = False, fmt: int = FORMAT_ARG, region_rows: int = 0,
-            region_desired=None, noalloc: bool = False) -> ArgCsrMatrix:
+            region_desired=None, noalloc: bool = False, keep_plan: bool = True) -> ArgCsrMatrix:
     """CSR -> ARG-CSR (or, with fmt=FORMAT_RG, row-grouped CSR) on the GPU
     (argcsr_convert); allocates the result.  `schedule` also builds the
     heavy-group launch schedule.  With `device_grouping` step 1 runs on the
-    device and the host copy of row_ptr is not used (argcsr_plan_device,
-    row_ptr_host = NULL).  `region_desired` (with `region_rows`) gives
-    ARG-CSR a desiredChunkSize per region of rows (argcsr_plan_regions; the
-    sizes are planned on the host).  `noalloc` converts with
-    argcsr_convert_noalloc (the library allocates no device memory; the
-    result tensors are still allocated here, as the caller's outputs)."""
+    device and the host copy of row_ptr is not used: steps 1-3 run once,
+    kept on the device between sizing and conversion (argcsr_plan_device_keep
+    + argcsr_convert_planned), or, without `keep_plan`, twice
+    (argcsr_plan_device, then argcsr_convert with row_ptr_host = NULL).
+    `region_desired` (with `region_rows`) gives ARG-CSR a desiredChunkSize
+    per region of rows (argcsr_plan_regions; the sizes are planned on the
+    host).  `noalloc` converts with argcsr_convert_noalloc (the library
+    allocates no device memory; the result tensors are still allocated here,
+    as the caller's outputs)."""
     if noalloc and device_grouping:
         raise ValueError("argcsr_convert_noalloc groups the rows on the host")
     if fmt == FORMAT_RG:
         desired_chunk_size = 0
     regions = None
+    plan_h = None
     if region_desired is not None:
         regions = np.ascontiguousarray(np.asarray(region_desired, dtype=np.int32))
         desired_chunk_size = 0
         G, S, H = plan_regions(A.row_ptr_host, block_dim, region_rows, regions)
+    elif device_grouping and keep_plan:
+        if A.row_ptr.dtype != torch.int32 or not A.row_ptr.is_contiguous():
+            raise ValueError("row_ptr must be a contiguous int32 device tensor")
+        g, s_, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
+        plan_h = ctypes.c_void_p(0)
+        check(lib().argcsr_plan_device_keep(A.n_rows, _ptr(A.row_ptr), int(block_dim),
+                                            int(desired_chunk_size), int(fmt), ctypes.byref(g),
+                                            ctypes.byref(s_), ctypes.byref(h),
+                                            ctypes.byref(plan_h), _stream(stream)),
+              "argcsr_plan_device_keep")
+        G, S, H = g.value, s_.value, h.value
     elif device_grouping:
         G, S, H = plan_device(A.row_ptr, block_dim, desired_chunk_size, stream, fmt)
     else:
         G, S, H = plan(A.row_ptr_host, block_dim, desired_chunk_size, fmt)
-    dev = A.row_ptr.device
-    out = ArgCsrMatrix(
-        A.n_rows, A.n_cols, int(block_dim), int(desired_chunk_size), int(dtype), G, A.nnz, S,
-        torch.empty((G, 4), dtype=torch.int32, device=dev),
-        torch.empty(A.n_rows, dtype=torch.int32, device=dev),
-        torch.empty(S, dtype=torch.int32, device=dev),
-        torch.empty(S, dtype=_STORAGE[dtype], device=dev),
-        torch.empty(H, dtype=torch.int32, device=dev) if schedule else None,
-        H if schedule else 0, 0, int(fmt))
-    d = out.desc()
-    if schedule and H == 0:
-        d.heavy_groups = None
-    if regions is not None:
-        d.region_rows = int(region_rows)
-        d.region_desired = regions.ctypes.data_as(ctypes.c_void_p)
-    rp_host = None if device_grouping else A.row_ptr_host.ctypes.data_as(ctypes.c_void_p)
-    fn, name = ((lib().argcsr_convert_noalloc, "argcsr_convert_noalloc") if noalloc
-                else (lib().argcsr_convert, "argcsr_convert"))
-    check(fn(A.n_rows, A.n_cols, rp_host, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val),
-             ctypes.byref(d), _stream(stream)), name)
+    try:
+        dev = A.row_ptr.device
+        out = ArgCsrMatrix(
+            A.n_rows, A.n_cols, int(block_dim), int(desired_chunk_size), int(dtype), G, A.nnz, S,
+            torch.empty((G, 4), dtype=torch.int32, device=dev),
+            torch.empty(A.n_rows, dtype=torch.int32, device=dev),
+            torch.empty(S, dtype=torch.int32, device=dev),
+            torch.empty(S, dtype=_STORAGE[dtype], device=dev),
+            torch.empty(H, dtype=torch.int32, device=dev) if schedule else None,
+            H if schedule else 0, 0, int(fmt))
+        d = out.desc()
+        if schedule and H == 0:
+            d.heavy_groups = None
+        if regions is not None:
+            d.region_rows = int(region_rows)
+            d.region_desired = regions.ctypes.data_as(ctypes.c_void_p)
+        if plan_h is not None:
+            check(lib().argcsr_convert_planned(plan_h, A.n_cols, _ptr(A.row_ptr), _ptr(A.col),
+                                               _ptr(A.val), ctypes.byref(d), _stream(stream)),
+                  "argcsr_convert_planned")
+        else:
+            rp_host = (None if device_grouping
+                       else A.row_ptr_host.ctypes.data_as(ctypes.c_void_p))
+            fn, name = ((lib().argcsr_convert_noalloc, "argcsr_convert_noalloc") if noalloc
+                        else (lib().argcsr_convert, "argcsr_convert"))
+            check(fn(A.n_rows, A.n_cols, rp_host, _ptr(A.row_ptr), _ptr(A.col), _ptr(A.val),
+                     ctypes.byref(d), _stream(stream)), name)
+    finally:
+        if plan_h is not None:
+            lib().argcsr_device_plan_destroy(plan_h)
     out.nnz = int(d.nnz)
     out.heavy_chunk = int(d.heavy_chunk)
     if not schedule:
@@ -290,6 +316,52 @@ def csr_spmv(A: DeviceCsr, x: torch.Tensor, y: Optional[torch.Tensor] = None,
     check(lib().argcsr_csr_spmv(A.n_rows, A.n_cols, A.nnz, _ptr(A.row_ptr), _ptr(A.col),
                                 _ptr(vals), int(dtype), int(lanes_per_row), _ptr(x), _ptr(y),
                                 _stream(stream)), "argcsr_csr_spmv")
+    return y
+
+
+@dataclass
+class CsrBins:
+    """Rows of a CSR matrix grouped by length (argcsr_csr_bin_rows)."""
+    rows: torch.Tensor           # device int32 [n_rows], bin by bin
+    bin_start: np.ndarray        # host int32 [CSR_BINS + 1]
+
+
+def csr_bins(A: DeviceCsr, stream=None) -> CsrBins:
+    """Bins A's rows by length for csr_spmv_binned (argcsr_csr_bin_rows)."""
+    rows = torch.empty(A.n_rows, dtype=torch.int32, device=A.row_ptr.device)
+    start = np.zeros(_lib_mod.CSR_BINS + 1, dtype=np.int32)
+    check(lib().argcsr_csr_bin_rows(A.n_rows, _ptr(A.row_ptr), _ptr(rows),
+                                    start.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+          "argcsr_csr_bin_rows")
+    return CsrBins(rows, start)
+
+
+def csr_spmv_binned(A: DeviceCsr, x: torch.Tensor, bins: CsrBins,
+                    y: Optional[torch.Tensor] = None, values: Optional[torch.Tensor] = None,
+                    dtype: int = F64, stream=None) -> torch.Tensor:
+    """Plain CSR y = A x with a lane count per row-length bin
+    (argcsr_csr_spmv_binned); arguments as for csr_spmv."""
+    vals = A.val if values is None else values
+    if dtype not in _STORAGE:
+        raise ValueError(f"unknown dtype {dtype}")
+    if vals.dtype != _STORAGE[dtype] or not vals.is_contiguous() or vals.numel() != A.nnz:
+        raise ValueError(f"values must be a contiguous {_STORAGE[dtype]} vector of length {A.nnz}")
+    want = vector_dtype(dtype)
+    if x.dtype != want or not x.is_contiguous() or x.numel() != A.n_cols:
+        raise ValueError(f"x must be a contiguous {want} vector of length {A.n_cols}")
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=want, device=x.device)
+    elif y.dtype != want or not y.is_contiguous() or y.numel() != A.n_rows:
+        raise ValueError(f"y must be a contiguous {want} vector of length {A.n_rows}")
+    if y.data_ptr() == x.data_ptr() and x.numel() > 0:
+        raise ValueError("y must not alias x")
+    if bins.rows.numel() != A.n_rows or bins.rows.dtype != torch.int32:
+        raise ValueError("bins were not made for this matrix")
+    st = np.ascontiguousarray(bins.bin_start, dtype=np.int32)
+    check(lib().argcsr_csr_spmv_binned(A.n_rows, A.n_cols, A.nnz, _ptr(A.row_ptr), _ptr(A.col),
+                                       _ptr(vals), int(dtype), _ptr(bins.rows),
+                                       st.ctypes.data_as(ctypes.c_void_p), _ptr(x), _ptr(y),
+                                       _stream(stream)), "argcsr_csr_spmv_binned")
     return y
 
 

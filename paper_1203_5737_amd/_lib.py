@@ -15,6 +15,7 @@ OK, EINVAL, EOVERFLOW, ENOMEM, EHIP, EBUDGET, EBUSY, ENOTFOUND, EUNSUPPORTED, EN
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 PENDING = 1
 PROBE_SINK = 16384                    # ARGCSR_PROBE_SINK
+CSR_BINS = 8                          # ARGCSR_CSR_BINS
 REQ_ADMIT, REQ_SPMV, REQ_CG, REQ_EVICT = 0, 1, 2, 3
 F64, F32, BF16, F16 = 0, 1, 2, 3
 FORMAT_ARG, FORMAT_RG = 0, 1          # argcsr_format
@@ -103,6 +104,12 @@ SIGNATURES = {
     "argcsr_plan_device": (ctypes.c_int, [i32, vp, i32, i32, i32, ctypes.POINTER(i32),
                                           ctypes.POINTER(i64), ctypes.POINTER(i32), vp]),
     "argcsr_convert": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, ctypes.POINTER(MatrixDesc), vp]),
+    "argcsr_plan_device_keep": (ctypes.c_int, [i32, vp, i32, i32, i32, ctypes.POINTER(i32),
+                                               ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                               ctypes.POINTER(vp), vp]),
+    "argcsr_convert_planned": (ctypes.c_int, [vp, i32, vp, vp, vp, ctypes.POINTER(MatrixDesc),
+                                              vp]),
+    "argcsr_device_plan_destroy": (ctypes.c_int, [vp]),
     "argcsr_convert_noalloc": (ctypes.c_int, [i32, i32, vp, vp, vp, vp,
                                               ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_stage_plan": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), i32, vp, ctypes.POINTER(i32),
@@ -110,6 +117,9 @@ SIGNATURES = {
     "argcsr_stage": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp]),
     "argcsr_spmv": (ctypes.c_int, [ctypes.POINTER(MatrixDesc), vp, vp, vp]),
     "argcsr_csr_spmv": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, i32, vp, vp, vp]),
+    "argcsr_csr_bin_rows": (ctypes.c_int, [i32, vp, vp, vp, vp]),
+    "argcsr_csr_spmv_binned": (ctypes.c_int, [i32, i32, i64, vp, vp, vp, i32, vp, vp, vp, vp,
+                                              vp]),
     "argcsr_batch_create": (ctypes.c_int, [i32, ctypes.POINTER(MatrixDesc), ctypes.POINTER(vp),
                                            ctypes.POINTER(vp), ctypes.POINTER(vp)]),
     "argcsr_batch_graph_launch": (ctypes.c_int, [vp, vp]),

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "common.hpp"
@@ -452,6 +453,20 @@ void launch_fill(int32_t n_groups, hipStream_t s, const int32_t* rp, const int32
 }  // namespace
 }  // namespace argcsr
 
+// A device plan (argcsr_plan_device_keep): steps 1-3 of one matrix kept on
+// the device for argcsr_convert_planned.
+struct argcsr_device_plan {
+  int32_t n_rows = 0, block_dim = 0, desired_chunk_size = 0, format = 0;
+  int32_t n_groups = 0, n_heavy = 0;
+  int64_t n_slots = 0;
+  argcsr_group_info* groups = nullptr;    // first_row, size, chunk_size (offset not yet set)
+  int32_t* tm = nullptr;                  // threads mapping
+  ~argcsr_device_plan() {
+    if (groups) (void)hipFree(groups);
+    if (tm) (void)hipFree(tm);
+  }
+};
+
 // Fixed scratch of argcsr_convert_noalloc: one copy per GPU (this process's
 // code object), held until the process ends.  Host code reaches it only
 // through the address hipGetSymbolAddress returns for the current device.
@@ -513,7 +528,9 @@ int noalloc_scratch(void** out) {
 // g_group_chunk; nothing is allocated.
 int convert_impl(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
                  const int32_t* row_ptr, const int32_t* col, const double* val,
-                 argcsr_matrix* out, hipStream_t s, bool fixed) {
+                 argcsr_matrix* out, hipStream_t s, bool fixed,
+                 const argcsr_device_plan* planned = nullptr,
+                 const argcsr_group_info* pregrouped = nullptr) {
   if (!out) return fail(ARGCSR_EINVAL, "out is NULL");
   if (n_rows < 0 || n_cols < 0) return fail(ARGCSR_EINVAL, "negative dimension");
   if (out->n_rows != n_rows || out->n_cols != n_cols)
@@ -547,7 +564,26 @@ int convert_impl(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
   int64_t nnz = 0;
   int32_t G = 0;
   bool groups_uploaded = false;
-  if (row_ptr_host) {
+  if (planned) {
+    // steps 1-3 were kept by argcsr_plan_device_keep
+    if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
+    G = planned->n_groups;
+    if (n_rows > 0) {
+      int32_t last = 0;
+      ARGCSR_HIP(hipMemcpyAsync(&last, row_ptr + n_rows, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      ARGCSR_HIP(hipStreamSynchronize(s));
+      nnz = last;
+    }
+  } else if (row_ptr_host && pregrouped) {
+    // step 1 done (and row_ptr_host validated) by the caller
+    nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
+    G = out->n_groups;
+    if (G > 0 && !out->groups) return fail(ARGCSR_EINVAL, "NULL device buffer");
+    if (G > 0)
+      ARGCSR_HIP(hipMemcpyAsync(out->groups, pregrouped, sizeof(argcsr_group_info) * size_t(G),
+                                hipMemcpyHostToDevice, s));
+    groups_uploaded = true;
+  } else if (row_ptr_host) {
     rc = check_row_ptr(n_rows, row_ptr_host);
     if (rc) return rc;
     nnz = n_rows > 0 ? row_ptr_host[n_rows] : 0;
@@ -630,18 +666,26 @@ int convert_impl(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
   const int32_t heavy_chunk = out->heavy_chunk;
 
   clear_status_kernel<<<1, 1, 0, s>>>(st);
-  if (row_ptr_host) {
-    if (!groups_uploaded)
-      ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
-                                sizeof(argcsr_group_info) * size_t(G), hipMemcpyHostToDevice, s));
+  if (planned) {
+    ARGCSR_HIP(hipMemcpyAsync(out->groups, planned->groups, sizeof(argcsr_group_info) * size_t(G),
+                              hipMemcpyDeviceToDevice, s));
+    ARGCSR_HIP(hipMemcpyAsync(out->threads_mapping, planned->tm, sizeof(int32_t) * size_t(n_rows),
+                              hipMemcpyDeviceToDevice, s));
   } else {
-    rc = device_groups.write(out->groups);
-    if (rc) return rc;
+    if (row_ptr_host) {
+      if (!groups_uploaded)
+        ARGCSR_HIP(hipMemcpyAsync(out->groups, host_groups.data(),
+                                  sizeof(argcsr_group_info) * size_t(G), hipMemcpyHostToDevice,
+                                  s));
+    } else {
+      rc = device_groups.write(out->groups);
+      if (rc) return rc;
+    }
+    const int wave_blocks = (G + kWaves - 1) / kWaves;
+    chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, out->groups, G, T,
+                                                     out->format == ARGCSR_FORMAT_RG ? 1 : 0,
+                                                     out->threads_mapping);
   }
-  const int wave_blocks = (G + kWaves - 1) / kWaves;
-  chunks_kernel<<<wave_blocks, kWaves * 64, 0, s>>>(row_ptr, out->groups, G, T,
-                                                   out->format == ARGCSR_FORMAT_RG ? 1 : 0,
-                                                   out->threads_mapping);
   ARGCSR_HIP(hipGetLastError());
   offsets_reduce_kernel<<<n_tiles, kScanBlock, 0, s>>>(out->groups, G, T, tile_sums);
   tiles_scan_kernel<<<1, kScanBlock, 0, s>>>(tile_sums, n_tiles, &st->total_slots);
@@ -683,6 +727,20 @@ int convert_impl(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
 }  // namespace
 }  // namespace argcsr
 
+namespace argcsr {
+
+int convert_pregrouped(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                       const argcsr_group_info* groups_host, const int32_t* row_ptr,
+                       const int32_t* col, const double* val, argcsr_matrix* out,
+                       hipStream_t s) {
+  if (!row_ptr_host || (out && out->n_groups > 0 && !groups_host))
+    return fail(ARGCSR_EINVAL, "a pregrouped conversion needs row_ptr_host and the groups");
+  return convert_impl(n_rows, n_cols, row_ptr_host, row_ptr, col, val, out, s, false, nullptr,
+                      groups_host);
+}
+
+}  // namespace argcsr
+
 extern "C" int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
                               const int32_t* row_ptr, const int32_t* col, const double* val,
                               argcsr_matrix* out, void* stream) {
@@ -700,11 +758,15 @@ extern "C" int argcsr_convert_noalloc(int32_t n_rows, int32_t n_cols, const int3
                               static_cast<hipStream_t>(stream), true);
 }
 
-extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
-                                  int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
-                                  int64_t* n_slots, int32_t* n_heavy, void* stream) {
-  using namespace argcsr;
-  clear_error();
+namespace argcsr {
+namespace {
+
+// Steps 1-3 from a device row_ptr; the sizes of the result.  With `keep`,
+// the group table and the threads mapping stay in device memory the plan
+// owns; otherwise they live in stream-ordered scratch and are dropped.
+int plan_device_impl(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
+                     int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
+                     int64_t* n_slots, int32_t* n_heavy, hipStream_t s, argcsr_device_plan* keep) {
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
   if (n_rows < 0) return fail(ARGCSR_EINVAL, "n_rows < 0");
   if (format != ARGCSR_FORMAT_ARG && format != ARGCSR_FORMAT_RG)
@@ -714,7 +776,6 @@ extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_
     return fail(ARGCSR_EINVAL, "block_dim must be in [1, %d] and desired_chunk_size >= 1",
                 kMaxBlockDim);
   if (n_rows > 0 && !row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   DeviceGrouping dg;
   int rc = dg.build(n_rows, row_ptr, block_dim, desired_chunk_size, format, s);
   if (rc) return rc;
@@ -723,16 +784,26 @@ extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_
   *n_slots = 0;
   if (n_heavy) *n_heavy = 0;
   if (G == 0) return ARGCSR_OK;
-  // steps 2-3 into scratch: the chunk sizes give the slot count and the
-  // heavy-group count exactly as argcsr_plan computes them on the host
+  // steps 2-3 (into the plan's buffers or scratch): the chunk sizes give the
+  // slot count and the heavy-group count exactly as argcsr_plan computes
+  // them on the host
   const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
-  const size_t groups_bytes = sizeof(argcsr_group_info) * size_t(G);
-  const size_t tm_bytes = (sizeof(int32_t) * size_t(n_rows) + 15) / 16 * 16;
+  const size_t groups_bytes = keep ? 0 : sizeof(argcsr_group_info) * size_t(G);
+  const size_t tm_bytes = keep ? 0 : (sizeof(int32_t) * size_t(n_rows) + 15) / 16 * 16;
   StreamScratch ws;
   rc = ws.alloc(groups_bytes + tm_bytes + sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), s);
   if (rc) return rc;
-  auto* groups = static_cast<argcsr_group_info*>(ws.ptr);
-  auto* tm = reinterpret_cast<int32_t*>(static_cast<char*>(ws.ptr) + groups_bytes);
+  argcsr_group_info* groups = static_cast<argcsr_group_info*>(ws.ptr);
+  int32_t* tm = reinterpret_cast<int32_t*>(static_cast<char*>(ws.ptr) + groups_bytes);
+  if (keep) {
+    if (hipMalloc(reinterpret_cast<void**>(&keep->groups), sizeof(argcsr_group_info) * size_t(G)) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&keep->tm), sizeof(int32_t) * size_t(n_rows)) !=
+            hipSuccess)
+      return fail(ARGCSR_ENOMEM, "device plan of %d groups could not be allocated", G);
+    groups = keep->groups;
+    tm = keep->tm;
+  }
   auto* st = reinterpret_cast<Status*>(static_cast<char*>(ws.ptr) + groups_bytes + tm_bytes);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
   int64_t* heavy_tiles = tile_sums + n_tiles;
@@ -758,5 +829,70 @@ extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_
   *n_slots = S;
   if (n_heavy) *n_heavy = int32_t(host_st.total_heavy);
   if (S > INT32_MAX) return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", (long long)S);
+  if (keep) {
+    keep->n_groups = G;
+    keep->n_slots = S;
+    keep->n_heavy = int32_t(host_st.total_heavy);
+  }
+  return ARGCSR_OK;
+}
+
+}  // namespace
+}  // namespace argcsr
+
+extern "C" int argcsr_plan_device(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
+                                  int32_t desired_chunk_size, int32_t format, int32_t* n_groups,
+                                  int64_t* n_slots, int32_t* n_heavy, void* stream) {
+  argcsr::clear_error();
+  return argcsr::plan_device_impl(n_rows, row_ptr, block_dim, desired_chunk_size, format,
+                                  n_groups, n_slots, n_heavy, static_cast<hipStream_t>(stream),
+                                  nullptr);
+}
+
+extern "C" int argcsr_plan_device_keep(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
+                                       int32_t desired_chunk_size, int32_t format,
+                                       int32_t* n_groups, int64_t* n_slots, int32_t* n_heavy,
+                                       argcsr_device_plan** plan, void* stream) {
+  using namespace argcsr;
+  clear_error();
+  if (!plan) return fail(ARGCSR_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  auto* p = new (std::nothrow) argcsr_device_plan();
+  if (!p) return fail(ARGCSR_ENOMEM, "device plan");
+  p->n_rows = n_rows;
+  p->block_dim = block_dim;
+  p->desired_chunk_size = format == ARGCSR_FORMAT_RG ? 0 : desired_chunk_size;
+  p->format = format;
+  const int rc = plan_device_impl(n_rows, row_ptr, block_dim, desired_chunk_size, format,
+                                  n_groups, n_slots, n_heavy, static_cast<hipStream_t>(stream), p);
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *plan = p;
+  return ARGCSR_OK;
+}
+
+extern "C" int argcsr_convert_planned(const argcsr_device_plan* plan, int32_t n_cols,
+                                      const int32_t* row_ptr, const int32_t* col,
+                                      const double* val, argcsr_matrix* out, void* stream) {
+  using namespace argcsr;
+  clear_error();
+  if (!plan || !out) return fail(ARGCSR_EINVAL, "plan or out is NULL");
+  if (out->n_rows != plan->n_rows || out->block_dim != plan->block_dim ||
+      out->format != plan->format || out->n_groups != plan->n_groups ||
+      out->n_slots != plan->n_slots ||
+      (plan->format == ARGCSR_FORMAT_ARG && out->desired_chunk_size != plan->desired_chunk_size))
+    return fail(ARGCSR_EINVAL, "out does not describe the planned matrix");
+  if (out->region_desired) return fail(ARGCSR_EINVAL, "a device plan has one desired_chunk_size");
+  if (out->heavy_groups && out->n_heavy != plan->n_heavy)
+    return fail(ARGCSR_EINVAL, "out->n_heavy = %d but the plan has %d", out->n_heavy,
+                plan->n_heavy);
+  return convert_impl(plan->n_rows, n_cols, nullptr, row_ptr, col, val, out,
+                      static_cast<hipStream_t>(stream), false, plan);
+}
+
+extern "C" int argcsr_device_plan_destroy(argcsr_device_plan* plan) {
+  delete plan;
   return ARGCSR_OK;
 }

@@ -100,7 +100,7 @@ namespace {
 int plan_impl(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
               int32_t desired_chunk_size, int32_t format, int32_t region_rows,
               const int32_t* region_desired, int32_t* n_groups, int64_t* n_slots,
-              int32_t* n_heavy) {
+              int32_t* n_heavy, std::vector<argcsr_group_info>* keep = nullptr) {
   if (!n_groups || !n_slots) return fail(ARGCSR_EINVAL, "NULL output pointer");
   if (format != ARGCSR_FORMAT_ARG && format != ARGCSR_FORMAT_RG)
     return fail(ARGCSR_EINVAL, "unknown format %d", format);
@@ -112,7 +112,8 @@ int plan_impl(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
   if (rc) return rc;
   rc = check_regions(n_rows, region_rows, region_desired);
   if (rc) return rc;
-  std::vector<argcsr_group_info> groups;
+  std::vector<argcsr_group_info> own;
+  std::vector<argcsr_group_info>& groups = keep ? *keep : own;
   rc = group_rows(n_rows, row_ptr_host, block_dim, desired_chunk_size, format, &groups,
                   region_rows, region_desired);
   if (rc) return rc;
@@ -133,6 +134,8 @@ int plan_impl(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
   for (auto& th : pool) th.join();
   int64_t slots = 0;
   for (size_t g = 0; g < G; ++g) slots += int64_t(chunk[g]) * block_dim;
+  if (keep)
+    for (size_t g = 0; g < G; ++g) groups[g].chunk_size = chunk[g];
   const int32_t heavy_chunk = heavy_chunk_for(block_dim, slots, (int32_t)groups.size());
   int32_t heavy = 0;
   for (int32_t c : chunk) heavy += c > heavy_chunk;
@@ -145,6 +148,15 @@ int plan_impl(int32_t n_rows, const int32_t* row_ptr_host, int32_t block_dim,
 }
 
 }  // namespace
+
+int plan_host_groups(int32_t n_rows, const int32_t* rp, int32_t block_dim, int32_t desired,
+                     int32_t format, std::vector<argcsr_group_info>* groups, int64_t* n_slots,
+                     int32_t* n_heavy) {
+  int32_t G = 0;
+  return plan_impl(n_rows, rp, block_dim, desired, format, 0, nullptr, &G, n_slots, n_heavy,
+                   groups);
+}
+
 }  // namespace argcsr
 
 extern "C" int argcsr_plan(int32_t n_rows, const int32_t* row_ptr_host,

@@ -2,6 +2,8 @@
 // (grouping) and the chunk-size rule of step 2 used for sizing.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <vector>
 
@@ -47,6 +49,23 @@ int for_each_group(int32_t n_rows, const int32_t* rp, int32_t block_dim, int32_t
   }
   return 0;
 }
+
+// Steps 1-2 on the host, keeping the group table: first_row, size and
+// chunk_size of every group (offset left 0), with the slot and heavy-group
+// counts argcsr_plan reports.  Validates row_ptr.
+int plan_host_groups(int32_t n_rows, const int32_t* rp, int32_t block_dim, int32_t desired,
+                     int32_t format, std::vector<argcsr_group_info>* groups, int64_t* n_slots,
+                     int32_t* n_heavy);
+
+// argcsr_convert with step 1 already done on the host: groups_host holds
+// out->n_groups groups (first_row, size) in row order as group_rows or
+// plan_host_groups make them for out's parameters, from a row_ptr_host that
+// has been validated (it is not scanned again).  Synchronous, as
+// argcsr_convert.  (convert.hip)
+int convert_pregrouped(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
+                       const argcsr_group_info* groups_host, const int32_t* row_ptr,
+                       const int32_t* col, const double* val, argcsr_matrix* out,
+                       hipStream_t s);
 
 // Checks a region table: region_rows >= 1 and every entry >= 1.
 int check_regions(int32_t n_rows, int32_t region_rows, const int32_t* region_desired);

@@ -8,7 +8,12 @@
 //      used first, those no queued request names before the others) if the
 //      budget is short, and waiting, with every request behind it, while the
 //      matrix cannot fit until running requests end; SPMV/CG requests enter
-//      free slots as slots and memory allow;
+//      free slots as slots and memory allow.  The host side of an ADMIT
+//      (steps 1-2 of the conversion with the group table kept, and a copy of
+//      the CSR arrays into pinned staging) is done ahead by a preparation
+//      thread, so the scheduler itself only uploads the arrays and runs the
+//      conversion kernels; until the preparation is done the ADMIT waits at
+//      the head of the queue while running requests keep stepping;
 //   2. advances every active request by one step in a few launches for all
 //      of them together: a pull of the step's descriptors from mapped pinned
 //      memory, one multi-matrix ARG-CSR SpMV per precision (FP32 values for
@@ -136,6 +141,30 @@ enum ReqStatus : int32_t { kPending = 1 };
 // admit(): the matrix does not fit yet; memory frees up as running requests
 // end, so the ADMIT stays at the head of the queue and is tried again
 constexpr int kAdmitWait = 2;
+// admit(): the preparation thread has not finished the ADMIT's host side
+// yet; it stays at the head of the queue and is tried again
+constexpr int kAdmitPending = 3;
+
+// The host side of an ADMIT, done ahead of the scheduler by the preparation
+// thread: steps 1-2 of the conversion with the group table kept, and the CSR
+// arrays copied into pinned staging.  Shared by the request and the thread's
+// queue.  State: kQueued -> kRunning -> kReady by the thread; the scheduler
+// takes a kQueued one away (kAbandoned: the thread skips it) or waits for a
+// kRunning one, so the caller's arrays are never read after its ADMIT has
+// completed.
+struct AdmitPrep {
+  enum : int { kQueued = 0, kRunning = 1, kReady = 2, kAbandoned = 3 };
+  std::atomic<int> state{kQueued};
+  argcsr_request q{};
+  int32_t T = 0, D = 0;
+  bool found_resident = false;   // resident when the thread looked: nothing prepared
+  int rc = ARGCSR_OK;            // planning error, returned by the ADMIT
+  std::vector<argcsr_group_info> groups;
+  int64_t n_slots = 0;
+  int32_t n_heavy = 0;
+  void* stage = nullptr;         // pinned row_ptr | col | val, or NULL (upload from q's arrays)
+  size_t off_col = 0, off_val = 0;
+};
 
 struct Request {
   uint64_t ticket = 0;
@@ -157,6 +186,7 @@ struct Request {
   // ADMIT: sizes from argcsr_plan, kept while the ADMIT waits for memory
   int32_t plan_groups = -1, plan_heavy = 0;
   int64_t plan_slots = 0;
+  std::shared_ptr<AdmitPrep> prep;   // host side done ahead (see AdmitPrep)
   // pinned staging of the input (set by the copy helper when filled) and of
   // the result
   void* stage = nullptr;
@@ -211,6 +241,13 @@ struct argcsr_server {
   bool helper_stop = false;                  // guarded by hmu
   std::vector<argcsr::Request*> staging;     // scheduler: waiting for their input copy
   std::vector<void*> stage_release;          // scheduler: free after the next step's sync
+  // ADMIT preparation thread
+  std::thread preparer;
+  std::mutex pmu;
+  std::condition_variable pcv;
+  std::deque<std::shared_ptr<argcsr::AdmitPrep>> preps;   // guarded by pmu
+  bool preparer_stop = false;                              // guarded by pmu
+  std::unordered_map<int64_t, int32_t> resident_ids;       // resident matrices (mu)
 };
 
 namespace argcsr {
@@ -247,6 +284,7 @@ bool pinned(const argcsr_server* s, const Resident* m) {
 void evict(argcsr_server* s, Resident* m) {
   for (void* p : m->blocks) s->arena.release(p);
   std::lock_guard<std::mutex> lock(s->mu);
+  s->resident_ids.erase(m->id);
   s->stats.evictions++;
   s->stats.resident_matrices--;
   s->stats.resident_bytes -= int64_t(m->bytes);
@@ -295,25 +333,143 @@ bool memory_will_free(const argcsr_server* s) {
   return !s->active.empty() || !s->staging.empty();
 }
 
+// Conversion parameters of an ADMIT: the server's block_dim, and its
+// desired_chunk_size or else the mean row length in [1, 64].
+void admit_params(const argcsr_server_config& cfg, const argcsr_request& q, int64_t nnz,
+                  int32_t* T, int32_t* D) {
+  *T = cfg.block_dim > 0 ? cfg.block_dim : 64;
+  *D = cfg.desired_chunk_size;
+  if (*D <= 0) {
+    const double mean = q.n_rows > 0 ? double(nnz) / q.n_rows : 1.0;
+    *D = int32_t(std::min(64.0, std::max(1.0, std::round(mean))));
+  }
+}
+
+// Checks of an ADMIT's arguments that need no scan of row_ptr.
+int check_admit(const argcsr_request& q) {
+  if (q.n_rows < 0 || q.n_cols < 0) return fail(ARGCSR_EINVAL, "negative dimension");
+  if (q.n_rows > 0 && !q.row_ptr) return fail(ARGCSR_EINVAL, "row_ptr is NULL");
+  if (int64_t(q.n_cols) * 8 > kMaxVectorBytes)
+    return fail(ARGCSR_EUNSUPPORTED, "x of %d columns exceeds the gather range", q.n_cols);
+  return ARGCSR_OK;
+}
+
+// The preparation thread: for each ADMIT in submission order whose matrix
+// is not resident, steps 1-2 on the host (group table kept) and a copy of
+// the CSR arrays into pinned staging.
+void preparer(argcsr_server* s) {
+  for (;;) {
+    std::shared_ptr<AdmitPrep> p;
+    {
+      std::unique_lock<std::mutex> lock(s->pmu);
+      s->pcv.wait(lock, [&] { return s->preparer_stop || !s->preps.empty(); });
+      if (s->preps.empty()) return;
+      p = std::move(s->preps.front());
+      s->preps.pop_front();
+    }
+    int expected = AdmitPrep::kQueued;
+    if (!p->state.compare_exchange_strong(expected, AdmitPrep::kRunning)) continue;  // abandoned
+    const argcsr_request& q = p->q;
+    {
+      std::lock_guard<std::mutex> lock(s->mu);
+      p->found_resident = s->resident_ids.count(q.matrix_id) != 0;
+    }
+    if (!p->found_resident) {
+      p->rc = check_admit(q);
+      if (p->rc == ARGCSR_OK) {
+        p->rc = check_row_ptr(q.n_rows, q.row_ptr);
+        const int64_t nnz = p->rc == ARGCSR_OK && q.n_rows > 0 ? q.row_ptr[q.n_rows] : 0;
+        if (p->rc == ARGCSR_OK && nnz > 0 && (!q.col || !q.val))
+          p->rc = fail(ARGCSR_EINVAL, "NULL CSR arrays");
+        if (p->rc == ARGCSR_OK) {
+          admit_params(s->cfg, q, nnz, &p->T, &p->D);
+          p->rc = plan_host_groups(q.n_rows, q.row_ptr, p->T, p->D, ARGCSR_FORMAT_ARG,
+                                   &p->groups, &p->n_slots, &p->n_heavy);
+        }
+        if (p->rc == ARGCSR_OK) {
+          // row_ptr | col | val, each 256-byte aligned
+          auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+          const size_t rp_b = sizeof(int32_t) * size_t(q.n_rows + 1);
+          const size_t col_b = sizeof(int32_t) * size_t(nnz), val_b = sizeof(double) * size_t(nnz);
+          p->off_col = up(rp_b);
+          p->off_val = p->off_col + up(col_b);
+          p->stage = s->pinned.alloc(p->off_val + val_b);
+          if (p->stage) {
+            char* st = static_cast<char*>(p->stage);
+            std::memcpy(st, q.row_ptr, rp_b);
+            if (nnz > 0) {
+              std::memcpy(st + p->off_col, q.col, col_b);
+              std::memcpy(st + p->off_val, q.val, val_b);
+            }
+          }
+        }
+      }
+    }
+    p->state.store(AdmitPrep::kReady, std::memory_order_release);
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->cv_work.notify_one();
+  }
+}
+
+// Lets go of an ADMIT's preparation once the ADMIT is complete: a queued
+// one is abandoned, a running one waited for (it still reads the caller's
+// arrays), a ready one's staging freed.
+void drop_prep(argcsr_server* s, Request* r) {
+  AdmitPrep* p = r->prep.get();
+  if (!p) return;
+  int expected = AdmitPrep::kQueued;
+  if (!p->state.compare_exchange_strong(expected, AdmitPrep::kAbandoned)) {
+    while (p->state.load(std::memory_order_acquire) == AdmitPrep::kRunning)
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+    if (p->state.load(std::memory_order_acquire) == AdmitPrep::kReady) {
+      s->pinned.release(p->stage);
+      p->stage = nullptr;
+    }
+  }
+  r->prep.reset();
+}
+
 int admit(argcsr_server* s, Request* r) {
   const argcsr_request& q = r->q;
+  AdmitPrep* prep = r->prep.get();
   if (s->resident.count(q.matrix_id)) {
+    // nothing to convert; a preparation still reading the caller's arrays
+    // must finish first (the ADMIT completes when this returns)
+    if (prep) {
+      int expected = AdmitPrep::kQueued;
+      if (!prep->state.compare_exchange_strong(expected, AdmitPrep::kAbandoned)) {
+        if (expected == AdmitPrep::kRunning) return kAdmitPending;
+        s->pinned.release(prep->stage);           // kReady: its staging is ours to free
+        prep->stage = nullptr;
+      }
+      r->prep.reset();
+    }
     s->resident[q.matrix_id]->last_use = now_ns();
     return ARGCSR_OK;
   }
-  int rc = check_row_ptr(q.n_rows, q.row_ptr);
+  bool prepared = false;
+  if (prep) {
+    const int st = prep->state.load(std::memory_order_acquire);
+    if (st == AdmitPrep::kQueued || st == AdmitPrep::kRunning) return kAdmitPending;
+    if (st == AdmitPrep::kReady && !prep->found_resident) {
+      if (prep->rc) {
+        const int rc = prep->rc;
+        r->prep.reset();
+        return rc;
+      }
+      prepared = true;
+    }
+  }
+  int rc = check_admit(q);
   if (rc) return rc;
-  if (q.n_rows < 0 || q.n_cols < 0) return fail(ARGCSR_EINVAL, "negative dimension");
-  if (int64_t(q.n_cols) * 8 > kMaxVectorBytes)
-    return fail(ARGCSR_EUNSUPPORTED, "x of %d columns exceeds the gather range", q.n_cols);
+  if (!prepared) {
+    rc = check_row_ptr(q.n_rows, q.row_ptr);
+    if (rc) return rc;
+  }
   const int64_t nnz = q.n_rows > 0 ? q.row_ptr[q.n_rows] : 0;
   if (nnz > 0 && (!q.col || !q.val)) return fail(ARGCSR_EINVAL, "NULL CSR arrays");
-  int32_t T = s->cfg.block_dim > 0 ? s->cfg.block_dim : 64;
-  int32_t D = s->cfg.desired_chunk_size;
-  if (D <= 0) {
-    const double mean = q.n_rows > 0 ? double(nnz) / q.n_rows : 1.0;
-    D = int32_t(std::min(64.0, std::max(1.0, std::round(mean))));
-  }
+  int32_t T = 0, D = 0;
+  admit_params(s->cfg, q, nnz, &T, &D);
   auto m = std::make_unique<Resident>();
   m->id = q.matrix_id;
   argcsr_matrix& A = m->m64;
@@ -322,7 +478,11 @@ int admit(argcsr_server* s, Request* r) {
   A.block_dim = T;
   A.desired_chunk_size = D;
   A.dtype = ARGCSR_F64;
-  if (r->plan_groups < 0) {       // planned once, also when the ADMIT has to wait
+  if (prepared) {
+    r->plan_groups = int32_t(prep->groups.size());
+    r->plan_slots = prep->n_slots;
+    r->plan_heavy = prep->n_heavy;
+  } else if (r->plan_groups < 0) {       // planned once, also when the ADMIT has to wait
     rc = argcsr_plan(q.n_rows, q.row_ptr, T, D, ARGCSR_FORMAT_ARG, &r->plan_groups,
                      &r->plan_slots, &r->plan_heavy);
     if (rc) {
@@ -384,21 +544,36 @@ int admit(argcsr_server* s, Request* r) {
                 (long long)q.matrix_id, (long long)A.n_slots, s->arena.capacity());
   }
   rc = ARGCSR_OK;
-  if (hipMemcpyAsync(d_rp, q.row_ptr, sizeof(int32_t) * size_t(q.n_rows + 1),
+  // the CSR arrays: from the preparation's pinned staging (asynchronous
+  // DMA), or from the caller's memory
+  const char* st = prepared ? static_cast<const char*>(prep->stage) : nullptr;
+  const void* src_rp = st ? static_cast<const void*>(st) : q.row_ptr;
+  const void* src_col = st ? static_cast<const void*>(st + prep->off_col) : q.col;
+  const void* src_val = st ? static_cast<const void*>(st + prep->off_val) : q.val;
+  if (hipMemcpyAsync(d_rp, src_rp, sizeof(int32_t) * size_t(q.n_rows + 1),
                      hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-      (nnz > 0 && (hipMemcpyAsync(d_col, q.col, sizeof(int32_t) * size_t(nnz),
+      (nnz > 0 && (hipMemcpyAsync(d_col, src_col, sizeof(int32_t) * size_t(nnz),
                                   hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-                   hipMemcpyAsync(d_val, q.val, sizeof(double) * size_t(nnz),
+                   hipMemcpyAsync(d_val, src_val, sizeof(double) * size_t(nnz),
                                   hipMemcpyHostToDevice, s->stream) != hipSuccess)))
     rc = fail(ARGCSR_EHIP, "CSR upload failed");
   if (rc == ARGCSR_OK)
-    rc = argcsr_convert(q.n_rows, q.n_cols, q.row_ptr, d_rp, d_col, d_val, &A, s->stream);
+    rc = prepared ? convert_pregrouped(q.n_rows, q.n_cols, q.row_ptr, prep->groups.data(), d_rp,
+                                       d_col, d_val, &A, s->stream)
+                  : argcsr_convert(q.n_rows, q.n_cols, q.row_ptr, d_rp, d_col, d_val, &A,
+                                   s->stream);
   if (rc == ARGCSR_OK && A.n_slots > 0) {
     const int64_t blocks = std::min<int64_t>((A.n_slots + kVecBlock - 1) / kVecBlock, 8192);
     round_values_kernel<<<int(blocks), kVecBlock, 0, s->stream>>>(
         static_cast<const double*>(A.values), m->values32, A.n_slots);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
       rc = fail(ARGCSR_EHIP, "value rounding failed");
+  }
+  (void)hipStreamSynchronize(s->stream);          // the uploads have read the staging
+  if (prep) {
+    s->pinned.release(prep->stage);
+    prep->stage = nullptr;
+    r->prep.reset();
   }
   for (size_t i = resident_blocks; i < m->blocks.size(); ++i) s->arena.release(m->blocks[i]);
   m->blocks.resize(resident_blocks);
@@ -412,6 +587,7 @@ int admit(argcsr_server* s, Request* r) {
   m->last_use = now_ns();
   {
     std::lock_guard<std::mutex> lock(s->mu);
+    s->resident_ids[q.matrix_id] = 1;
     s->stats.admissions++;
     s->stats.resident_matrices++;
     s->stats.resident_bytes += int64_t(m->bytes);
@@ -850,11 +1026,12 @@ void scheduler(argcsr_server* s) {
         if (r->res.t_start_ns == 0) r->res.t_start_ns = now_ns();
         const bool was_resident = s->resident.count(r->q.matrix_id) != 0;
         const int rc = admit(s, r);
-        if (rc == kAdmitWait) {                 // requests behind it wait too (in order)
+        if (rc == kAdmitWait || rc == kAdmitPending) {   // requests behind it wait too (in order)
           admit_waiting = true;
           break;
         }
         s->pending.pop_front();
+        drop_prep(s, r);
         r->res.status = rc;
         r->res.iterations = (r->res.status == ARGCSR_OK && !was_resident) ? 1 : 0;
         publish(s, r);
@@ -945,6 +1122,7 @@ void scheduler(argcsr_server* s) {
     delete r;
   }
   for (Request* r : s->pending) {
+    drop_prep(s, r);                          // before the caller may free the arrays
     r->res.status = ARGCSR_ENOTFOUND;
     publish(s, r);
     delete r;
@@ -992,6 +1170,7 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
   }
   for (int32_t k = cfg->max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->helper = std::thread(copy_helper, s);
+  s->preparer = std::thread(preparer, s);
   s->worker = std::thread(scheduler, s);
   *out = s;
   return ARGCSR_OK;
@@ -1018,6 +1197,14 @@ extern "C" int argcsr_server_submit(argcsr_server* s, const argcsr_request* q, u
   if (q->kind == ARGCSR_REQ_SPMV || q->kind == ARGCSR_REQ_CG) {
     s->refs[q->matrix_id]++;
     s->stats.submitted++;
+  }
+  if (q->kind == ARGCSR_REQ_ADMIT) {
+    auto p = std::make_shared<AdmitPrep>();
+    p->q = *q;
+    r->prep = p;
+    std::lock_guard<std::mutex> plock(s->pmu);
+    s->preps.push_back(std::move(p));
+    s->pcv.notify_one();
   }
   s->incoming.push_back(r);
   *ticket = r->ticket;
@@ -1095,6 +1282,14 @@ extern "C" int argcsr_server_destroy(argcsr_server* s) {
     s->hcv.notify_all();
   }
   if (s->helper.joinable()) s->helper.join();
+  {
+    std::lock_guard<std::mutex> lock(s->pmu);    // the preparer drains its queue, then exits
+    s->preparer_stop = true;
+    s->pcv.notify_all();
+  }
+  if (s->preparer.joinable()) s->preparer.join();
+  for (auto& p : s->preps) s->pinned.release(p->stage);
+  s->preps.clear();
   for (Request* r : s->staging) {               // never started
     s->pinned.release(r->stage);
     r->res.status = ARGCSR_ENOTFOUND;

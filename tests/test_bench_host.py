@@ -60,6 +60,7 @@ def test_traffic_is_used_only_for_the_current_kernel():
     rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
     for key, kh, fetch, write in rows:
         wl, dt, T, D = key.split("/")
-        got = bench.traffic_for(wl, dt, int(T[1:]), int(D[1:]))
+        num = lambda v: int(v) if v.isdigit() else v          # "auto": the tuner's choice
+        got = bench.traffic_for(wl, dt, num(T[1:]), num(D[1:]))
         assert got == (int(fetch) + int(write) if kh == h else None)
     assert bench.traffic_for("powerlaw", "f64", 999, 1) is None

@@ -32,13 +32,14 @@ def announce(msg):
     print(f"\n[gpu] {msg}", flush=True)
 
 
-def compare_conversion(ac, A, T, D, dtype, device_grouping=False, fmt=0):
+def compare_conversion(ac, A, T, D, dtype, device_grouping=False, fmt=0, keep_plan=True):
     announce(f"convert n={A.n_rows} nnz={A.nnz} T={T} D={D} dtype={dtype} "
-             f"device_grouping={device_grouping} format={fmt}")
+             f"device_grouping={device_grouping} format={fmt} keep_plan={keep_plan}")
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
     if device_grouping:
         assert ac.plan_device(dev.row_ptr, T, D, fmt=fmt) == ac.plan(A.rp, T, D, fmt)
-    M = ac.convert(dev, T, D, dtype, device_grouping=device_grouping, fmt=fmt)
+    M = ac.convert(dev, T, D, dtype, device_grouping=device_grouping, fmt=fmt,
+                   keep_plan=keep_plan)
     if fmt == ac.FORMAT_RG:
         ref = oracle.rg_convert(A.rp, A.col, A.val, T, dtype)
     else:
@@ -268,6 +269,55 @@ def test_device_grouping_random(ac):
         assert np.array_equal(M.groups.cpu().numpy(), ref.groups), (i, T, D)
         assert np.array_equal(M.threads_mapping.cpu().numpy(), ref.tm)
         assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
+
+
+def test_device_grouping_without_kept_plan(ac):
+    """argcsr_convert with row_ptr_host = NULL groups the rows itself (the
+    path without a device plan): the same bytes as the oracle."""
+    A, _ = powerlaw_sample(200_000, seed=35)
+    for T, D, dt in [(64, 1, oracle.F64), (128, 2, oracle.F32), (7, 3, oracle.F16)]:
+        compare_conversion(ac, A, T, D, dt, device_grouping=True, keep_plan=False)
+    compare_conversion(ac, csr_from_lengths([0, 500] * 300, 600, 77), 64, 2, oracle.F64,
+                       device_grouping=True, keep_plan=False)
+    compare_conversion(ac, fig3(), 8, 0, oracle.F64, device_grouping=True, fmt=ac.FORMAT_RG,
+                       keep_plan=False)
+
+
+def test_convert_planned_rejects_another_matrix(ac):
+    """A device plan converts only the matrix it was made for: out's sizes or
+    parameters that differ from the plan's are refused before any write."""
+    import ctypes
+    L = ac._lib
+    A, _ = powerlaw_sample(20_000, seed=36)
+    dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
+    g, s, h = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    plan = ctypes.c_void_p(0)
+    s_ = ac._stream(None)
+    ac.check(L.lib().argcsr_plan_device_keep(A.n_rows, ac._ptr(dev.row_ptr), 64, 1, 0,
+                                             ctypes.byref(g), ctypes.byref(s), ctypes.byref(h),
+                                             ctypes.byref(plan), s_), "plan")
+    try:
+        assert (g.value, s.value, h.value) == ac.plan(A.rp, 64, 1)
+        M = ac.convert(dev, 64, 1)
+        for field, bad in [("n_slots", s.value + 64), ("block_dim", 128),
+                           ("desired_chunk_size", 2), ("n_groups", g.value - 1)]:
+            d = M.desc()
+            setattr(d, field, bad)
+            rc = L.lib().argcsr_convert_planned(plan, A.n_cols, ac._ptr(dev.row_ptr),
+                                                ac._ptr(dev.col), ac._ptr(dev.val),
+                                                ctypes.byref(d), s_)
+            assert rc == L.EINVAL, field
+        # the right descriptor converts to the same bytes as argcsr_convert
+        M2 = ac.convert(dev, 64, 1)
+        d = M2.desc()
+        M2.columns.fill_(0)
+        ac.check(L.lib().argcsr_convert_planned(plan, A.n_cols, ac._ptr(dev.row_ptr),
+                                                ac._ptr(dev.col), ac._ptr(dev.val),
+                                                ctypes.byref(d), s_), "planned")
+        for f in ("groups", "threads_mapping", "columns", "values", "heavy_groups"):
+            assert torch.equal(getattr(M, f), getattr(M2, f)), f
+    finally:
+        L.lib().argcsr_device_plan_destroy(plan)
 
 
 def test_device_grouping_rejects_bad_row_ptr(ac):
