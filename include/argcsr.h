@@ -245,7 +245,8 @@ int argcsr_convert_planned(const argcsr_device_plan* plan, int32_t n_cols, const
                            const int32_t* col, const double* val, argcsr_matrix* out,
                            void* stream);
 
-/* Frees a device plan (NULL is a no-op).  No conversion may be running with it. */
+/* Frees a device plan (NULL is a no-op), in the order of the stream it was
+ * planned on.  No conversion may be running with it. */
 int argcsr_device_plan_destroy(argcsr_device_plan* plan);
 
 /*
@@ -587,7 +588,11 @@ typedef struct {
 int argcsr_server_create(const argcsr_server_config* cfg, argcsr_server** out);
 
 /* Queues a request (thread-safe, non-blocking) and returns its ticket.
- * Requests are taken in submission order.  A matrix that a running request
+ * Requests are taken in submission order, except that while an ADMIT's
+ * conversion runs (on a stream of its own) the requests behind it that do
+ * not depend on it may start: ADMITs and SPMV/CG requests of matrices that
+ * are resident; a request for the matrix being converted, another ADMIT that
+ * must convert, or an EVICT waits for it.  A matrix that a running request
  * uses is never evicted; queued requests do not pin their matrices (an ADMIT
  * evicts matrices no queued request names first).  An ADMIT that finds the
  * budget full even after evicting every matrix no running request uses

@@ -177,14 +177,14 @@ def plan_device(row_ptr: torch.Tensor, block_dim: int, desired_chunk_size: int, 
 def convert(A: DeviceCsr, block_dim: int = 64, desired_chunk_size: int = 1,
             dtype: int = F64, stream=None, schedule: bool = True,
             device_grouping: bool = False, fmt: int = FORMAT_ARG, region_rows: int = 0,
-            region_desired=None, noalloc: bool = False, keep_plan: bool = True) -> ArgCsrMatrix:
+            region_desired=None, noalloc: bool = False, keep_plan: bool = False) -> ArgCsrMatrix:
     """CSR -> ARG-CSR (or, with fmt=FORMAT_RG, row-grouped CSR) on the GPU
     (argcsr_convert); allocates the result.  `schedule` also builds the
     heavy-group launch schedule.  With `device_grouping` step 1 runs on the
-    device and the host copy of row_ptr is not used: steps 1-3 run once,
-    kept on the device between sizing and conversion (argcsr_plan_device_keep
-    + argcsr_convert_planned), or, without `keep_plan`, twice
-    (argcsr_plan_device, then argcsr_convert with row_ptr_host = NULL).
+    device and the host copy of row_ptr is not used: steps 1-3 run twice
+    (argcsr_plan_device, then argcsr_convert with row_ptr_host = NULL), or,
+    with `keep_plan`, once, kept on the device between sizing and conversion
+    (argcsr_plan_device_keep + argcsr_convert_planned).
     `region_desired` (with `region_rows`) gives ARG-CSR a desiredChunkSize
     per region of rows (argcsr_plan_regions; the sizes are planned on the
     host).  `noalloc` converts with argcsr_convert_noalloc (the library

@@ -55,6 +55,21 @@ struct Status {                       // device-side results read back by the ho
 
 __global__ void clear_status_kernel(Status* st) { *st = Status{}; }
 
+// dst[i] = src[i] for n 32-bit words (a device plan's tables into the
+// caller's buffers)
+__global__ __launch_bounds__(256) void copy_words_kernel(const int32_t* __restrict__ src,
+                                                        int32_t* __restrict__ dst, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    dst[i] = src[i];
+}
+
+void copy_words(const void* src, void* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  copy_words_kernel<<<dim3(uint32_t(blocks)), 256, 0, s>>>(static_cast<const int32_t*>(src),
+                                                          static_cast<int32_t*>(dst), n);
+}
+
 // LDS of one fill wave: chunk starts and lengths, then the staged columns and
 // values (the byte count keeps the next wave's region 8-byte aligned)
 template <typename S>
@@ -455,15 +470,18 @@ void launch_fill(int32_t n_groups, hipStream_t s, const int32_t* rp, const int32
 
 // A device plan (argcsr_plan_device_keep): steps 1-3 of one matrix kept on
 // the device for argcsr_convert_planned.
+// Its buffers are stream-ordered allocations on the planning stream (freed
+// on it too: every conversion with the plan has waited for its own work).
 struct argcsr_device_plan {
   int32_t n_rows = 0, block_dim = 0, desired_chunk_size = 0, format = 0;
   int32_t n_groups = 0, n_heavy = 0;
   int64_t n_slots = 0;
   argcsr_group_info* groups = nullptr;    // first_row, size, chunk_size (offset not yet set)
   int32_t* tm = nullptr;                  // threads mapping
+  void* block = nullptr;                  // the one allocation holding both
+  hipStream_t stream = nullptr;
   ~argcsr_device_plan() {
-    if (groups) (void)hipFree(groups);
-    if (tm) (void)hipFree(tm);
+    if (block) (void)hipFreeAsync(block, stream);
   }
 };
 
@@ -667,10 +685,8 @@ int convert_impl(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
 
   clear_status_kernel<<<1, 1, 0, s>>>(st);
   if (planned) {
-    ARGCSR_HIP(hipMemcpyAsync(out->groups, planned->groups, sizeof(argcsr_group_info) * size_t(G),
-                              hipMemcpyDeviceToDevice, s));
-    ARGCSR_HIP(hipMemcpyAsync(out->threads_mapping, planned->tm, sizeof(int32_t) * size_t(n_rows),
-                              hipMemcpyDeviceToDevice, s));
+    copy_words(planned->groups, out->groups, 4 * int64_t(G), s);
+    copy_words(planned->tm, out->threads_mapping, int64_t(n_rows), s);
   } else {
     if (row_ptr_host) {
       if (!groups_uploaded)
@@ -788,21 +804,17 @@ int plan_device_impl(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
   // slot count and the heavy-group count exactly as argcsr_plan computes
   // them on the host
   const int32_t n_tiles = (G + kScanTile - 1) / kScanTile;
-  const size_t groups_bytes = keep ? 0 : sizeof(argcsr_group_info) * size_t(G);
-  const size_t tm_bytes = keep ? 0 : (sizeof(int32_t) * size_t(n_rows) + 15) / 16 * 16;
+  const size_t groups_bytes = sizeof(argcsr_group_info) * size_t(G);
+  const size_t tm_bytes = (sizeof(int32_t) * size_t(n_rows) + 15) / 16 * 16;
   StreamScratch ws;
   rc = ws.alloc(groups_bytes + tm_bytes + sizeof(Status) + 2 * sizeof(int64_t) * size_t(n_tiles), s);
   if (rc) return rc;
   argcsr_group_info* groups = static_cast<argcsr_group_info*>(ws.ptr);
   int32_t* tm = reinterpret_cast<int32_t*>(static_cast<char*>(ws.ptr) + groups_bytes);
-  if (keep) {
-    if (hipMalloc(reinterpret_cast<void**>(&keep->groups), sizeof(argcsr_group_info) * size_t(G)) !=
-            hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&keep->tm), sizeof(int32_t) * size_t(n_rows)) !=
-            hipSuccess)
-      return fail(ARGCSR_ENOMEM, "device plan of %d groups could not be allocated", G);
-    groups = keep->groups;
-    tm = keep->tm;
+  if (keep) {                    // the plan takes the scratch over at the end (groups and mapping first)
+    keep->stream = s;
+    keep->groups = groups;
+    keep->tm = tm;
   }
   auto* st = reinterpret_cast<Status*>(static_cast<char*>(ws.ptr) + groups_bytes + tm_bytes);
   int64_t* tile_sums = reinterpret_cast<int64_t*>(st + 1);
@@ -828,12 +840,14 @@ int plan_device_impl(int32_t n_rows, const int32_t* row_ptr, int32_t block_dim,
   ARGCSR_HIP(hipStreamSynchronize(s));
   *n_slots = S;
   if (n_heavy) *n_heavy = int32_t(host_st.total_heavy);
-  if (S > INT32_MAX) return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", (long long)S);
   if (keep) {
+    keep->block = ws.ptr;        // owned by the plan now (freed with it)
+    ws.ptr = nullptr;
     keep->n_groups = G;
     keep->n_slots = S;
     keep->n_heavy = int32_t(host_st.total_heavy);
   }
+  if (S > INT32_MAX) return fail(ARGCSR_EOVERFLOW, "%lld slots exceed INT32_MAX", (long long)S);
   return ARGCSR_OK;
 }
 

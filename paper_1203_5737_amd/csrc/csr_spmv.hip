@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "group.hpp"
 #include "values.hpp"
 
 namespace argcsr {
@@ -252,7 +253,8 @@ extern "C" int argcsr_csr_bin_rows(int32_t n_rows, const int32_t* row_ptr, int32
   const int64_t blocks = (int64_t(n_rows) + kCsrBlock - 1) / kCsrBlock;
   const size_t bytes = sizeof(int32_t) * size_t(blocks) * kBins;
   int32_t* d_counts = nullptr;
-  ARGCSR_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_counts), bytes, s));
+  int rc = scratch_alloc_async(reinterpret_cast<void**>(&d_counts), bytes, s);
+  if (rc) return rc;
   bin_count_kernel<<<dim3(uint32_t(blocks)), kCsrBlock, 0, s>>>(n_rows, row_ptr, d_counts);
   std::vector<int32_t> h(size_t(blocks) * kBins);
   hipError_t e = hipMemcpyAsync(h.data(), d_counts, bytes, hipMemcpyDeviceToHost, s);

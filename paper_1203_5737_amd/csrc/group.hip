@@ -20,6 +20,8 @@
 // K = bit length of n.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "group.hpp"
 
@@ -114,9 +116,40 @@ __global__ __launch_bounds__(kGroupBlock) void starts_kernel(
 
 }  // namespace
 
+int scratch_alloc_async(void** p, size_t bytes, hipStream_t s) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static hipMemPool_t pools[kMaxDevices] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(ARGCSR_EHIP, "no current device");
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!pools[dev]) {
+      hipMemPoolProps props{};
+      props.allocType = hipMemAllocationTypePinned;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      hipMemPool_t created = nullptr;
+      if (hipMemPoolCreate(&created, &props) != hipSuccess)
+        return fail(ARGCSR_ENOMEM, "memory pool of device %d could not be created", dev);
+      uint64_t keep_all = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(created, hipMemPoolAttrReleaseThreshold, &keep_all);
+      pools[dev] = created;
+    }
+    pool = pools[dev];
+  }
+  if (hipMallocFromPoolAsync(p, bytes < 256 ? 256 : bytes, pool, s) != hipSuccess) {
+    *p = nullptr;
+    return fail(ARGCSR_ENOMEM, "device scratch of %zu bytes could not be allocated", bytes);
+  }
+  return ARGCSR_OK;
+}
+
 int StreamScratch::alloc(size_t bytes, hipStream_t s) {
   stream = s;
-  if (hipMallocAsync(&ptr, bytes < 256 ? 256 : bytes, s) != hipSuccess) {
+  if (scratch_alloc_async(&ptr, bytes, s) != ARGCSR_OK) {
     ptr = nullptr;
     return fail(ARGCSR_ENOMEM, "device scratch of %zu bytes could not be allocated", bytes);
   }
@@ -141,7 +174,7 @@ int DeviceGrouping::build(int32_t n, const int32_t* rp, int32_t block_dim, int32
   stride = int64_t(n) + 1;
   const int64_t n_regions = region_desired ? (int64_t(n) + region_rows - 1) / region_rows : 0;
   const size_t bytes = sizeof(int32_t) * (size_t(levels_n) * size_t(stride) + 2 + size_t(n_regions));
-  if (hipMallocAsync(reinterpret_cast<void**>(&levels), bytes, s) != hipSuccess) {
+  if (scratch_alloc_async(reinterpret_cast<void**>(&levels), bytes, s) != ARGCSR_OK) {
     levels = nullptr;
     return fail(ARGCSR_ENOMEM, "grouping tables of %zu bytes could not be allocated", bytes);
   }

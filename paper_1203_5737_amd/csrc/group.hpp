@@ -35,7 +35,15 @@ struct DeviceGrouping {
   ~DeviceGrouping() { release(); }
 };
 
-// Device scratch allocated and freed in stream order (hipMallocAsync /
+// Stream-ordered device allocation from the library's own memory pool on
+// the current device (created on first use, one per device, with a release
+// threshold that keeps freed memory in the pool: repeated conversions reuse
+// their scratch instead of mapping it again at every synchronisation).  The
+// pool holds at most the largest scratch any call needed until the process
+// ends.  Free with hipFreeAsync.
+int scratch_alloc_async(void** p, size_t bytes, hipStream_t s);
+
+// Device scratch allocated and freed in stream order (scratch_alloc_async /
 // hipFreeAsync): work queued on the stream may still use it after the
 // owner goes out of scope, and concurrent conversions never share it.
 struct StreamScratch {

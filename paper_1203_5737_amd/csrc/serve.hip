@@ -144,6 +144,9 @@ constexpr int kAdmitWait = 2;
 // admit(): the preparation thread has not finished the ADMIT's host side
 // yet; it stays at the head of the queue and is tried again
 constexpr int kAdmitPending = 3;
+// admit(): the matrix's memory is allocated and its conversion handed to the
+// converter thread (its own stream); the ADMIT completes when that is done
+constexpr int kAdmitStarted = 4;
 
 // The host side of an ADMIT, done ahead of the scheduler by the preparation
 // thread: steps 1-2 of the conversion with the group table kept, and the CSR
@@ -164,6 +167,28 @@ struct AdmitPrep {
   int32_t n_heavy = 0;
   void* stage = nullptr;         // pinned row_ptr | col | val, or NULL (upload from q's arrays)
   size_t off_col = 0, off_val = 0;
+};
+
+struct Request;
+
+// A conversion handed to the converter thread: the matrix's resident
+// arrays and the CSR staging are allocated in the arena (by the scheduler,
+// which owns it); the thread uploads the CSR arrays, converts, rounds the
+// FP32 copy of the values and waits for its stream.
+struct AdmitJob {
+  Request* r = nullptr;
+  std::unique_ptr<Resident> m;
+  std::vector<size_t> sizes;      // arena bytes of m's blocks
+  size_t resident_blocks = 0;     // m->blocks[resident_blocks..] are the CSR staging
+  int32_t* d_rp = nullptr;
+  int32_t* d_col = nullptr;
+  double* d_val = nullptr;
+  const void* src_rp = nullptr;   // pinned staging or the caller's arrays
+  const void* src_col = nullptr;
+  const void* src_val = nullptr;
+  int64_t nnz = 0;
+  const argcsr_group_info* groups = nullptr;   // prepared step 1, or NULL
+  int rc = ARGCSR_OK;
 };
 
 struct Request {
@@ -248,6 +273,18 @@ struct argcsr_server {
   std::deque<std::shared_ptr<argcsr::AdmitPrep>> preps;   // guarded by pmu
   bool preparer_stop = false;                              // guarded by pmu
   std::unordered_map<int64_t, int32_t> resident_ids;       // resident matrices (mu)
+  // converter thread: one conversion at a time on its own stream
+  std::thread converter;
+  hipStream_t conv_stream = nullptr;
+  std::mutex cmu;
+  std::condition_variable ccv;
+  argcsr::AdmitJob* conv_todo = nullptr;                   // guarded by cmu
+  bool converter_stop = false;                             // guarded by cmu
+  std::unique_ptr<argcsr::AdmitJob> admitting;             // scheduler: the conversion in flight
+  std::atomic<int> conv_done{0};
+  // recorded on the scheduler's stream when a conversion starts; the
+  // converter's stream waits for it (see start_admission)
+  hipEvent_t conv_after = nullptr;
 };
 
 namespace argcsr {
@@ -525,75 +562,158 @@ int admit(argcsr_server* s, Request* r) {
   auto give_back = [&]() {
     for (void* p : m->blocks) s->arena.release(p);
   };
-  A.groups = static_cast<argcsr_group_info*>(grab(sizeof(argcsr_group_info) * size_t(A.n_groups)));
-  A.threads_mapping = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(q.n_rows)));
-  A.columns = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(A.n_slots)));
-  A.values = grab(sizeof(double) * size_t(A.n_slots));
-  m->values32 = static_cast<float*>(grab(sizeof(float) * size_t(A.n_slots)));
-  A.heavy_groups = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(std::max(A.n_heavy, 1))));
-  // CSR staging, released after the conversion
-  const size_t resident_blocks = m->blocks.size();
-  int32_t* d_rp = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(q.n_rows + 1)));
-  int32_t* d_col = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(std::max<int64_t>(nnz, 1))));
-  double* d_val = static_cast<double*>(grab(sizeof(double) * size_t(std::max<int64_t>(nnz, 1))));
-  if (m->blocks.size() != resident_blocks + 3 || !A.groups || !A.threads_mapping || !A.columns ||
-      !A.values || !m->values32 || !A.heavy_groups) {
+  const size_t resident_blocks = 6;               // then the CSR staging, released after the conversion
+  int32_t* d_rp = nullptr;
+  int32_t* d_col = nullptr;
+  double* d_val = nullptr;
+  auto allocate = [&]() -> bool {
+    A.groups = static_cast<argcsr_group_info*>(grab(sizeof(argcsr_group_info) * size_t(A.n_groups)));
+    A.threads_mapping = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(q.n_rows)));
+    A.columns = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(A.n_slots)));
+    A.values = grab(sizeof(double) * size_t(A.n_slots));
+    m->values32 = static_cast<float*>(grab(sizeof(float) * size_t(A.n_slots)));
+    A.heavy_groups = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(std::max(A.n_heavy, 1))));
+    d_rp = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(q.n_rows + 1)));
+    d_col = static_cast<int32_t*>(grab(sizeof(int32_t) * size_t(std::max<int64_t>(nnz, 1))));
+    d_val = static_cast<double*>(grab(sizeof(double) * size_t(std::max<int64_t>(nnz, 1))));
+    if (m->blocks.size() == resident_blocks + 3) return true;
     give_back();
-    if (memory_will_free(s)) return kAdmitWait;     // fragmented: retry after requests end
-    return fail(ARGCSR_EBUDGET, "matrix %lld (%lld slots) does not fit the %zu-byte budget",
-                (long long)q.matrix_id, (long long)A.n_slots, s->arena.capacity());
+    m->blocks.clear();
+    sizes.clear();
+    return false;
+  };
+  if (!allocate()) {
+    // the blocks already placed can split the free space (they went into the
+    // holes that evictions left): with requests running, wait for them;
+    // with nothing running, evict every other matrix and place the blocks
+    // again on the emptied arena
+    if (memory_will_free(s)) return kAdmitWait;
+    for (auto it = s->resident.begin(); it != s->resident.end();) {
+      if (it->first != q.matrix_id && !pinned(s, it->second.get())) {
+        evict(s, it->second.get());
+        it = s->resident.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    if (!allocate())
+      return fail(ARGCSR_EBUDGET, "matrix %lld (%lld slots) does not fit the %zu-byte budget",
+                  (long long)q.matrix_id, (long long)A.n_slots, s->arena.capacity());
   }
-  rc = ARGCSR_OK;
-  // the CSR arrays: from the preparation's pinned staging (asynchronous
-  // DMA), or from the caller's memory
+  // the conversion goes to the converter thread; the CSR arrays come from
+  // the preparation's pinned staging (asynchronous DMA) or the caller's memory
+  auto job = std::make_unique<AdmitJob>();
   const char* st = prepared ? static_cast<const char*>(prep->stage) : nullptr;
-  const void* src_rp = st ? static_cast<const void*>(st) : q.row_ptr;
-  const void* src_col = st ? static_cast<const void*>(st + prep->off_col) : q.col;
-  const void* src_val = st ? static_cast<const void*>(st + prep->off_val) : q.val;
-  if (hipMemcpyAsync(d_rp, src_rp, sizeof(int32_t) * size_t(q.n_rows + 1),
-                     hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-      (nnz > 0 && (hipMemcpyAsync(d_col, src_col, sizeof(int32_t) * size_t(nnz),
-                                  hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-                   hipMemcpyAsync(d_val, src_val, sizeof(double) * size_t(nnz),
-                                  hipMemcpyHostToDevice, s->stream) != hipSuccess)))
+  job->r = r;
+  job->sizes = std::move(sizes);
+  job->resident_blocks = resident_blocks;
+  job->d_rp = d_rp;
+  job->d_col = d_col;
+  job->d_val = d_val;
+  job->src_rp = st ? static_cast<const void*>(st) : q.row_ptr;
+  job->src_col = st ? static_cast<const void*>(st + prep->off_col) : q.col;
+  job->src_val = st ? static_cast<const void*>(st + prep->off_val) : q.val;
+  job->nnz = nnz;
+  job->groups = prepared ? prep->groups.data() : nullptr;
+  job->m = std::move(m);
+  s->admitting = std::move(job);
+  return kAdmitStarted;
+}
+
+// The converter thread's part of an ADMIT (on its own stream, waited for).
+void convert_job(argcsr_server* s, AdmitJob* j) {
+  const argcsr_request& q = j->r->q;
+  argcsr_matrix& A = j->m->m64;
+  hipStream_t cs = s->conv_stream;
+  int rc = ARGCSR_OK;
+  if (hipStreamWaitEvent(cs, s->conv_after, 0) != hipSuccess)
+    rc = fail(ARGCSR_EHIP, "conversion could not be ordered after the scheduler's stream");
+  if (rc == ARGCSR_OK && hipMemcpyAsync(j->d_rp, j->src_rp, sizeof(int32_t) * size_t(q.n_rows + 1),
+                     hipMemcpyHostToDevice, cs) != hipSuccess ||
+      (j->nnz > 0 && (hipMemcpyAsync(j->d_col, j->src_col, sizeof(int32_t) * size_t(j->nnz),
+                                     hipMemcpyHostToDevice, cs) != hipSuccess ||
+                      hipMemcpyAsync(j->d_val, j->src_val, sizeof(double) * size_t(j->nnz),
+                                     hipMemcpyHostToDevice, cs) != hipSuccess)))
     rc = fail(ARGCSR_EHIP, "CSR upload failed");
   if (rc == ARGCSR_OK)
-    rc = prepared ? convert_pregrouped(q.n_rows, q.n_cols, q.row_ptr, prep->groups.data(), d_rp,
-                                       d_col, d_val, &A, s->stream)
-                  : argcsr_convert(q.n_rows, q.n_cols, q.row_ptr, d_rp, d_col, d_val, &A,
-                                   s->stream);
+    rc = j->groups ? convert_pregrouped(q.n_rows, q.n_cols, q.row_ptr, j->groups, j->d_rp,
+                                        j->d_col, j->d_val, &A, cs)
+                   : argcsr_convert(q.n_rows, q.n_cols, q.row_ptr, j->d_rp, j->d_col, j->d_val,
+                                    &A, cs);
   if (rc == ARGCSR_OK && A.n_slots > 0) {
     const int64_t blocks = std::min<int64_t>((A.n_slots + kVecBlock - 1) / kVecBlock, 8192);
-    round_values_kernel<<<int(blocks), kVecBlock, 0, s->stream>>>(
-        static_cast<const double*>(A.values), m->values32, A.n_slots);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
-      rc = fail(ARGCSR_EHIP, "value rounding failed");
+    round_values_kernel<<<int(blocks), kVecBlock, 0, cs>>>(static_cast<const double*>(A.values),
+                                                           j->m->values32, A.n_slots);
+    if (hipGetLastError() != hipSuccess) rc = fail(ARGCSR_EHIP, "value rounding failed");
   }
-  (void)hipStreamSynchronize(s->stream);          // the uploads have read the staging
-  if (prep) {
-    s->pinned.release(prep->stage);
-    prep->stage = nullptr;
-    r->prep.reset();
-  }
-  for (size_t i = resident_blocks; i < m->blocks.size(); ++i) s->arena.release(m->blocks[i]);
-  m->blocks.resize(resident_blocks);
-  if (rc) {
-    give_back();
-    return rc;
-  }
-  m->bytes = 0;
-  for (size_t i = 0; i < resident_blocks; ++i) m->bytes += sizes[i];
-  if (A.n_heavy == 0) A.heavy_groups = nullptr;
-  m->last_use = now_ns();
-  {
+  if (hipStreamSynchronize(cs) != hipSuccess && rc == ARGCSR_OK)
+    rc = fail(ARGCSR_EHIP, "conversion stream failed");
+  j->rc = rc;
+}
+
+void converter(argcsr_server* s) {
+  (void)hipSetDevice(s->cfg.device);
+  for (;;) {
+    AdmitJob* j = nullptr;
+    {
+      std::unique_lock<std::mutex> lock(s->cmu);
+      s->ccv.wait(lock, [&] { return s->converter_stop || s->conv_todo; });
+      if (!s->conv_todo) return;
+      j = s->conv_todo;
+      s->conv_todo = nullptr;
+    }
+    convert_job(s, j);
+    s->conv_done.store(1, std::memory_order_release);
     std::lock_guard<std::mutex> lock(s->mu);
-    s->resident_ids[q.matrix_id] = 1;
-    s->stats.admissions++;
-    s->stats.resident_matrices++;
-    s->stats.resident_bytes += int64_t(m->bytes);
+    s->cv_work.notify_one();
   }
-  s->resident[q.matrix_id] = std::move(m);
-  return ARGCSR_OK;
+}
+
+// Scheduler: the converter finished the ADMIT in flight; the CSR staging
+// goes back to the arena, the matrix becomes resident (or its memory goes
+// back too), and the ADMIT completes.
+void finish_admission(argcsr_server* s) {
+  std::unique_ptr<AdmitJob> j = std::move(s->admitting);
+  s->conv_done.store(0, std::memory_order_relaxed);
+  Request* r = j->r;
+  Resident* m = j->m.get();
+  for (size_t i = j->resident_blocks; i < m->blocks.size(); ++i) s->arena.release(m->blocks[i]);
+  m->blocks.resize(j->resident_blocks);
+  drop_prep(s, r);                                // its staging has been read
+  if (j->rc == ARGCSR_OK) {
+    argcsr_matrix& A = m->m64;
+    m->bytes = 0;
+    for (size_t i = 0; i < j->resident_blocks; ++i) m->bytes += j->sizes[i];
+    if (A.n_heavy == 0) A.heavy_groups = nullptr;
+    m->last_use = now_ns();
+    {
+      std::lock_guard<std::mutex> lock(s->mu);
+      s->resident_ids[r->q.matrix_id] = 1;
+      s->stats.admissions++;
+      s->stats.resident_matrices++;
+      s->stats.resident_bytes += int64_t(m->bytes);
+    }
+    s->resident[r->q.matrix_id] = std::move(j->m);
+  } else {
+    for (void* p : m->blocks) s->arena.release(p);
+  }
+  r->res.status = j->rc;
+  r->res.iterations = j->rc == ARGCSR_OK ? 1 : 0;
+  publish(s, r);
+  delete r;
+}
+
+// Starts a conversion the scheduler has prepared with admit().  Arena blocks
+// are freed in the order of the scheduler's stream (a finished request's
+// vectors are released while the copy of its result is still queued), so
+// the blocks the conversion writes may still be read there: its stream
+// first waits for everything queued on the scheduler's stream so far.
+void start_admission(argcsr_server* s) {
+  (void)hipEventRecord(s->conv_after, s->stream);
+  s->conv_done.store(0, std::memory_order_relaxed);
+  std::lock_guard<std::mutex> lock(s->cmu);
+  s->conv_todo = s->admitting.get();
+  s->ccv.notify_one();
 }
 
 void release_request(argcsr_server* s, Request* r) {
@@ -1018,19 +1138,32 @@ void scheduler(argcsr_server* s) {
         s->incoming.pop_front();
       }
     }
-    // admissions and new requests, in submission order
+    // the conversion in flight, if it has finished
+    if (s->admitting && s->conv_done.load(std::memory_order_acquire)) finish_admission(s);
+    // admissions and new requests, in submission order; while a conversion
+    // runs (on the converter's stream) the requests behind its ADMIT that do
+    // not depend on it may start: no-op ADMITs of resident matrices and
+    // SPMV/CG requests of resident matrices.  A request of the matrix being
+    // converted, another conversion, or an EVICT waits for it.
     bool admit_waiting = false;
-    while (!s->pending.empty()) {
-      Request* r = s->pending.front();
+    for (size_t i = 0; i < s->pending.size();) {
+      Request* r = s->pending[i];
+      const int64_t converting = s->admitting ? s->admitting->r->q.matrix_id : -1;
+      const bool busy = s->admitting != nullptr;
       if (r->q.kind == ARGCSR_REQ_ADMIT) {
-        if (r->res.t_start_ns == 0) r->res.t_start_ns = now_ns();
         const bool was_resident = s->resident.count(r->q.matrix_id) != 0;
+        if (busy && (!was_resident || r->q.matrix_id == converting)) break;
+        if (r->res.t_start_ns == 0) r->res.t_start_ns = now_ns();
         const int rc = admit(s, r);
         if (rc == kAdmitWait || rc == kAdmitPending) {   // requests behind it wait too (in order)
           admit_waiting = true;
           break;
         }
-        s->pending.pop_front();
+        s->pending.erase(s->pending.begin() + std::ptrdiff_t(i));
+        if (rc == kAdmitStarted) {                        // completes in finish_admission
+          start_admission(s);
+          continue;
+        }
         drop_prep(s, r);
         r->res.status = rc;
         r->res.iterations = (r->res.status == ARGCSR_OK && !was_resident) ? 1 : 0;
@@ -1039,7 +1172,8 @@ void scheduler(argcsr_server* s) {
         continue;
       }
       if (r->q.kind == ARGCSR_REQ_EVICT) {
-        s->pending.pop_front();
+        if (busy) break;
+        s->pending.erase(s->pending.begin() + std::ptrdiff_t(i));
         auto it = s->resident.find(r->q.matrix_id);
         const bool used = it != s->resident.end() && pinned(s, it->second.get());
         if (it == s->resident.end()) r->res.status = ARGCSR_ENOTFOUND;
@@ -1053,15 +1187,16 @@ void scheduler(argcsr_server* s) {
         delete r;
         continue;
       }
+      if (r->q.matrix_id == converting) break;    // needs the matrix being converted
       if (s->free_slots.empty()) break;           // wait for a slot
       const int rc = activate(s, r);
       if (rc == ARGCSR_EBUSY) {
-        if (memory_will_free(s)) break;           // memory frees up as requests finish
+        if (memory_will_free(s) || busy) break;   // memory frees up as requests finish
         r->res.status = fail(ARGCSR_EBUDGET, "request does not fit the budget");
       } else if (rc != ARGCSR_OK) {
         r->res.status = rc;
       }
-      s->pending.pop_front();
+      s->pending.erase(s->pending.begin() + std::ptrdiff_t(i));
       if (rc == ARGCSR_OK) {
         if (r->stage) s->staging.push_back(r);   // starts once its input is staged
         else s->active.push_back(r);
@@ -1096,7 +1231,7 @@ void scheduler(argcsr_server* s) {
       s->staging[i] = s->staging.back();
       s->staging.pop_back();
     }
-    if (admit_waiting && s->active.empty()) {
+    if ((admit_waiting || s->admitting) && s->active.empty()) {
       // only input copies are in flight: give the copy helper a moment
       std::unique_lock<std::mutex> lock(s->mu);
       s->cv_work.wait_for(lock, std::chrono::microseconds(200));
@@ -1114,7 +1249,11 @@ void scheduler(argcsr_server* s) {
       }
     }
   }
-  // shut down: fail what is left
+  // shut down: the conversion in flight finishes first (it writes into the
+  // arena), then what is left fails
+  while (s->admitting && !s->conv_done.load(std::memory_order_acquire))
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  if (s->admitting) finish_admission(s);
   for (Request* r : s->active) {
     r->res.status = ARGCSR_ENOTFOUND;
     release_request(s, r);
@@ -1153,7 +1292,10 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
   if (!rc) rc = s->arena.init(size_t(cfg->budget_bytes));
   if (!rc && cfg->staging_bytes >= 0)
     rc = s->pinned.init(cfg->staging_bytes > 0 ? size_t(cfg->staging_bytes) : kDefaultStaging);
-  if (!rc && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+  // both streams at the default priority
+  if (!rc && (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+              hipStreamCreateWithFlags(&s->conv_stream, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&s->conv_after, hipEventDisableTiming) != hipSuccess))
     rc = fail(ARGCSR_EHIP, "hipStreamCreate failed");
   if (!rc && (hipMalloc(&s->d_scalars, sizeof(CgScalars) * size_t(cfg->max_active)) != hipSuccess ||
               hipHostMalloc(&s->h_scalars, sizeof(CgScalars) * size_t(cfg->max_active),
@@ -1163,6 +1305,8 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
     rc = fail(ARGCSR_ENOMEM, "server buffers could not be allocated");
   if (rc) {
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->conv_stream) (void)hipStreamDestroy(s->conv_stream);
+    if (s->conv_after) (void)hipEventDestroy(s->conv_after);
     if (s->d_scalars) (void)hipFree(s->d_scalars);
     if (s->h_scalars) (void)hipHostFree(s->h_scalars);
     delete s;
@@ -1171,6 +1315,7 @@ extern "C" int argcsr_server_create(const argcsr_server_config* cfg, argcsr_serv
   for (int32_t k = cfg->max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->helper = std::thread(copy_helper, s);
   s->preparer = std::thread(preparer, s);
+  s->converter = std::thread(converter, s);
   s->worker = std::thread(scheduler, s);
   *out = s;
   return ARGCSR_OK;
@@ -1288,6 +1433,12 @@ extern "C" int argcsr_server_destroy(argcsr_server* s) {
     s->pcv.notify_all();
   }
   if (s->preparer.joinable()) s->preparer.join();
+  {
+    std::lock_guard<std::mutex> lock(s->cmu);    // the scheduler waited for its last conversion
+    s->converter_stop = true;
+    s->ccv.notify_all();
+  }
+  if (s->converter.joinable()) s->converter.join();
   for (auto& p : s->preps) s->pinned.release(p->stage);
   s->preps.clear();
   for (Request* r : s->staging) {               // never started
@@ -1300,6 +1451,8 @@ extern "C" int argcsr_server_destroy(argcsr_server* s) {
   s->staging.clear();
   (void)hipStreamSynchronize(s->stream);
   (void)hipStreamDestroy(s->stream);
+  if (s->conv_stream) (void)hipStreamDestroy(s->conv_stream);
+  if (s->conv_after) (void)hipEventDestroy(s->conv_after);
   free_desc(s);
   (void)hipFree(s->d_scalars);
   (void)hipHostFree(s->h_scalars);

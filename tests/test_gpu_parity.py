@@ -32,7 +32,7 @@ def announce(msg):
     print(f"\n[gpu] {msg}", flush=True)
 
 
-def compare_conversion(ac, A, T, D, dtype, device_grouping=False, fmt=0, keep_plan=True):
+def compare_conversion(ac, A, T, D, dtype, device_grouping=False, fmt=0, keep_plan=False):
     announce(f"convert n={A.n_rows} nnz={A.nnz} T={T} D={D} dtype={dtype} "
              f"device_grouping={device_grouping} format={fmt} keep_plan={keep_plan}")
     dev = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
@@ -271,16 +271,19 @@ def test_device_grouping_random(ac):
         assert np.array_equal(M.columns.cpu().numpy(), ref.columns)
 
 
-def test_device_grouping_without_kept_plan(ac):
-    """argcsr_convert with row_ptr_host = NULL groups the rows itself (the
-    path without a device plan): the same bytes as the oracle."""
+def test_device_grouping_with_kept_plan(ac):
+    """argcsr_plan_device_keep + argcsr_convert_planned (steps 1-3 once, kept
+    on the device): the same bytes as the oracle."""
     A, _ = powerlaw_sample(200_000, seed=35)
-    for T, D, dt in [(64, 1, oracle.F64), (128, 2, oracle.F32), (7, 3, oracle.F16)]:
-        compare_conversion(ac, A, T, D, dt, device_grouping=True, keep_plan=False)
+    for T, D, dt in [(64, 1, oracle.F64), (128, 2, oracle.F32), (7, 3, oracle.F16),
+                     (1000, 1, oracle.BF16)]:
+        compare_conversion(ac, A, T, D, dt, device_grouping=True, keep_plan=True)
     compare_conversion(ac, csr_from_lengths([0, 500] * 300, 600, 77), 64, 2, oracle.F64,
-                       device_grouping=True, keep_plan=False)
+                       device_grouping=True, keep_plan=True)
+    compare_conversion(ac, csr_from_lengths([0] * 3000, 10, 78), 64, 1, oracle.F64,
+                       device_grouping=True, keep_plan=True)
     compare_conversion(ac, fig3(), 8, 0, oracle.F64, device_grouping=True, fmt=ac.FORMAT_RG,
-                       keep_plan=False)
+                       keep_plan=True)
 
 
 def test_convert_planned_rejects_another_matrix(ac):

@@ -245,6 +245,28 @@ def test_serve_requests_join_while_others_run(srv_mod):
         assert min(r["t_start_ns"] for r in r_late) < min(r["t_done_ns"] for r in r_first)
 
 
+def test_serve_shutdown_with_admissions_in_preparation(srv_mod):
+    """Destroying the server right after submitting ADMITs of large matrices,
+    whose host side the preparation thread is still doing (queued ones are
+    abandoned, a running one is waited for, pinned staging is freed), ends
+    cleanly, twice; a new server then admits and serves correctly."""
+    print("\n[gpu] serve shutdown during preparation", flush=True)
+    mats = pool(6, 2e5, 4e5)
+    for _ in range(2):
+        srv = srv_mod.Server(budget_bytes=1 << 30, max_active=4)
+        for i, A in enumerate(mats):
+            srv.admit(i, A.rp, A.col, A.val, A.n_cols)
+        srv.spmv(0, np.ones(mats[0].n_cols, np.float32), mats[0].n_rows)
+        srv.close()
+    rng = np.random.default_rng(8)
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=4) as srv:
+        admit_all(srv, mats[:2])
+        x = rng.uniform(-1, 1, mats[1].n_cols).astype(np.float32)
+        t, y = srv.spmv(1, x, mats[1].n_rows)
+        assert srv.wait(t, 120.0)["status"] == 0
+        assert spmv_ok(mats[1], x, y)
+
+
 def test_serve_budget_eviction_and_errors(srv_mod):
     print("\n[gpu] serve budget", flush=True)
     from paper_1203_5737_amd import _lib
@@ -310,6 +332,33 @@ def test_serve_admissions_wait_under_memory_pressure(srv_mod):
         st = srv.stats()
         assert st["failed"] == 0 and st["completed"] == len(reqs)
         assert st["evictions"] > 0 and st["resident_bytes"] <= budget
+
+
+def test_serve_results_while_conversions_run(srv_mod):
+    """Regression: a finished request's vectors return to the arena while the
+    copy of its result is still queued on the scheduler's stream; a
+    conversion on the converter's stream may get those blocks, so it must be
+    ordered after that stream.  Many short SpMV requests finishing while
+    admissions convert under a budget that forces reuse: every result is
+    checked."""
+    print("\n[gpu] serve results while conversions run", flush=True)
+    mats = pool(12, 1e4, 4e4)
+    rng = np.random.default_rng(77)
+    reqs = []
+    for k in range(160):
+        m = int(rng.integers(0, len(mats)))
+        reqs.append((m, rng.uniform(-1, 1, mats[m].n_cols).astype(np.float32)))
+    with srv_mod.Server(budget_bytes=8 << 20, max_active=8) as srv:
+        tickets = []
+        for m, x in reqs:
+            A = mats[m]
+            ta = srv.admit(m, A.rp, A.col, A.val, A.n_cols)
+            tickets.append((ta,) + srv.spmv(m, x, A.n_rows))
+        for k, ((m, x), (ta, t, y)) in enumerate(zip(reqs, tickets)):
+            ra, r = srv.wait(ta, 120.0), srv.wait(t, 120.0)
+            assert ra["status"] == 0 and r["status"] == 0, (k, m, ra, r, srv.stats())
+            assert spmv_ok(mats[m], x, y)
+        assert srv.stats()["evictions"] > 0
 
 
 def test_serve_rejects_wrong_vector_lengths(srv_mod):
