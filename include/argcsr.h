@@ -472,7 +472,9 @@ typedef struct {
  * longest and the mean row length when at most 64} and row-grouped CSR at
  * {64,128,256} (24 to 30 candidates) is sized with
  * argcsr_plan, ranked by a cost model (padded bytes, group count, long
- * groups), and the best n_finalists are converted and timed on `stream`,
+ * groups), and n_finalists of them are converted and timed on `stream` --
+ * candidates whose layout repeats a better-ranked one's are skipped, and the
+ * best of each block size comes first --
  * each launch after a 512 MiB read-modify-write that evicts the caches
  * (the median of 7 decides).
  * The choice is cached for the process under a signature of the row-length

@@ -8,7 +8,8 @@
 // row-grouped CSR at each T is planned on
 // the host (steps 1-2 give the group count, slot count and heavy-group
 // count exactly), ranked by a cost
-// model, and the best `n_finalists` are converted and timed on the device,
+// model, and `n_finalists` of them (distinct layouts, the best of each
+// block size first) are converted and timed on the device,
 // cold: each timed launch follows a read-modify-write pass over a buffer
 // larger than the Infinity Cache and the L2s together, so the matrix comes
 // from HBM as it does in a batch of many matrices or after other work; the
@@ -175,6 +176,7 @@ extern "C" int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* ro
   }
   const int sv = value_bytes(dtype), sx = dtype == ARGCSR_F64 ? 8 : 4;
   std::vector<Candidate> cands;
+  int32_t n_planned = 0;
   auto add = [&](int32_t T, int32_t D, int32_t format) {
     int32_t G = 0, H = 0;
     int64_t S = 0;
@@ -201,6 +203,36 @@ extern "C" int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* ro
   if (cands.empty()) return fail(ARGCSR_EOVERFLOW, "no (block_dim, desired_chunk_size) fits int32");
   std::stable_sort(cands.begin(), cands.end(),
                    [](const Candidate& a, const Candidate& b) { return a.model_us < b.model_us; });
+  // finalists: candidates with a layout of their own (the same T, group
+  // count, slot count and heavy count as a better-ranked one is the same
+  // layout on every matrix tried: e.g. D = 27, 32, 64 and row-grouped CSR
+  // on rows of 27), the best of each T first, then the next in model order
+  {
+    std::vector<Candidate> distinct;
+    for (const Candidate& c : cands) {
+      bool dup = false;
+      for (const Candidate& d : distinct)
+        dup |= d.T == c.T && d.G == c.G && d.S == c.S && d.heavy == c.heavy;
+      if (!dup) distinct.push_back(c);
+    }
+    std::vector<Candidate> order;
+    std::vector<bool> used(distinct.size(), false);
+    for (int32_t T : kBlockDims) {
+      for (size_t i = 0; i < distinct.size(); ++i)
+        if (!used[i] && distinct[i].T == T) {
+          used[i] = true;
+          order.push_back(distinct[i]);
+          break;
+        }
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const Candidate& a, const Candidate& b) { return a.model_us < b.model_us; });
+    for (size_t i = 0; i < distinct.size(); ++i)
+      if (!used[i]) order.push_back(distinct[i]);
+    const int32_t planned = int32_t(cands.size());
+    cands.swap(order);
+    n_planned = planned;
+  }
   const int n_time = std::max(0, std::min<int>(n_finalists, int(cands.size())));
   int best = 0;
   if (n_time > 0 && n_rows > 0) {
@@ -232,8 +264,7 @@ extern "C" int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* ro
       if (cands[i].measured_us < cands[best].measured_us) best = i;
   }
   const Candidate& c = cands[best];
-  *out = argcsr_tune_result{c.T,       c.D,   c.model_us,  c.measured_us, 0, int32_t(cands.size()),
-                            n_time, c.format};
+  *out = argcsr_tune_result{c.T, c.D, c.model_us, c.measured_us, 0, n_planned, n_time, c.format};
   std::lock_guard<std::mutex> lock(g_cache_mutex);
   g_cache[key] = *out;
   return ARGCSR_OK;
