@@ -65,13 +65,25 @@ int launch_staged(const argcsr_matrix* A, const void* x, void* y, hipStream_t s)
   return ARGCSR_OK;
 }
 
+// Steps per load batch of the staged kernel with x in LDS, chosen by a
+// sweep on the 27-point stencil (MI355X, cold): FP64 x at W = 1 takes 16
+// (124.0 us against 126.5 with 8), at W = 2 and 4 fewer steps than the plain
+// kernel (139.5 us with 2 against 149.3 with 4 at W = 2; 137.5 with 1
+// against 152.6 with 2 at W = 4); 4- and 2-byte values at W = 2 take 2
+// (FP32 71.2 against 73.2 us, BF16 56.0 against 56.6).
+template <int DT, int W>
+constexpr int staged_steps() {
+  if (sizeof(typename Val<DT>::acc) == 8) return W == 1 ? 16 : W == 2 ? 2 : 1;
+  return W == 1 ? 8 : W == 2 ? 2 : 2;
+}
+
 template <int DT, int W, int U>
 int launch_w(const argcsr_matrix* A, const void* x, void* y, hipStream_t s) {
   if (!A->local) {
     launch<DT, W, U>(A, x, y, s);
     return ARGCSR_OK;
   }
-  return A->stage_lds ? launch_staged<DT, W, U, true>(A, x, y, s)
+  return A->stage_lds ? launch_staged<DT, W, staged_steps<DT, W>(), true>(A, x, y, s)
                       : launch_staged<DT, W, U, false>(A, x, y, s);
 }
 
