@@ -303,15 +303,19 @@ def f32_variant(A, x, dev, timer, torch, ac, steps):
 
 def tuned_record(ac, dev, dtype, xd, yd, timer, steps):
     """What argcsr_autotune picks for the matrix (4 finalists timed cold by
-    the tuner), converted and timed here the same way as the fixed choice."""
+    the tuner, each ARG-CSR finalist also with x staged), converted (and
+    staged when chosen) and timed here the same way as the fixed choice."""
     r = ac.autotune(dev, dtype, n_finalists=4)
     M = ac.convert(dev, r["block_dim"], r["desired_chunk_size"], dtype, fmt=r["format"])
+    if r["staged"]:
+        M = ac.stage(M, 0, True)
     f = lambda: ac.spmv(M, xd, yd)
     timer.run(f, 3)
     t, _ = timer.run(f, steps)
     B = useful_bytes_of(dev, dtype)
     return stats(t) | {"block_dim": r["block_dim"], "desired_chunk_size": r["desired_chunk_size"],
                        "format": "row-grouped" if r["format"] else "ARG-CSR",
+                       "x_staged": bool(r["staged"]),
                        "tuner_median_us": r["measured_us"], "model_us": r["model_us"],
                        "candidates_timed": r["n_timed"],
                        "gbps": B / (t.mean() * 1e-3) / 1e9}
@@ -384,7 +388,8 @@ def leg_stencil27(torch, ac, timer, steps):
 def batch_record(torch, ac, count, dtype, steps, warmup, cold=True, extras=True):
     """`count` matrices (n log-uniform in [1e3, 2e5], half U{5..50} nonzeros
     per row, half clip(Zipf(2.2), 1, min(5000, n))), (T, D, format) chosen
-    per matrix by the autotuner's cost model; a step is ONE replay of the
+    per matrix by argcsr_autotune_member (the batch-throughput model); a step
+    is ONE replay of the
     batch's hipGraph (queue reset + persistent kernel over all matrices'
     groups)."""
     import synth
@@ -394,10 +399,9 @@ def batch_record(torch, ac, count, dtype, steps, warmup, cold=True, extras=True)
     t0 = time.perf_counter()
     for A, x in mats:
         d = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, "cuda")
-        # ranked by the tuner's cost model, not timed: a small matrix timed
-        # alone favours more groups than it needs among 255 others (measured
-        # on this batch: 873 us model-ranked, 914 us with 3 timed finalists)
-        r = ac.autotune(d, dtype, n_finalists=0)
+        # ranked by the batch-throughput model, not timed: a small matrix
+        # timed alone favours more groups than it needs among 255 others
+        r = ac.autotune_member(A.rp, dtype)
         tunes.append((r["block_dim"], r["desired_chunk_size"], r["from_cache"], r["format"]))
         Ms.append(ac.convert(d, r["block_dim"], r["desired_chunk_size"], dtype, fmt=r["format"]))
         devs.append(d)
@@ -416,7 +420,7 @@ def batch_record(torch, ac, count, dtype, steps, warmup, cold=True, extras=True)
     # every member against y = A x in FP64 (numpy), after the last replay
     errs = [error_vs_fp64(A, x, y.cpu().numpy()) for (A, x), y in zip(mats, ys)]
     rec = {"workload": f"batch of {count} matrices, n log-uniform [1e3,2e5], half U{{5..50}} "
-                       "nnz/row, half clip(Zipf(2.2),1,min(5000,n)); (T, D) by the tuner's model "
+                       "nnz/row, half clip(Zipf(2.2),1,min(5000,n)); (T, D) by the batch-member model "
                        "per matrix; one hipGraph replay per step",
            "n_mats": count, "n_rows": sum(A.n_rows for A, _ in mats), "nnz": nnz,
            "value_dtype": DTYPE_NAMES[dtype], "useful_bytes": B, "gbps": gbps,

@@ -461,6 +461,8 @@ typedef struct {
   int32_t n_candidates;        /* candidates planned */
   int32_t n_timed;             /* candidates converted and timed */
   int32_t format;              /* chosen argcsr_format */
+  int32_t staged;              /* 1: faster with x staged in LDS (argcsr_stage_plan
+                                  and argcsr_stage with gap 0, stage_lds = 1) */
 } argcsr_tune_result;
 
 /*
@@ -470,13 +472,16 @@ typedef struct {
  * than one format, row-grouped CSR winning on finite-difference matrices
  * (Sec. 5).  Every ARG-CSR pair in {64,128,256} x {1,2,4,8,16,32,64, the
  * longest and the mean row length when at most 64} and row-grouped CSR at
- * {64,128,256} (24 to 30 candidates) is sized with
- * argcsr_plan, ranked by a cost model (padded bytes, group count, long
- * groups), and n_finalists of them are converted and timed on `stream` --
- * candidates whose layout repeats a better-ranked one's are skipped, and the
- * best of each block size comes first --
- * each launch after a 512 MiB read-modify-write that evicts the caches
- * (the median of 7 decides).
+ * {64,128,256} (24 to 30 candidates) is sized with argcsr_plan and ranked
+ * by a cost model fitted to cold timings on matrices of both regimes (the
+ * longest of: padded bytes at the stream rate, the groups' latency chains
+ * over the waves the chip keeps in flight, one group's chain), and
+ * n_finalists of them are converted and timed on `stream` -- candidates
+ * whose layout repeats a better-ranked one's are skipped, and the best of
+ * each block size comes first -- each launch after a 512 MiB
+ * read-modify-write that evicts the caches (the median of 7 decides).  An
+ * ARG-CSR finalist whose groups fit the staging limits is timed again with
+ * x staged in LDS, and `staged` reports whether that was faster.
  * The choice is cached for the process under a signature of the row-length
  * distribution.
  *   arguments as for argcsr_convert; dtype is the value storage type
@@ -487,6 +492,21 @@ typedef struct {
 int argcsr_autotune(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
                     const int32_t* row_ptr, const int32_t* col, const double* val, int32_t dtype,
                     int32_t n_finalists, argcsr_tune_result* out, void* stream);
+
+/*
+ * argcsr_autotune_member -- the (T, D, format) for a matrix that will run as
+ * one member of a batch (argcsr_batch_create), where the persistent kernel
+ * overlaps the members and a member's cost is its share of the batch's
+ * throughput rather than the time of its own launch.  The same candidates as
+ * argcsr_autotune are ranked, without timing, by a model fitted to
+ * whole-batch timings: the bytes of the member's slots and groups at a rate
+ * that depends on the block size, plus a cost per group.  Host only (no
+ * device memory or stream); model_us is the member's estimated share of the
+ * batch time, measured_us is -1.  Cached like argcsr_autotune (separately).
+ * Errors: EINVAL, EOVERFLOW.
+ */
+int argcsr_autotune_member(int32_t n_rows, const int32_t* row_ptr_host, int32_t dtype,
+                           argcsr_tune_result* out);
 
 /* Forgets all cached autotune choices. */
 int argcsr_autotune_clear_cache(void);

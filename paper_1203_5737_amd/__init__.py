@@ -453,5 +453,16 @@ def autotune(A: DeviceCsr, dtype: int = F64, n_finalists: int = 4, stream=None) 
     return {k: getattr(r, k) for k, _ in TuneResult._fields_}
 
 
+def autotune_member(row_ptr_host, dtype: int = F32) -> dict:
+    """(block_dim, desired_chunk_size, format) for a matrix that runs as one
+    member of a Batch (argcsr_autotune_member: the batch-throughput model,
+    host only, nothing timed)."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr_host, dtype=np.int32))
+    r = TuneResult()
+    check(lib().argcsr_autotune_member(int(rp.shape[0] - 1), rp.ctypes.data_as(ctypes.c_void_p),
+                                       int(dtype), ctypes.byref(r)), "argcsr_autotune_member")
+    return {k: getattr(r, k) for k, _ in TuneResult._fields_}
+
+
 def autotune_clear_cache() -> None:
     check(lib().argcsr_autotune_clear_cache(), "argcsr_autotune_clear_cache")

@@ -57,7 +57,8 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("block_dim", ctypes.c_int32), ("desired_chunk_size", ctypes.c_int32),
                 ("model_us", ctypes.c_double), ("measured_us", ctypes.c_double),
                 ("from_cache", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
-                ("n_timed", ctypes.c_int32), ("format", ctypes.c_int32)]
+                ("n_timed", ctypes.c_int32), ("format", ctypes.c_int32),
+                ("staged", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -128,6 +129,7 @@ SIGNATURES = {
     "argcsr_batch_destroy": (ctypes.c_int, [vp]),
     "argcsr_autotune": (ctypes.c_int, [i32, i32, vp, vp, vp, vp, i32, i32,
                                        ctypes.POINTER(TuneResult), vp]),
+    "argcsr_autotune_member": (ctypes.c_int, [i32, vp, i32, ctypes.POINTER(TuneResult)]),
     "argcsr_autotune_clear_cache": (ctypes.c_int, []),
     "argcsr_probe_read": (ctypes.c_int, [vp, i64, vp, vp]),
     "argcsr_probe_gather": (ctypes.c_int, [vp, i64, vp, i32, i32, vp, vp]),

@@ -127,7 +127,7 @@ def test_autotune_times_finalists(ac):
 
 def test_full_batch_of_256_as_benchmarked(ac):
     """The 256-matrix batch the benchmark times (FP32, (T, D, format) chosen
-    per matrix by the autotuner with 3 timed finalists, one hipGraph replay):
+    per matrix by the batch-member model, one hipGraph replay):
     every member within the FP32 bound of the oracle and bitwise equal to its
     own single launch."""
     print("\n[gpu] full batch of 256", flush=True)
@@ -135,7 +135,7 @@ def test_full_batch_of_256_as_benchmarked(ac):
     conv = []
     for A, x in mats:
         d = ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV)
-        r = ac.autotune(d, ac.F32, n_finalists=3)
+        r = ac.autotune_member(A.rp, ac.F32)
         M = ac.convert(d, r["block_dim"], r["desired_chunk_size"], ac.F32, fmt=r["format"])
         conv.append((M, torch.from_numpy(x).to(DEV, torch.float32)))
         del d

@@ -220,14 +220,54 @@ def test_autotune_model_ranking_on_host(L, ora):
                        else ora.rg_convert(A.rp, A.col, A.val, T))
                 G, S = ref.n_groups, ref.n_slots
                 H = int((ref.groups[:, 3] > heavy_chunk_for(T, S, G)).sum())
-                model = (S * (sv + 4) + 16 * G + A.n_rows * (4 + sx)) / 5e6 + 4e-4 * G + 2e-3 * H
+                # the longest of: bytes at 5 TB/s, the groups' latency chains
+                # (3 us per group, 0.15 us per 64-slot step, x4.5 for FP64) over
+                # 8192 waves in flight, one group's chain; plus 2 ns per heavy group
+                step = 0.15 * (4.5 if dt == ac.F64 else 1.0)
+                nbytes = S * (sv + 4) + 16 * G + A.n_rows * (4 + sx) + A.n_cols * sx
+                model = max(nbytes / 5e6, (3.0 * G + step * S / 64) / 8192.0,
+                            3.0 + step * S / 64 / G) + 2e-3 * H
                 if best is None or model < best[0]:
                     best = (model, T, D, 0 if D else 1)
         assert (r["block_dim"], r["desired_chunk_size"], r["format"]) == best[1:]
         assert abs(r["model_us"] - best[0]) < 1e-9 * max(1.0, best[0])
         assert r["n_candidates"] == 3 * (len(desired) + 1)
-        assert r["n_timed"] == 0 and r["from_cache"] == 0
+        assert r["n_timed"] == 0 and r["from_cache"] == 0 and r["staged"] == 0
         assert ac.autotune(d, dt, n_finalists=0)["from_cache"] == 1
+
+
+def test_autotune_member_ranking_on_host(L, ora):
+    """The batch-member choice is the minimum of the batch-throughput model
+    over the same candidates; recompute the model from the oracle's sizes."""
+    import paper_1203_5737_amd as ac
+    ac.autotune_clear_cache()
+    bw = {64: 5.25e6, 128: 4.9e6, 256: 4.0e6}             # bytes per us by block size
+    for k, dt in [(1, ac.F32), (2, ac.F64), (5, ac.BF16)]:
+        A = synth.batch_member(k, 1e3, 2e4)[0]
+        r = ac.autotune_member(A.rp, dt)
+        sv = {ac.F64: 8, ac.F32: 4, ac.BF16: 2}[dt]
+        lengths = np.diff(A.rp.astype(np.int64))
+        desired = [1, 2, 4, 8, 16, 32, 64]
+        for extra in (int(lengths.max()), int((A.nnz + A.n_rows // 2) // A.n_rows)):
+            if 1 <= extra <= 64 and extra not in desired:
+                desired.append(extra)
+        best = None
+        for T in (64, 128, 256):
+            for D in desired + [0]:
+                ref = (ora.convert(A.rp, A.col, A.val, T, D) if D
+                       else ora.rg_convert(A.rp, A.col, A.val, T))
+                G, S = ref.n_groups, ref.n_slots
+                cost = (S * (sv + 4) + 16 * G) / bw[T] + 3.5e-4 * G
+                if best is None or cost < best[0]:
+                    best = (cost, T, D, 0 if D else 1)
+        assert (r["block_dim"], r["desired_chunk_size"], r["format"]) == best[1:]
+        assert abs(r["model_us"] - best[0]) < 1e-9 * max(1.0, best[0])
+        assert r["n_candidates"] == 3 * (len(desired) + 1)
+        assert r["n_timed"] == 0 and r["measured_us"] < 0 and r["staged"] == 0
+        assert ac.autotune_member(A.rp, dt)["from_cache"] == 1
+    with pytest.raises(ac.ArgCsrError) as e:
+        ac.autotune_member(np.array([0, 2, 1], np.int32), ac.F32)
+    assert e.value.code == ac._lib.EINVAL
 
 
 def test_probes_reject_bad_arguments(L):
