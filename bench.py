@@ -45,12 +45,19 @@ FLUSH_BYTES = 1 << 30
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
 DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
 VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2}
-KERNEL_SOURCES = ["paper_1203_5737_amd/csrc/spmv_kernels.hpp", "paper_1203_5737_amd/csrc/spmv.hip",
-                  "paper_1203_5737_amd/csrc/values.hpp", "paper_1203_5737_amd/csrc/common.hpp",
-                  "paper_1203_5737_amd/csrc/schedule.hpp",
-                  "paper_1203_5737_amd/csrc/spmv_staged.hpp", "paper_1203_5737_amd/csrc/stage.hpp",
-                  "paper_1203_5737_amd/csrc/batch.hip", "paper_1203_5737_amd/csrc/workqueue.hpp",
-                  "paper_1203_5737_amd/csrc/tune.cpp"]
+# Sources each measured kernel's HBM traffic depends on: the SpMV kernels;
+# with staging of x, the staged kernel and the tile tables; in a batch, the
+# batch kernel, its work queue and the member choices of the autotuner.
+_CSRC = "paper_1203_5737_amd/csrc/"
+SOURCE_SETS = {
+    "spmv": [_CSRC + f for f in ("spmv_kernels.hpp", "spmv.hip", "values.hpp", "common.hpp",
+                                 "schedule.hpp")],
+}
+SOURCE_SETS["staged"] = SOURCE_SETS["spmv"] + [_CSRC + f for f in ("spmv_staged.hpp", "stage.hpp",
+                                                                   "stage.hip")]
+SOURCE_SETS["batch"] = SOURCE_SETS["spmv"] + [_CSRC + f for f in ("batch.hip", "workqueue.hpp",
+                                                                  "tune.cpp")]
+KERNEL_SOURCES = list(dict.fromkeys(f for v in SOURCE_SETS.values() for f in v))
 # (block_dim, desired_chunk_size) per workload unless given on the command line
 DEFAULT_PARAMS = {"powerlaw": (64, 1), "stencil27": (128, 27), "laplace64": (64, 1),
                   "mixed": (64, 1)}
@@ -67,12 +74,19 @@ def log(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kind: str = "") -> str:
+    """Hash of the sources of one kernel kind (SOURCE_SETS), or of all."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in SOURCE_SETS[kind] if kind else KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def traffic_kind(workload: str) -> str:
+    """The source set a traffic record of `workload` depends on."""
+    return ("staged" if workload.endswith("-staged") else
+            "batch" if workload == "batch" else "spmv")
 
 
 def load_workload(name: str):
@@ -235,7 +249,8 @@ def error_vs_fp64(A, x, y):
 
 def traffic_for(workload: str, dtype_name: str, T: int, D: int):
     """HBM bytes per launch measured by rocprofv3 FETCH_SIZE/WRITE_SIZE for
-    the current kernel source (None when absent or the kernel has changed)."""
+    the current sources of the kernel (None when absent or those sources have
+    changed since the counters were taken)."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -243,7 +258,8 @@ def traffic_for(workload: str, dtype_name: str, T: int, D: int):
     for line in open(path):
         f = line.split()
         # key  kernel_hash  fetch_bytes  write_bytes  (scaled, per launch)
-        if len(f) >= 4 and not line.startswith("#") and f[0] == want and f[1] == kernel_source_hash():
+        if (len(f) >= 4 and not line.startswith("#") and f[0] == want
+                and f[1] == kernel_source_hash(traffic_kind(workload))):
             return int(f[2]) + int(f[3])
     return None
 

@@ -56,11 +56,15 @@ def test_error_vs_fp64():
 def test_traffic_is_used_only_for_the_current_kernel():
     h = bench.kernel_source_hash()
     assert len(h) == 16 and int(h, 16) >= 0
+    kinds = {k: bench.kernel_source_hash(k) for k in bench.SOURCE_SETS}
+    assert len(set(kinds.values()) | {h}) == len(kinds) + 1
+    assert set(bench.KERNEL_SOURCES) == {f for v in bench.SOURCE_SETS.values() for f in v}
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
     for key, kh, fetch, write in rows:
         wl, dt, T, D = key.split("/")
         num = lambda v: int(v) if v.isdigit() else v          # "auto": the tuner's choice
         got = bench.traffic_for(wl, dt, num(T[1:]), num(D[1:]))
-        assert got == (int(fetch) + int(write) if kh == h else None)
+        current = kinds[bench.traffic_kind(wl)]
+        assert got == (int(fetch) + int(write) if kh == current else None)
     assert bench.traffic_for("powerlaw", "f64", 999, 1) is None
