@@ -136,7 +136,13 @@ def test_stage_random_banded(ac, seed):
     gap = int(rng.choice([0, 1, 5, 64, 1000]))
     ref = oracle.convert(A.rp, A.col, A.val, T, D, dtype)
     if oracle.stage(ref, gap, MAX_TILES) == oracle.STAGE_TOO_MANY_TILES:
-        pytest.skip("this draw needs more than 64 tiles in some group")
+        # a draw with a group of more than 64 tiles: the GPU must refuse it too
+        announce(f"stage beyond the tile limit n={A.n_rows} T={T} D={D} gap={gap}")
+        M = ac.convert(ac.to_device_csr(A.rp, A.col, A.val, A.n_cols, DEV), T, D, dtype)
+        with pytest.raises(ac.ArgCsrError) as e:
+            ac.stage(M, gap=gap)
+        assert e.value.code == ac._lib.EUNSUPPORTED
+        return
     run_case(ac, A, T, D, dtype, gap, vec(A.n_cols, seed, dtype))
 
 
