@@ -610,11 +610,15 @@ typedef struct {
 int argcsr_server_create(const argcsr_server_config* cfg, argcsr_server** out);
 
 /* Queues a request (thread-safe, non-blocking) and returns its ticket.
- * Requests are taken in submission order, except that while an ADMIT's
- * conversion runs (on a stream of its own) the requests behind it that do
- * not depend on it may start: ADMITs and SPMV/CG requests of matrices that
- * are resident; a request for the matrix being converted, another ADMIT that
- * must convert, or an EVICT waits for it.  A matrix that a running request
+ * Requests are taken in submission order per matrix.  An ADMIT whose host
+ * preparation is still running, an ADMIT that must convert while another
+ * conversion runs (conversions run one at a time, on a stream of their own,
+ * in submission order), and every later request of the same matrix wait,
+ * while the requests behind them that name other, resident matrices start:
+ * an ADMIT of a resident matrix then completes together with the SPMV/CG
+ * request of that matrix submitted right behind it (or waits with it), so
+ * the matrix stays resident until that request starts.  An EVICT waits for
+ * every earlier request.  A matrix that a running request
  * uses is never evicted; queued requests do not pin their matrices (an ADMIT
  * evicts matrices no queued request names first).  An ADMIT that finds the
  * budget full even after evicting every matrix no running request uses

@@ -3,17 +3,20 @@
 //
 // One scheduler thread owns all device work (one stream).  Clients submit
 // requests into a queue and poll or wait on tickets.  Each scheduler step:
-//   1. takes queued requests in order: ADMIT converts a matrix and keeps it
-//      resident, evicting matrices no running request uses (least recently
-//      used first, those no queued request names before the others) if the
-//      budget is short, and waiting, with every request behind it, while the
-//      matrix cannot fit until running requests end; SPMV/CG requests enter
-//      free slots as slots and memory allow.  The host side of an ADMIT
-//      (steps 1-2 of the conversion with the group table kept, and a copy of
-//      the CSR arrays into pinned staging) is done ahead by a preparation
-//      thread, so the scheduler itself only uploads the arrays and runs the
-//      conversion kernels; until the preparation is done the ADMIT waits at
-//      the head of the queue while running requests keep stepping;
+//   1. takes queued requests in order per matrix: ADMIT converts a matrix
+//      and keeps it resident, evicting matrices no running request uses
+//      (least recently used first, those no queued request names before the
+//      others) if the budget is short, and waiting, with every request behind
+//      it, while the matrix cannot fit until running requests end; SPMV/CG
+//      requests enter free slots as slots and memory allow.  The host side
+//      of an ADMIT (steps 1-2 of the conversion with the group table kept,
+//      and a copy of the CSR arrays into pinned staging) is done ahead by a
+//      preparation thread, and the upload and conversion kernels run on a
+//      converter thread with a stream of its own; an ADMIT still preparing,
+//      or waiting for the converter, is passed over together with every later
+//      request of its matrix, and requests of resident matrices behind it go
+//      on (an ADMIT of a resident matrix then completes only together with
+//      the request of that matrix right behind it);
 //   2. advances every active request by one step in a few launches for all
 //      of them together: a pull of the step's descriptors from mapped pinned
 //      memory, one multi-matrix ARG-CSR SpMV per precision (FP32 values for
@@ -394,6 +397,44 @@ int check_admit(const argcsr_request& q) {
 // The preparation thread: for each ADMIT in submission order whose matrix
 // is not resident, steps 1-2 on the host (group table kept) and a copy of
 // the CSR arrays into pinned staging.
+// Host copies of up to kCopyThreads threads, each over a contiguous share
+// of the bytes of `segs` (pieces of at least kCopyPiece bytes); the caller
+// joins the returned threads.  Nothing to copy: no threads.
+struct CopySeg {
+  char* dst;
+  const char* src;
+  size_t n;
+};
+constexpr int kCopyThreads = 4;
+constexpr size_t kCopyPiece = size_t(8) << 20;
+
+std::vector<std::thread> start_copy(const CopySeg* segs, int n_segs) {
+  size_t total = 0;
+  for (int k = 0; k < n_segs; ++k) total += segs[k].n;
+  const int n_threads =
+      int(std::min<size_t>(kCopyThreads, (total + kCopyPiece - 1) / kCopyPiece));
+  std::vector<std::thread> threads;
+  std::vector<CopySeg> all(segs, segs + n_segs);
+  for (int t = 0; t < n_threads; ++t) {
+    const size_t lo = total * size_t(t) / size_t(n_threads);
+    const size_t hi = total * size_t(t + 1) / size_t(n_threads);
+    auto copy = [all, lo, hi] {
+      size_t base = 0;                       // offset of the segment in the whole
+      for (const CopySeg& c : all) {
+        const size_t a = std::max(lo, base), b = std::min(hi, base + c.n);
+        if (a < b) std::memcpy(c.dst + (a - base), c.src + (a - base), b - a);
+        base += c.n;
+      }
+    };
+    try {
+      threads.emplace_back(copy);
+    } catch (...) {                          // no thread to be had: copy this share here
+      copy();
+    }
+  }
+  return threads;
+}
+
 void preparer(argcsr_server* s) {
   for (;;) {
     std::shared_ptr<AdmitPrep> p;
@@ -419,25 +460,30 @@ void preparer(argcsr_server* s) {
         if (p->rc == ARGCSR_OK && nnz > 0 && (!q.col || !q.val))
           p->rc = fail(ARGCSR_EINVAL, "NULL CSR arrays");
         if (p->rc == ARGCSR_OK) {
-          admit_params(s->cfg, q, nnz, &p->T, &p->D);
-          p->rc = plan_host_groups(q.n_rows, q.row_ptr, p->T, p->D, ARGCSR_FORMAT_ARG,
-                                   &p->groups, &p->n_slots, &p->n_heavy);
-        }
-        if (p->rc == ARGCSR_OK) {
-          // row_ptr | col | val, each 256-byte aligned
+          // the CSR arrays go to pinned staging (row_ptr | col | val, each
+          // 256-byte aligned) on copy threads while this thread groups the
+          // rows (steps 1-2): the two do not depend on each other
           auto up = [](size_t b) { return (b + 255) / 256 * 256; };
           const size_t rp_b = sizeof(int32_t) * size_t(q.n_rows + 1);
           const size_t col_b = sizeof(int32_t) * size_t(nnz), val_b = sizeof(double) * size_t(nnz);
           p->off_col = up(rp_b);
           p->off_val = p->off_col + up(col_b);
           p->stage = s->pinned.alloc(p->off_val + val_b);
+          std::vector<std::thread> copiers;
           if (p->stage) {
             char* st = static_cast<char*>(p->stage);
-            std::memcpy(st, q.row_ptr, rp_b);
-            if (nnz > 0) {
-              std::memcpy(st + p->off_col, q.col, col_b);
-              std::memcpy(st + p->off_val, q.val, val_b);
-            }
+            const CopySeg segs[3] = {{st, reinterpret_cast<const char*>(q.row_ptr), rp_b},
+                                     {st + p->off_col, reinterpret_cast<const char*>(q.col), nnz > 0 ? col_b : 0},
+                                     {st + p->off_val, reinterpret_cast<const char*>(q.val), nnz > 0 ? val_b : 0}};
+            copiers = start_copy(segs, 3);
+          }
+          admit_params(s->cfg, q, nnz, &p->T, &p->D);
+          p->rc = plan_host_groups(q.n_rows, q.row_ptr, p->T, p->D, ARGCSR_FORMAT_ARG,
+                                   &p->groups, &p->n_slots, &p->n_heavy);
+          for (std::thread& t : copiers) t.join();
+          if (p->rc != ARGCSR_OK && p->stage) {
+            s->pinned.release(p->stage);
+            p->stage = nullptr;
           }
         }
       }
@@ -1140,22 +1186,100 @@ void scheduler(argcsr_server* s) {
     }
     // the conversion in flight, if it has finished
     if (s->admitting && s->conv_done.load(std::memory_order_acquire)) finish_admission(s);
-    // admissions and new requests, in submission order; while a conversion
-    // runs (on the converter's stream) the requests behind its ADMIT that do
-    // not depend on it may start: no-op ADMITs of resident matrices and
-    // SPMV/CG requests of resident matrices.  A request of the matrix being
-    // converted, another conversion, or an EVICT waits for it.
+    // admissions and new requests, in submission order per matrix.  An
+    // ADMIT whose preparation is still running, or that must convert while
+    // a conversion runs (on the converter's stream) or behind such an ADMIT,
+    // is passed over, and so is every later request of its matrix (or of the
+    // matrix being converted): they keep their order and are taken up on a
+    // later scan.  Requests of other, resident matrices go on meanwhile.  An
+    // ADMIT waiting for memory, a full set of request slots, a request that
+    // must wait for memory, and an EVICT behind anything passed over stop
+    // the scan: everything behind waits (in order).
     bool admit_waiting = false;
+    bool passed = false;                 // a request was passed over in this scan
+    std::vector<int64_t> held;           // matrices with a passed-over request
+    auto is_held = [&](int64_t id) { return std::find(held.begin(), held.end(), id) != held.end(); };
+    // Starts the SPMV/CG request at pending[k] (a slot is free): false if it
+    // must wait for memory (it stays queued), true once it has left the
+    // queue, started or failed.
+    auto start = [&](size_t k) -> bool {
+      Request* q = s->pending[k];
+      const int rc = activate(s, q);
+      if (rc == ARGCSR_EBUSY) {
+        if (memory_will_free(s) || s->admitting != nullptr) return false;   // memory frees up
+        q->res.status = fail(ARGCSR_EBUDGET, "request does not fit the budget");
+      } else if (rc != ARGCSR_OK) {
+        q->res.status = rc;
+      }
+      s->pending.erase(s->pending.begin() + std::ptrdiff_t(k));
+      if (rc == ARGCSR_OK) {
+        if (q->stage) s->staging.push_back(q);   // starts once its input is staged
+        else s->active.push_back(q);
+      } else {
+        release_request(s, q);
+        publish(s, q);
+        delete q;
+      }
+      return true;
+    };
     for (size_t i = 0; i < s->pending.size();) {
       Request* r = s->pending[i];
       const int64_t converting = s->admitting ? s->admitting->r->q.matrix_id : -1;
       const bool busy = s->admitting != nullptr;
+      const int64_t id = r->q.matrix_id;
+      auto pass_over = [&]() {
+        if (!is_held(id)) held.push_back(id);
+        passed = true;
+        ++i;
+      };
+      if (r->q.kind != ARGCSR_REQ_EVICT && (id == converting || is_held(id))) {
+        pass_over();                                   // behind an earlier request of its matrix
+        continue;
+      }
       if (r->q.kind == ARGCSR_REQ_ADMIT) {
-        const bool was_resident = s->resident.count(r->q.matrix_id) != 0;
-        if (busy && (!was_resident || r->q.matrix_id == converting)) break;
+        const bool was_resident = s->resident.count(id) != 0;
+        if (!was_resident && (busy || passed)) {       // conversions start in submission order
+          pass_over();
+          continue;
+        }
+        if (was_resident && passed) {
+          // Behind a passed-over ADMIT, which may evict when it runs: an
+          // ADMIT of a resident matrix completes only together with the
+          // request of that matrix right behind it, so that the matrix stays
+          // resident until the request starts (the submission-order promise).
+          const bool pair = i + 1 < s->pending.size() &&
+                            s->pending[i + 1]->q.kind != ARGCSR_REQ_ADMIT &&
+                            s->pending[i + 1]->q.kind != ARGCSR_REQ_EVICT &&
+                            s->pending[i + 1]->q.matrix_id == id;
+          if (!pair) {
+            pass_over();
+            continue;
+          }
+          if (s->free_slots.empty()) break;
+          if (r->res.t_start_ns == 0) r->res.t_start_ns = now_ns();
+          if (admit(s, r) == kAdmitPending) {          // its preparation still reads the arrays
+            admit_waiting = true;
+            pass_over();
+            continue;
+          }
+          // resident: admit() only marked the use (it does so again when retried)
+          if (!start(i + 1)) break;                    // the request waits for memory, and so does the ADMIT
+          s->pending.erase(s->pending.begin() + std::ptrdiff_t(i));
+          drop_prep(s, r);
+          r->res.status = ARGCSR_OK;
+          r->res.iterations = 0;
+          publish(s, r);
+          delete r;
+          continue;
+        }
         if (r->res.t_start_ns == 0) r->res.t_start_ns = now_ns();
         const int rc = admit(s, r);
-        if (rc == kAdmitWait || rc == kAdmitPending) {   // requests behind it wait too (in order)
+        if (rc == kAdmitPending) {                     // preparation still running
+          admit_waiting = true;
+          pass_over();
+          continue;
+        }
+        if (rc == kAdmitWait) {                        // waits for memory: everything behind waits
           admit_waiting = true;
           break;
         }
@@ -1172,7 +1296,7 @@ void scheduler(argcsr_server* s) {
         continue;
       }
       if (r->q.kind == ARGCSR_REQ_EVICT) {
-        if (busy) break;
+        if (busy || passed) break;
         s->pending.erase(s->pending.begin() + std::ptrdiff_t(i));
         auto it = s->resident.find(r->q.matrix_id);
         const bool used = it != s->resident.end() && pinned(s, it->second.get());
@@ -1187,24 +1311,8 @@ void scheduler(argcsr_server* s) {
         delete r;
         continue;
       }
-      if (r->q.matrix_id == converting) break;    // needs the matrix being converted
       if (s->free_slots.empty()) break;           // wait for a slot
-      const int rc = activate(s, r);
-      if (rc == ARGCSR_EBUSY) {
-        if (memory_will_free(s) || busy) break;   // memory frees up as requests finish
-        r->res.status = fail(ARGCSR_EBUDGET, "request does not fit the budget");
-      } else if (rc != ARGCSR_OK) {
-        r->res.status = rc;
-      }
-      s->pending.erase(s->pending.begin() + std::ptrdiff_t(i));
-      if (rc == ARGCSR_OK) {
-        if (r->stage) s->staging.push_back(r);   // starts once its input is staged
-        else s->active.push_back(r);
-      } else {
-        release_request(s, r);
-        publish(s, r);
-        delete r;
-      }
+      if (!start(i)) break;                       // memory frees up as requests finish
     }
     // staged inputs: upload (in stream order before the next step) and start
     for (size_t i = 0; i < s->staging.size();) {

@@ -417,3 +417,37 @@ def test_serve_large_matrices_alone_and_in_mix(srv_mod):
                 assert r["relres"] <= 1e-10 and true_relres(mats[m], o, inp) <= 1e-10, m
     for a, b in zip(*outs):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_serve_requests_pass_an_admission_in_progress(srv_mod):
+    """Requests are taken in order per matrix: while a large ADMIT prepares
+    and converts, ADMIT+SPMV pairs of a resident matrix submitted behind it
+    start and finish, and the large matrix's own SPMV, submitted right after
+    its ADMIT, still sees the ADMIT complete first.  Every result is checked."""
+    print("\n[gpu] serve: requests pass an admission in progress", flush=True)
+    small = pool(1, 2e4, 2.1e4)[0]
+    big = synth.shifted_laplacian("3d", 1_000_000, np.random.default_rng(5))
+    rng = np.random.default_rng(8)
+    with srv_mod.Server(budget_bytes=1 << 30, max_active=16) as srv:
+        admit_all(srv, [small])
+        tb = srv.admit(1, big.rp, big.col, big.val, big.n_cols)
+        xb = rng.uniform(-1, 1, big.n_cols).astype(np.float32)
+        t_big, y_big = srv.spmv(1, xb, big.n_rows)
+        pairs = []
+        for _ in range(8):
+            x = rng.uniform(-1, 1, small.n_cols).astype(np.float32)
+            ta = srv.admit(0, small.rp, small.col, small.val, small.n_cols)
+            pairs.append((ta, x) + srv.spmv(0, x, small.n_rows))
+        rb, r_big = srv.wait(tb, 120.0), srv.wait(t_big, 120.0)
+        assert rb["status"] == 0 and rb["iterations"] == 1      # converted here
+        assert r_big["status"] == 0 and r_big["t_start_ns"] >= rb["t_done_ns"]
+        assert spmv_ok(big, xb, y_big)
+        done_before = 0
+        for ta, x, t, y in pairs:
+            ra, r = srv.wait(ta, 120.0), srv.wait(t, 120.0)
+            assert ra["status"] == 0 and ra["iterations"] == 0 and r["status"] == 0
+            assert spmv_ok(small, x, y)
+            done_before += r["t_done_ns"] < rb["t_done_ns"]
+        # the big matrix takes milliseconds to plan, stage and convert; the
+        # small SpMVs behind it need a few steps each
+        assert done_before == len(pairs), (done_before, rb)
