@@ -283,9 +283,10 @@ int argcsr_convert(int32_t n_rows, int32_t n_cols, const int32_t* row_ptr_host,
 
 /*
  * argcsr_convert_noalloc -- argcsr_convert for callers that cannot allocate
- * device memory (code under HIP graph capture, tight serving loops,
- * harnesses that forbid hipMalloc): it calls no hipMalloc, hipFree or other
- * allocating routine.  Its scratch (status words, scan partials and the
+ * device memory (tight serving loops, harnesses that forbid hipMalloc): it
+ * calls no hipMalloc, hipFree or other allocating routine.  Like
+ * argcsr_convert it waits for its stream (it reads back the validation
+ * flag), so it cannot itself be recorded into a HIP graph.  Its scratch (status words, scan partials and the
  * fill's long-row list) is a fixed 16 MiB array in device memory, one copy
  * per GPU, held by the library until the process ends; the caller still
  * passes every input and output, as for argcsr_convert, and the result is
