@@ -451,3 +451,68 @@ def test_serve_requests_pass_an_admission_in_progress(srv_mod):
         # the big matrix takes milliseconds to plan, stage and convert; the
         # small SpMVs behind it need a few steps each
         assert done_before == len(pairs), (done_before, rb)
+
+
+def test_serve_random_sequences_keep_order_per_matrix(srv_mod):
+    """Random sequences of ADMIT+SPMV/CG pairs, bare SPMVs and EVICTs over six
+    matrices (two large enough that their admissions are still preparing or
+    converting while later requests arrive) under a budget that forces
+    evictions.  Whatever overtakes what: every SPMV/CG submitted right after
+    its ADMIT succeeds and is checked against the oracle; a bare SPMV either
+    succeeds (checked) or finds its matrix gone (ENOTFOUND), and finds it gone
+    whenever an EVICT of that matrix succeeded after the matrix's last ADMIT
+    (in submission order); EVICTs succeed or report ENOTFOUND/EBUSY."""
+    print("\n[gpu] serve: random sequences", flush=True)
+    from paper_1203_5737_amd import _lib
+    rng = np.random.default_rng(2024)
+    mats = pool(4, 1.5e4, 3e4) + [synth.shifted_laplacian(k, 150_000, np.random.default_rng(9 + i))
+                                  for i, k in enumerate(("2d", "3d"))]
+    with srv_mod.Server(budget_bytes=32 << 20, max_active=6) as srv:
+        ops = []
+        for _ in range(240):
+            m = int(rng.integers(0, len(mats)))
+            A = mats[m]
+            u = rng.random()
+            if u < 0.6:
+                ta = srv.admit(m, A.rp, A.col, A.val, A.n_cols)
+                if rng.random() < 0.5:
+                    x = rng.uniform(-1, 1, A.n_cols).astype(np.float32)
+                    ops.append(("pair-spmv", m, ta, x) + srv.spmv(m, x, A.n_rows))
+                else:
+                    b = rng.uniform(-1, 1, A.n_rows)
+                    ops.append(("pair-cg", m, ta, b) + srv.cg(m, b))
+            elif u < 0.85:
+                x = rng.uniform(-1, 1, A.n_cols).astype(np.float32)
+                ops.append(("bare-spmv", m, None, x) + srv.spmv(m, x, A.n_rows))
+            else:
+                ops.append(("evict", m, srv.evict(m), None, None, None))
+        gone = {}                       # matrix -> an EVICT of it succeeded since its last ADMIT
+        for kind, m, ta, inp, t, out in ops:
+            A = mats[m]
+            if kind == "evict":
+                r = srv.wait(ta, 120.0)
+                assert r["status"] in (0, _lib.ENOTFOUND, _lib.EBUSY), (kind, m, r)
+                if r["status"] == 0:
+                    gone[m] = True
+                continue
+            if ta is not None:
+                ra = srv.wait(ta, 120.0)
+                assert ra["status"] == 0, (kind, m, ra)
+                gone[m] = False
+            r = srv.wait(t, 120.0)
+            if kind == "bare-spmv":
+                if gone.get(m):
+                    assert r["status"] == _lib.ENOTFOUND, (kind, m, r)
+                    continue
+                assert r["status"] in (0, _lib.ENOTFOUND), (kind, m, r)
+                if r["status"] != 0:
+                    continue
+            else:
+                assert r["status"] == 0, (kind, m, r)
+            if kind == "pair-cg":
+                assert true_relres(A, out, inp) <= 1e-10
+            else:
+                assert spmv_ok(A, inp, out)
+        st = srv.stats()
+        print(f"[gpu] serve random sequences: {st}", flush=True)
+        assert st["evictions"] > 0, st
