@@ -52,6 +52,7 @@
 #include <vector>
 
 #include "arena.hpp"
+#include "hostcopy.hpp"
 #include "common.hpp"
 #include "mspmv.hpp"
 #include "plan.hpp"
@@ -397,44 +398,6 @@ int check_admit(const argcsr_request& q) {
 // The preparation thread: for each ADMIT in submission order whose matrix
 // is not resident, steps 1-2 on the host (group table kept) and a copy of
 // the CSR arrays into pinned staging.
-// Host copies of up to kCopyThreads threads, each over a contiguous share
-// of the bytes of `segs` (pieces of at least kCopyPiece bytes); the caller
-// joins the returned threads.  Nothing to copy: no threads.
-struct CopySeg {
-  char* dst;
-  const char* src;
-  size_t n;
-};
-constexpr int kCopyThreads = 4;
-constexpr size_t kCopyPiece = size_t(8) << 20;
-
-std::vector<std::thread> start_copy(const CopySeg* segs, int n_segs) {
-  size_t total = 0;
-  for (int k = 0; k < n_segs; ++k) total += segs[k].n;
-  const int n_threads =
-      int(std::min<size_t>(kCopyThreads, (total + kCopyPiece - 1) / kCopyPiece));
-  std::vector<std::thread> threads;
-  std::vector<CopySeg> all(segs, segs + n_segs);
-  for (int t = 0; t < n_threads; ++t) {
-    const size_t lo = total * size_t(t) / size_t(n_threads);
-    const size_t hi = total * size_t(t + 1) / size_t(n_threads);
-    auto copy = [all, lo, hi] {
-      size_t base = 0;                       // offset of the segment in the whole
-      for (const CopySeg& c : all) {
-        const size_t a = std::max(lo, base), b = std::min(hi, base + c.n);
-        if (a < b) std::memcpy(c.dst + (a - base), c.src + (a - base), b - a);
-        base += c.n;
-      }
-    };
-    try {
-      threads.emplace_back(copy);
-    } catch (...) {                          // no thread to be had: copy this share here
-      copy();
-    }
-  }
-  return threads;
-}
-
 void preparer(argcsr_server* s) {
   for (;;) {
     std::shared_ptr<AdmitPrep> p;
