@@ -72,7 +72,7 @@ def _bind(L):
         "ora_cg": (i32, [i32, vp, vp, vp, vp, vp, f64, i32, vp]),
         "ora_round_array": (None, [i64, vp, i32, vp]),
         "ora_stage": (i64, [i32, vp, vp, i32, i32, i32, vp, vp, vp, i64, vp]),
-        "ora_unstage": (None, [i32, vp, i32, vp, vp, vp, vp, vp]),
+        "ora_unstage": (None, [i32, vp, i32, vp, vp, vp, vp]),
         "ora_decode_array": (None, [i64, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
@@ -285,9 +285,8 @@ def unstage(a: ArgCsr, st: Staging) -> np.ndarray:
     """The column index every slot names, from its local index (ora_unstage)."""
     out = np.empty(max(a.n_slots, 1), dtype=np.int32)
     ts = st.tile_start if st.tile_start.size else np.zeros(1, np.int32)
-    tl = st.tile_len if st.tile_len.size else np.zeros(1, np.int32)
     lib().ora_unstage(a.n_groups, _p(_c(a.groups, np.int32)), a.block_dim,
-                      _p(_c(st.tile_ptr, np.int32)), _p(_c(ts, np.int32)), _p(_c(tl, np.int32)),
+                      _p(_c(st.tile_ptr, np.int32)), _p(_c(ts, np.int32)),
                       _p(_c(st.local if st.local.size else np.zeros(1, np.uint16), np.uint16)),
                       _p(out))
     return out[:a.n_slots]

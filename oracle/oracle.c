@@ -463,11 +463,9 @@ void ora_argcsr_spmv(int32_t n_groups, const int32_t* groups, const int32_t* tm,
 /* every column s..e.  Each window is cut into tiles of 64 consecutive        */
 /* columns from its start (the last tile may be shorter).  The tiles of g,    */
 /* in column order, are tile_start/tile_len[tile_ptr[g] .. tile_ptr[g+1]).    */
-/* A slot holding column c gets the local index of c in the concatenation of  */
-/* its group's tiles: the lengths of the tiles before the one holding c, plus */
-/* c - tile_start of that tile (tiles packed one after the other, as a kernel */
-/* stages them); an artificial zero gets 0xFFFF (local indices stay below     */
-/* 64*1023 < 0xFFFF).  Returns the number of tiles, or ORA_EINVAL when a group needs */
+/* A slot holding column c gets the local index 64*q + (c - tile_start) for  */
+/* the q-th tile of its group that contains c; an artificial zero gets        */
+/* 0xFFFF.  Returns the number of tiles, or ORA_EINVAL when a group needs     */
 /* more than max_tiles (<= 1023) tiles, or ORA_EOVERFLOW when tile_cap is     */
 /* too small.  With tile_start == NULL only tile_ptr is filled.               */
 /* ------------------------------------------------------------------------ */
@@ -529,17 +527,13 @@ int64_t ora_stage(int32_t n_groups, const int32_t* groups, const int32_t* column
                 tile_start[total + q] = ts[q];
                 tile_len[total + q] = tl[q];
             }
-            /* local index of every slot: the tile holding its column, after */
-            /* the lengths of the tiles before it                             */
+            /* local index of every slot: the tile holding its column */
             for (int64_t s = 0; s < slots; s++) {
                 const int32_t c = columns[offset + s];
                 uint16_t v = 0xFFFF;
                 if (c != -1) {
-                    int32_t before = 0;
-                    for (int32_t q = 0; q < nt; q++) {
-                        if (c >= ts[q] && c < ts[q] + tl[q]) { v = (uint16_t)(before + (c - ts[q])); break; }
-                        before += tl[q];
-                    }
+                    for (int32_t q = 0; q < nt; q++)
+                        if (c >= ts[q] && c < ts[q] + tl[q]) { v = (uint16_t)(64 * q + (c - ts[q])); break; }
                 }
                 local[offset + s] = v;
             }
@@ -551,28 +545,19 @@ int64_t ora_stage(int32_t n_groups, const int32_t* groups, const int32_t* column
     return rc ? rc : total;
 }
 
-/* The inverse of the local indices: the column index each slot names --   */
-/* walking the group's tiles, the one whose span in the concatenation holds  */
-/* the local index, then its start plus the offset in it; -1 for 0xFFFF (and */
-/* for an index past the group's tiles).                                     */
+/* The inverse of the local indices: the column index each slot names,      */
+/* tile_start[tile_ptr[g] + local/64] + local%64, -1 for 0xFFFF.             */
 void ora_unstage(int32_t n_groups, const int32_t* groups, int32_t block_dim,
                  const int32_t* tile_ptr, const int32_t* tile_start,
-                 const int32_t* tile_len, const uint16_t* local, int32_t* columns_out)
+                 const uint16_t* local, int32_t* columns_out)
 {
     for (int32_t g = 0; g < n_groups; g++) {
         const int64_t offset = groups[4 * g + 2];
         const int64_t slots = (int64_t)groups[4 * g + 3] * block_dim;
         for (int64_t s = 0; s < slots; s++) {
             const uint16_t v = local[offset + s];
-            int32_t c = -1;
-            if (v != 0xFFFF) {
-                int32_t before = 0;
-                for (int32_t q = tile_ptr[g]; q < tile_ptr[g + 1]; q++) {
-                    if (v < before + tile_len[q]) { c = tile_start[q] + (v - before); break; }
-                    before += tile_len[q];
-                }
-            }
-            columns_out[offset + s] = c;
+            columns_out[offset + s] = v == 0xFFFF ? -1
+                : tile_start[tile_ptr[g] + v / 64] + v % 64;
         }
     }
 }

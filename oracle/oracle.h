@@ -133,9 +133,8 @@ int ora_rgcsr_convert(int32_t n_rows, const int32_t* rp, const int32_t* col,
 /* Staging of x for banded matrices (reading R11): per group, the distinct
  * columns of its slots merged into windows (at most `gap` absent columns
  * between neighbours inside a window), each window cut into tiles of 64
- * columns; local[slot] = the position of its column c in the concatenation
- * of the group's tiles (the lengths of the tiles before the one holding c,
- * plus c - its start), 0xFFFF for an artificial zero.  tile_ptr has
+ * columns; local[slot] = 64*q + (c - tile_start) for the group's q-th tile
+ * holding column c, 0xFFFF for an artificial zero.  tile_ptr has
  * n_groups+1 entries.  Returns the tile count, ORA_EINVAL if a group needs
  * more than max_tiles (<= 1023) tiles, ORA_EOVERFLOW if tile_cap is too
  * small; with tile_start == NULL only tile_ptr is filled (sizing). */
@@ -147,7 +146,7 @@ int64_t ora_stage(int32_t n_groups, const int32_t* groups, const int32_t* column
 /* Column index of every slot from its local index (-1 for 0xFFFF). */
 void ora_unstage(int32_t n_groups, const int32_t* groups, int32_t block_dim,
                  const int32_t* tile_ptr, const int32_t* tile_start,
-                 const int32_t* tile_len, const uint16_t* local, int32_t* columns_out);
+                 const uint16_t* local, int32_t* columns_out);
 
 /* SpMV read from the ARG-CSR storage by the format's definition (Sec. 3,
  * Sec. 4), FP64: each row's elements are found through the threads mapping

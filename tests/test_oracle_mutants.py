@@ -50,8 +50,7 @@ MUTANTS = {
     "rg_mapping_exclusive": ("tm[r] = (int32_t)(l + 1);", "tm[r] = (int32_t)l;"),
     "stage_gap_strict": ("(int64_t)u[i + 1] - last - 1 <= gap", "(int64_t)u[i + 1] - last - 1 < gap"),
     "stage_tiles_of_63": ("for (int64_t t = start; t <= last; t += 64) {", "for (int64_t t = start; t <= last; t += 63) {"),
-    "stage_local_tile_stride": ("v = (uint16_t)(before + (c - ts[q]));", "v = (uint16_t)(64 * q + (c - ts[q]));"),
-    "stage_local_drops_before": ("v = (uint16_t)(before + (c - ts[q]));", "v = (uint16_t)(c - ts[q]);"),
+    "stage_local_window_packed": ("v = (uint16_t)(64 * q + (c - ts[q]));", "v = (uint16_t)(q + (c - ts[q]));"),
     "stage_tile_drops_last_column": ("tl[nt] = (int32_t)(last - t + 1 < 64 ? last - t + 1 : 64);",
                                      "tl[nt] = (int32_t)(last - t < 64 ? last - t : 64);"),
     "rg_slices_offset_by_one": ("groups[4 * g + 0] = (int32_t)first;", "groups[4 * g + 0] = (int32_t)first + (g > 0);"),

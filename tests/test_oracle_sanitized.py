@@ -57,7 +57,7 @@ int main(void) {
         uint16_t *loc = malloc(sizeof(uint16_t) * (S64 + 1));
         int *back = malloc(sizeof(int) * (S64 + 1));
         if (ora_stage(G, groups, cols, T, gap, 1023, tp, ts, tl, nt, loc) != nt) return 10;
-        ora_unstage(G, groups, T, tp, ts, tl, loc, back);
+        ora_unstage(G, groups, T, tp, ts, loc, back);
         if (S64 > 0 && memcmp(back, cols, sizeof(int) * S64) != 0) return 11;
         free(ts); free(tl); free(loc); free(back);
       }
